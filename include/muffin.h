@@ -1,0 +1,183 @@
+/*
+ * libmuffin -- MUFFIN wideband deconvolution with ADA-PT parameter tuning
+ * (Ammanouil, Ferrari, Flamary, Ferrari, Mary, arXiv 1905.08468) on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Section 2.1, eqs. `model`, `probopt`, `RegAll`): given the dirty
+ * images y_l and PSFs of L bands, estimate the sky cube X >= 0 minimising
+ *   sum_l 1/2 ||y_l - H_l x_l||^2 + sum_l mu_l ||W_s x_l||_1
+ *                                 + sum_n gamma_n ||W_lambda x^n||_1,
+ * with mu_l = mu beta_l, gamma_n = gamma alpha_n (eq. `2regpar`), by the
+ * primal-dual iteration of Algorithm 2, optionally with the SURE-driven
+ * update of theta = (mu, gamma) every Delta iterations (Algorithm 5).
+ *
+ * Conventions
+ *  - Cubes are band-major, contiguous: element (l, i, j) at l*n*n + i*n + j.
+ *    The PSF cube is [L][2n][2n] with the PSF centre at (n, n); H_l is the
+ *    linear convolution with it, restricted to the n x n image window.
+ *  - Cube pointers are DEVICE pointers on the GPU current when the handle was
+ *    created, in the working type of the handle's mode (double for
+ *    MUFFIN_F64, float otherwise).  The caller owns them.  Work is enqueued on
+ *    the handle's stream; calls return without waiting unless stated.
+ *  - alpha/beta weight pointers are HOST double arrays (copied at the call).
+ *  - The library owns only its workspace, freed by muffin_destroy.
+ *  - Every function returns an int status: 0 = MUFFIN_OK, < 0 an error code
+ *    (muffin_strerror); nothing aborts or exits.  On error no output has been
+ *    written, except where noted.
+ *  - A handle must not be used from two threads at once; distinct handles are
+ *    independent.
+ */
+#ifndef MUFFIN_H
+#define MUFFIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct muffin_handle muffin_handle;
+
+enum {
+  MUFFIN_OK = 0,
+  MUFFIN_E_INVAL = -1,     /* bad configuration value or null pointer */
+  MUFFIN_E_SHAPE = -2,     /* unsupported size (n, L, levels, bases) */
+  MUFFIN_E_NOMEM = -3,     /* device allocation failed; nothing allocated */
+  MUFFIN_E_NONFINITE = -4, /* NaN or Inf in an input cube */
+  MUFFIN_E_HIP = -5,       /* HIP runtime error */
+  MUFFIN_E_STATE = -6      /* call out of order (e.g. run before set_problem) */
+};
+
+/* Arithmetic forms.  F64: everything in double.  F32: FFT, wavelet,
+ * element-wise and DCT work in float; power iteration, SURE/SUGAR sums and the
+ * theta update stay in double.  F32_BF16DCT: as F32 with the spectral DCT
+ * products on bf16 MFMA with a hi+lo split and float accumulation. */
+enum { MUFFIN_F64 = 0, MUFFIN_F32 = 1, MUFFIN_F32_BF16DCT = 2 };
+
+/* Step-size rules (Section 2.2): tau = rho / (beta_H/2 + sigma K) with
+ * K = max_l mu_l^2 + max_n gamma_n^2 (OPNORM, the operator norm of the dual
+ * operators, ||W_s|| = ||W_lambda|| = 1) or the printed sum
+ * K = sum_l mu_l^2 + sum_n gamma_n^2 (PAPER_SUM). */
+enum { MUFFIN_TAU_OPNORM = 0, MUFFIN_TAU_PAPER_SUM = 1 };
+
+typedef struct {
+  int32_t n;            /* image side, power of two, 8 <= n <= 2048 */
+  int32_t L;            /* bands, 1 <= L <= 256 */
+  int32_t n_bases;      /* P: db1..dbP in W_s, 1..8 (paper: 8) */
+  int32_t levels;       /* J: decomposition levels, 1 <= J, n / 2^J >= 1 */
+  int32_t mode;         /* MUFFIN_F64 / MUFFIN_F32 / MUFFIN_F32_BF16DCT */
+  double mu, gamma;     /* theta at start (eq. `2regpar`) */
+  double sigma;         /* dual step (paper: 10) */
+  double tau;           /* > 0: fixed primal step; <= 0: from tau_rule */
+  int32_t tau_rule;     /* MUFFIN_TAU_OPNORM or MUFFIN_TAU_PAPER_SUM */
+  double rho;           /* safety factor of the tau rule, in (0, 1) */
+  double eps_w;         /* epsilon of the weight rule (Section 2.1) */
+  int32_t sure;         /* 0: plain MUFFIN, fixed theta; 1: ADA-PT (Alg. 5) */
+  int32_t delta_period; /* Delta: theta update period (paper: 10) */
+  double eta_mu;        /* gradient steps of eq. `adaptgrad` */
+  double eta_gamma;
+  double eps_fd;        /* epsilon of SURE-FDMC (eq. `PSURE0`), > 0 if sure */
+  double sigma_w;       /* noise standard deviation, > 0 if sure */
+  int32_t deriv_reset;  /* 1: derivative states restart at each theta update */
+  int32_t pi_iters;     /* max power iterations for beta_H (if tau <= 0) */
+  double pi_tol;        /* relative change stopping the power iteration */
+} muffin_config;
+
+typedef struct {
+  int32_t iters_done;     /* iterations completed since muffin_set_problem */
+  int32_t theta_updates;  /* ADA-PT updates applied */
+  double mu, gamma, tau;  /* current values */
+  double beta_H;          /* Lipschitz constant used by the tau rule */
+  double psure;           /* PSURE-FDMC at the last update (eq. `PSURE0`) */
+  double sugar_mu;        /* SUGAR-FDMC at the last update (eq. `SUGAR`) */
+  double sugar_gamma;
+  double res2;            /* ||Y - H X||^2 at the last update */
+} muffin_report;
+
+/* Fills *cfg with the paper's defaults for an n x n x L cube: P = 8 bases,
+ * J = 3 levels (fewer when n is small), sigma = 10, Delta = 10, OPNORM rule,
+ * rho = 0.99, eps_w = 1e-6, plain MUFFIN (sure = 0), mu = gamma = 1. */
+int muffin_default_config(muffin_config* cfg, int32_t n, int32_t L);
+
+/* Device bytes the handle will hold for *cfg (admission control).  Returns 0
+ * for an invalid configuration. */
+size_t muffin_workspace_bytes(const muffin_config* cfg);
+
+/* Creates a handle: validates *cfg (E_INVAL / E_SHAPE), allocates the
+ * workspace (E_NOMEM, nothing left allocated), builds FFT, wavelet and DCT
+ * plans.  stream: hipStream_t used for all work (may be 0). */
+int muffin_create(muffin_handle** h, const muffin_config* cfg, void* stream);
+
+/* Sets the problem and runs the set-up of Section 2 (once per solve):
+ * transfer functions from the PSFs, weights, beta_H (power iteration, FP64),
+ * tau, zero state.
+ *   dirty: [L][n][n] device, psf: [L][2n][2n] device (working type).
+ *   alpha: host double[n*n] or NULL -> 1/(||y^n|| + eps_w);
+ *   beta:  host double[L]   or NULL -> 1/(||y_l|| + eps_w)
+ *          (the weight rule of Section 2.1 with the dirty cube as the
+ *           initial estimate; ||W x|| = ||x|| for both dictionaries).
+ *   delta: [L][n][n] device N(0,1) probe, required when cfg->sure.
+ * Checks the cubes for NaN/Inf (E_NONFINITE).  Synchronises the stream. */
+int muffin_set_problem(muffin_handle* h, const void* dirty, const void* psf,
+                       const double* alpha, const double* beta, const void* delta);
+
+/* Runs `iters` iterations (Algorithm 2, or Algorithm 5 when sure), resuming
+ * from the current state.  If report != NULL the stream is synchronised and
+ * *report filled; otherwise the call only enqueues work. */
+int muffin_run(muffin_handle* h, int32_t iters, muffin_report* report);
+
+/* Copies the current sky estimate X (Y trajectory) to x_out [L][n][n]. */
+int muffin_get_sky(muffin_handle* h, void* x_out);
+
+/* State access for checking and checkpointing.
+ *   which: 0 = X, 1 = U ([L][P][n][n]), 2 = V, 3 = T.
+ *   set:   0 = Y trajectory, 1 = Ybar trajectory, 2/3 = d/dmu, d/dgamma of
+ *          the Y trajectory, 4/5 = d/dmu, d/dgamma of the Ybar trajectory. */
+int muffin_get_state(muffin_handle* h, int32_t which, int32_t set, void* out);
+int muffin_set_state(muffin_handle* h, int32_t which, int32_t set, const void* in);
+
+/* Per-update history rows (k, mu, gamma, tau, sugar_mu, sugar_gamma, psure,
+ * res2), at most max_rows; returns the number of rows available. */
+int muffin_get_history(muffin_handle* h, double* rows, int32_t max_rows);
+
+/* Copies the weights in use (host arrays alpha[n*n], beta[L]) and the
+ * current report without running anything.  Synchronises the stream. */
+int muffin_get_weights(muffin_handle* h, double* alpha, double* beta);
+int muffin_get_report(muffin_handle* h, muffin_report* report);
+
+/* Optional device timing of the iteration's stages with HIP events recorded
+ * on the handle's stream (for measurement; adds event records, no sync).
+ * muffin_set_timing clears the totals.  muffin_get_timing synchronises the
+ * stream and writes, per stage, the total milliseconds and the number of
+ * timed calls; it returns the number of stages.  Stage names come from
+ * muffin_stage_name (e.g. "analysis_l1_deriv" is one kernel launch: level-1
+ * analysis + dual update of the four derivative sets). */
+int muffin_set_timing(muffin_handle* h, int32_t on);
+int muffin_get_timing(muffin_handle* h, double* ms, int64_t* calls, int32_t max_stages);
+const char* muffin_stage_name(int32_t stage);
+
+int muffin_destroy(muffin_handle* h);
+const char* muffin_strerror(int code);
+
+/* ---- operator entry points (same kernels as the iteration) ----
+ * in/out are device cubes of the handle's working type.
+ *   op_H:   out = H_l in_l     (eq. `model`)
+ *   op_HT:  out = H_l^T in_l
+ *   op_HTH: out = H_l^T H_l in_l (the data-fidelity gradient without y)
+ *   op_Ws:  out[L][P][n][n] = W_s in (1/sqrt(P) scaling included)
+ *   op_WsT: out[L][n][n] = W_s^T in
+ *   op_dct: out = W_lambda in (DCT-II along bands), op_idct: W_lambda^T in.
+ * Require muffin_set_problem (for H) or only muffin_create (W_s, DCT). */
+int muffin_op_H(muffin_handle* h, const void* in, void* out);
+int muffin_op_HT(muffin_handle* h, const void* in, void* out);
+int muffin_op_HTH(muffin_handle* h, const void* in, void* out);
+int muffin_op_Ws(muffin_handle* h, const void* in, void* out);
+int muffin_op_WsT(muffin_handle* h, const void* in, void* out);
+int muffin_op_dct(muffin_handle* h, const void* in, void* out);
+int muffin_op_idct(muffin_handle* h, const void* in, void* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MUFFIN_H */

@@ -1,0 +1,634 @@
+// Batched 2-D FFT convolution by the per-band PSF (the operator H_l of the
+// measurement model, eq. `model`, Section 2.1) and its adjoint, as used by
+// the data-fidelity gradient of eqs. `grad1`/`grad2` (Algorithms 1-2) and by
+// the derivative recursions (Algorithms 3-4: H^T H x').
+//
+// H_l is the linear convolution with a 2n x 2n PSF restricted to the n x n
+// image window; it is computed exactly as a circular convolution on the
+// 2n x 2n grid of the zero-padded image, H_l x = crop(F^-1(K_l F(pad x))),
+// with K_l = F(ifftshift(psf_l)).  Design:
+//  * rows are real: a length-2n real row (n values, n zeros) is transformed
+//    with one complex FFT of length n on (x[2m], x[2m+1]) pairs plus a
+//    Hermitian post-pass; the n+1 non-redundant frequencies are stored in n
+//    complex slots, kx = 0 and kx = n (both real) sharing slot 0;
+//  * row passes write their spectra transposed ([band][kx][row]), so column
+//    passes read and write whole columns contiguously;
+//  * a column pass does forward FFT (only n non-zero rows are read), the
+//    pointwise product with K (or conj K), inverse FFT, and keeps the n
+//    image rows.  Slot 0 holds two real sequences packed as one complex
+//    sequence; they are separated with the Hermitian split before the
+//    product and stay packed afterwards;
+//  * H^T H = 5 passes (row, column, row, column, row), the middle row pass
+//    doing inverse + crop + pad + forward in LDS;
+//  * FFTs run in LDS: Stockham autosort with radix 8/4/2 butterflies in
+//    registers, twiddles from a table made on the host.
+#include "internal.hpp"
+
+#include <cmath>
+#include <vector>
+
+namespace muffin {
+
+// -------------------------------------------------------------------------
+// small DFTs in registers (forward, exp(-2 pi i / R))
+// -------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void dft2(cplx<T>& a, cplx<T>& b) {
+  cplx<T> t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4(cplx<T>& a0, cplx<T>& a1, cplx<T>& a2, cplx<T>& a3) {
+  cplx<T> s02 = cadd(a0, a2), d02 = csub(a0, a2);
+  cplx<T> s13 = cadd(a1, a3), d13 = csub(a1, a3);
+  // -i * d13 = (d13.y, -d13.x)
+  a0 = cadd(s02, s13);
+  a2 = csub(s02, s13);
+  a1 = {d02.x + d13.y, d02.y - d13.x};
+  a3 = {d02.x - d13.y, d02.y + d13.x};
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dft_small(cplx<T>* v) {
+  if constexpr (R == 2) {
+    dft2(v[0], v[1]);
+  } else if constexpr (R == 4) {
+    dft4(v[0], v[1], v[2], v[3]);
+  } else {
+    static_assert(R == 8, "radix");
+    const T c = T(0.70710678118654752440084436210484903928);
+    cplx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    cplx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3);
+    dft4(o0, o1, o2, o3);
+    // o_k *= exp(-i pi k / 4)
+    o1 = {c * (o1.x + o1.y), c * (o1.y - o1.x)};
+    o2 = {o2.y, -o2.x};
+    o3 = {c * (o3.y - o3.x), -c * (o3.x + o3.y)};
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1);
+    v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2);
+    v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3);
+    v[7] = csub(e3, o3);
+  }
+}
+
+// One Stockham stage: input element j + r*nf/R, output (j - k) R + k + r Ns
+// with k = j mod Ns.  Every thread first loads all its butterflies, then the
+// block synchronises and stores, so the stage runs in place.
+template <typename T, int R, int NT, int EMAX>
+__device__ __forceinline__ void fft_stage(cplx<T>* buf, int lognf, int logNs, int batch,
+                                          int stride, const cplx<T>* __restrict__ tw,
+                                          int logTw) {
+  constexpr int MAXQ = (EMAX / R + NT - 1) / NT;
+  constexpr int LOGR = R == 2 ? 1 : (R == 4 ? 2 : 3);
+  const int lognbf = lognf - LOGR;
+  const int nbf = 1 << lognbf;
+  const int total = nbf * batch;
+  cplx<T> v[MAXQ][R];
+#pragma unroll
+  for (int q = 0; q < MAXQ; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if (t < total) {
+      const int b = t >> lognbf, j = t & (nbf - 1);
+      const cplx<T>* src = buf + b * stride + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = src[r * nbf];
+    }
+  }
+  __syncthreads();
+  const int Ns = 1 << logNs;
+  // twiddle for (r, k): exp(-2 pi i r k / (Ns R)) = tw[r k 2^(logTw - logNs - LOGR)]
+  const int shift = logTw - logNs - LOGR;
+#pragma unroll
+  for (int q = 0; q < MAXQ; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if (t < total) {
+      const int b = t >> lognbf, j = t & (nbf - 1);
+      const int k = j & (Ns - 1);
+      if (logNs > 0) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[(r * k) << shift]);
+      }
+      dft_small<T, R>(v[q]);
+      cplx<T>* dst = buf + b * stride + (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * Ns] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Forward FFT of `batch` sequences of length 2^lognf held in LDS.  Radix
+// schedule: 8s, finishing with 4 or 4,4 or 2 so no stage is wasted.
+template <typename T, int NT, int EMAX>
+__device__ __forceinline__ void lds_fft(cplx<T>* buf, int lognf, int batch, int stride,
+                        const cplx<T>* __restrict__ tw, int logTw) {
+  int done = 0;
+  while (done < lognf) {
+    const int rem = lognf - done;
+    if (rem == 1) {
+      fft_stage<T, 2, NT, EMAX>(buf, lognf, done, batch, stride, tw, logTw);
+      done += 1;
+    } else if (rem == 2 || rem == 4) {
+      fft_stage<T, 4, NT, EMAX>(buf, lognf, done, batch, stride, tw, logTw);
+      done += 2;
+    } else {
+      fft_stage<T, 8, NT, EMAX>(buf, lognf, done, batch, stride, tw, logTw);
+      done += 3;
+    }
+  }
+}
+
+__device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
+
+// Blocks are handed to the 8 XCDs round-robin; remap so that each XCD gets a
+// contiguous range of logical blocks (neighbouring row blocks then share the
+// XCD's L2 when their transposed writes land in the same cache lines).
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int per = (nb + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+static inline int xcd_grid(int nb) { return ((nb + 7) >> 3) << 3; }
+
+template <int NT>
+__device__ double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < NT / 64; ++i) s += sh[i];
+  }
+  return s;  // valid in thread 0
+}
+
+// -------------------------------------------------------------------------
+// row pass
+// -------------------------------------------------------------------------
+enum RowIn { IN_REAL = 0, IN_SPEC = 1, IN_PSF = 2 };
+enum RowOut { OUT_REAL = 0, OUT_SPEC = 1, OUT_PSFTMP = 2 };
+
+template <typename T>
+struct RowArgs {
+  const T* in[kMaxSets];
+  const cplx<T>* in_spec[kMaxSets];
+  T* out[kMaxSets];
+  cplx<T>* out_spec[kMaxSets];
+  const cplx<T>* tw;   // exp(-2 pi i k / 2n)
+  const T* y;          // residual reference for set 0, or null
+  double* partials;
+  int n, logn, L;
+  int rows;            // rows per band: n, or 2n for the PSF pass
+  int nblocks;         // logical blocks per set
+};
+
+template <typename T, int RB, int NT, int IN, int OUT>
+__global__ void __launch_bounds__(NT) row_pass(RowArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  __shared__ double red[NT / 64];
+  const int n = a.n, logn = a.logn;
+  const int stride = n + 1;  // padded LDS row stride
+  const int lb = xcd_remap(blockIdx.x, a.nblocks);
+  if (lb >= a.nblocks) return;
+  const int set = blockIdx.y;
+  const int rblocks = a.rows / RB;
+  const int band = lb / rblocks;
+  const int i0 = (lb - band * rblocks) * RB;
+  const int half = n >> 1;
+  constexpr int EMAX = (sizeof(T) == 8 ? 16 : 32) * NT;
+
+  // ---- load ----
+  if constexpr (IN == IN_REAL) {
+    const T* x = a.in[set] + ((size_t)band * n + i0) * n;
+    for (int t = threadIdx.x; t < RB * n; t += NT) {
+      const int r = t >> logn, m = t & (n - 1);
+      cplx<T> z = {T(0), T(0)};
+      if (m < half) {
+        const T* p = x + (size_t)r * n + 2 * m;
+        z = {p[0], p[1]};
+      }
+      buf[r * stride + m] = z;
+    }
+  } else if constexpr (IN == IN_PSF) {
+    // row i of ifftshift(psf): psf[(i + n) mod 2n][(j + n) mod 2n]
+    const int m2 = 2 * n;
+    const T* ps = a.in[set] + (size_t)band * m2 * m2;
+    for (int t = threadIdx.x; t < RB * n; t += NT) {
+      const int r = t >> logn, m = t & (n - 1);
+      const int row = (i0 + r + n) & (m2 - 1);
+      const int c0 = (2 * m + n) & (m2 - 1);
+      const T* p = ps + (size_t)row * m2;
+      buf[r * stride + m] = {p[c0], p[(c0 + 1) & (m2 - 1)]};
+    }
+  } else {
+    // packed half spectrum, column-major: spec[kx][row]
+    const cplx<T>* sp = a.in_spec[set] + (size_t)band * n * n + i0;
+    for (int t = threadIdx.x; t < RB * n; t += NT) {
+      const int kx = t / RB, r = t - kx * RB;
+      buf[r * stride + kx] = sp[(size_t)kx * n + r];
+    }
+    __syncthreads();
+    // Hermitian pre-pass of the real inverse: with A = X[k], B = conj X[n-k],
+    // Z[k] = (A + B) + i exp(i pi k / n) (A - B); store conj Z for the
+    // inverse-by-forward FFT.  Pairs (k, n-k) are owned by one thread.
+    for (int t = threadIdx.x; t < RB * (half + 1); t += NT) {
+      const int r = t / (half + 1), k = t - r * (half + 1);
+      cplx<T>* row = buf + r * stride;
+      if (k == 0) {
+        const cplx<T> s = row[0];  // (X[0], X[n]) both real
+        const T a0 = s.x, an = s.y;
+        row[0] = {a0 + an, -(a0 - an)};  // conj((a0 + an) + i (a0 - an))
+      } else {
+        const cplx<T> w = cconj(a.tw[k]);  // exp(+i pi k / n)
+        const cplx<T> A = row[k];
+        const cplx<T> B = cconj(row[n - k]);
+        const cplx<T> S = cadd(A, B), D = csub(A, B);
+        const cplx<T> wD = cmul(w, D);
+        const cplx<T> Zk = {S.x - wD.y, S.y + wD.x};
+        if (k == half) {
+          row[k] = cconj(Zk);
+        } else {
+          // partner: A' = X[n-k], B' = conj X[k], w' = exp(i pi (n-k)/n) = -conj(w)
+          const cplx<T> S2 = cconj(S);  // A' + B' = conj(A + B)
+          const cplx<T> D2 = {-D.x, D.y};  // A' - B' = -conj(D)
+          const cplx<T> wD2 = cmul(cplx<T>{-w.x, w.y}, D2);
+          const cplx<T> Zm = {S2.x - wD2.y, S2.y + wD2.x};
+          row[k] = cconj(Zk);
+          row[n - k] = cconj(Zm);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  if constexpr (IN == IN_SPEC) {
+    lds_fft<T, NT, EMAX>(buf, logn, RB, stride, a.tw, logn + 1);
+    // z = conj(buf): x[2m] = z.x, x[2m+1] = z.y for m < n/2 (image window)
+    double acc = 0.0;
+    if constexpr (OUT == OUT_REAL) {
+      T* o = a.out[set] + ((size_t)band * n + i0) * n;
+      for (int t = threadIdx.x; t < RB * half; t += NT) {
+        const int r = t / half, m = t - r * half;
+        const cplx<T> z = buf[r * stride + m];
+        T* p = o + (size_t)r * n + 2 * m;
+        p[0] = z.x;
+        p[1] = -z.y;
+      }
+      return;
+    } else {
+      const T* y = (a.y != nullptr && set == 0) ? a.y + ((size_t)band * n + i0) * n : nullptr;
+      for (int t = threadIdx.x; t < RB * n; t += NT) {
+        const int r = t >> logn, m = t & (n - 1);
+        cplx<T> z = {T(0), T(0)};
+        if (m < half) {
+          const cplx<T> c = buf[r * stride + m];
+          z = {c.x, -c.y};
+          if (y != nullptr) {
+            const T* q = y + (size_t)r * n + 2 * m;
+            const double e0 = double(z.x) - double(q[0]);
+            const double e1 = double(z.y) - double(q[1]);
+            acc += e0 * e0 + e1 * e1;
+          }
+        }
+        buf[r * stride + m] = z;
+      }
+      if (a.partials != nullptr && set == 0) {
+        const double s = block_sum<NT>(acc, red);
+        if (threadIdx.x == 0) a.partials[lb] = s;
+      }
+      __syncthreads();
+    }
+  }
+
+  if constexpr (OUT == OUT_SPEC || OUT == OUT_PSFTMP) {
+    lds_fft<T, NT, EMAX>(buf, logn, RB, stride, a.tw, logn + 1);
+    // Hermitian post-pass of the real forward transform:
+    // X[k] = (Z[k] + conj Z[n-k]) / 2 - (i / 2) exp(-i pi k / n) (Z[k] - conj Z[n-k])
+    for (int t = threadIdx.x; t < RB * (half + 1); t += NT) {
+      const int r = t / (half + 1), k = t - r * (half + 1);
+      cplx<T>* row = buf + r * stride;
+      if (k == 0) {
+        const cplx<T> z = row[0];
+        row[0] = {z.x + z.y, z.x - z.y};  // (X[0], X[n]), both real
+      } else {
+        const cplx<T> w = a.tw[k];
+        const cplx<T> A = row[k];
+        const cplx<T> B = cconj(row[n - k]);
+        const cplx<T> S = cadd(A, B), D = csub(A, B);
+        const cplx<T> wD = cmul(w, D);
+        // X = S/2 - (i/2) wD = (S.x + wD.y, S.y - wD.x) / 2
+        const cplx<T> Xk = {T(0.5) * (S.x + wD.y), T(0.5) * (S.y - wD.x)};
+        if (k == half) {
+          row[k] = Xk;
+        } else {
+          // partner twiddle exp(-i pi (n-k)/n) = -conj(w)
+          const cplx<T> S2 = cconj(S);
+          const cplx<T> D2 = {-D.x, D.y};
+          const cplx<T> wD2 = cmul(cplx<T>{-w.x, w.y}, D2);
+          row[n - k] = {T(0.5) * (S2.x + wD2.y), T(0.5) * (S2.y - wD2.x)};
+          row[k] = Xk;
+        }
+      }
+    }
+    __syncthreads();
+    if constexpr (OUT == OUT_SPEC) {
+      cplx<T>* sp = a.out_spec[set] + (size_t)band * n * n + i0;
+      for (int t = threadIdx.x; t < RB * n; t += NT) {
+        const int kx = t / RB, r = t - kx * RB;
+        sp[(size_t)kx * n + r] = buf[r * stride + kx];
+      }
+    } else {
+      // unpacked n+1 columns of 2n rows: tmp[band][kx][row]
+      const int m2 = 2 * n;
+      cplx<T>* sp = a.out_spec[set] + (size_t)band * (n + 1) * m2 + i0;
+      for (int t = threadIdx.x; t < RB * (n + 1); t += NT) {
+        const int kx = t / RB, r = t - kx * RB;
+        cplx<T> v;
+        if (kx == 0) v = {buf[r * stride].x, T(0)};
+        else if (kx == n) v = {buf[r * stride].y, T(0)};
+        else v = buf[r * stride + kx];
+        sp[(size_t)kx * m2 + r] = v;
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------------------
+// column pass
+// -------------------------------------------------------------------------
+template <typename T>
+struct ColArgs {
+  const cplx<T>* in[kMaxSets];
+  cplx<T>* out[kMaxSets];
+  const cplx<T>* Kh;   // [L][n+1][2n]
+  const cplx<T>* tw;
+  int n, logn, L;
+  int B;               // columns per block
+  int conj;            // use conj(K)
+  int nblocks;
+};
+
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) col_pass(ColArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int n = a.n, m2 = 2 * n, B = a.B;
+  const int lb = xcd_remap(blockIdx.x, a.nblocks);
+  if (lb >= a.nblocks) return;
+  const int set = blockIdx.y;
+  const int cpb = n / B;  // column groups per band
+  const int band = lb / cpb;
+  const int kx0 = (lb - band * cpb) * B;
+  constexpr int EMAX = 16 * NT;  // B * 2n <= 4096
+  const cplx<T>* src = a.in[set] + ((size_t)band * n + kx0) * n;
+  for (int t = threadIdx.x; t < B * m2; t += NT) {
+    const int b = t / m2, i = t - b * m2;
+    buf[b * m2 + i] = i < n ? src[(size_t)b * n + i] : cplx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  lds_fft<T, NT, EMAX>(buf, a.logn + 1, B, m2, a.tw, a.logn + 1);
+  const cplx<T>* Kb = a.Kh + (size_t)band * (n + 1) * m2;
+  for (int t = threadIdx.x; t < B * m2; t += NT) {
+    const int b = t / m2, ky = t - b * m2;
+    const int kx = kx0 + b;
+    cplx<T>* col = buf + b * m2;
+    if (kx != 0) {
+      cplx<T> K = Kb[(size_t)kx * m2 + ky];
+      if (a.conj) K = cconj(K);
+      col[ky] = cconj(cmul(col[ky], K));
+    } else if (ky <= n) {
+      // slot 0 packs two real columns (kx = 0 and kx = n) as p + i q;
+      // G = 1/2 (F + conj F-) K0 + 1/2 (F - conj F-) Kn, pairs (ky, 2n - ky)
+      const int kz = (m2 - ky) & (m2 - 1);
+      const cplx<T> F = col[ky], Fm = col[kz];
+      cplx<T> K0 = Kb[ky], Kn = Kb[(size_t)n * m2 + ky];
+      cplx<T> K0m = Kb[kz], Knm = Kb[(size_t)n * m2 + kz];
+      if (a.conj) {
+        K0 = cconj(K0); Kn = cconj(Kn); K0m = cconj(K0m); Knm = cconj(Knm);
+      }
+      const cplx<T> Sp = cadd(F, cconj(Fm)), Dp = csub(F, cconj(Fm));
+      cplx<T> G = cadd(cmul(Sp, K0), cmul(Dp, Kn));
+      G = {T(0.5) * G.x, T(0.5) * G.y};
+      if (kz != ky) {
+        const cplx<T> Sm = cadd(Fm, cconj(F)), Dm = csub(Fm, cconj(F));
+        cplx<T> Gm = cadd(cmul(Sm, K0m), cmul(Dm, Knm));
+        Gm = {T(0.5) * Gm.x, T(0.5) * Gm.y};
+        col[kz] = cconj(Gm);
+      }
+      col[ky] = cconj(G);
+    }
+  }
+  __syncthreads();
+  lds_fft<T, NT, EMAX>(buf, a.logn + 1, B, m2, a.tw, a.logn + 1);
+  cplx<T>* dst = a.out[set] + ((size_t)band * n + kx0) * n;
+  for (int t = threadIdx.x; t < B * n; t += NT) {
+    const int b = t / n, i = t - b * n;
+    dst[(size_t)b * n + i] = cconj(buf[b * m2 + i]);
+  }
+}
+
+// PSF column pass: full 2n-point transform of each of the n+1 columns,
+// scaled by 1/(2n)^2 (the inverse-transform normalisation, folded into K).
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) psf_cols(const cplx<T>* tmp, cplx<T>* Kh,
+                                               const cplx<T>* tw, int n, int logn) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int m2 = 2 * n;
+  const int kx = blockIdx.x, band = blockIdx.y;
+  const size_t off = ((size_t)band * (n + 1) + kx) * m2;
+  for (int i = threadIdx.x; i < m2; i += NT) buf[i] = tmp[off + i];
+  __syncthreads();
+  lds_fft<T, NT, 16 * NT>(buf, logn + 1, 1, m2, tw, logn + 1);
+  const T s = T(1.0 / (4.0 * double(n) * double(n)));
+  for (int i = threadIdx.x; i < m2; i += NT) {
+    const cplx<T> v = buf[i];
+    Kh[off + i] = {v.x * s, v.y * s};
+  }
+}
+
+// -------------------------------------------------------------------------
+// host side
+// -------------------------------------------------------------------------
+constexpr int kRowNT = 256;
+constexpr int kColNT = 256;
+
+template <typename T>
+static int row_rb(int n) {
+  // rows per block: keep RB * n <= 32 * NT and 64-byte transposed segments
+  const int emax = (sizeof(T) == 8 ? 16 : 32) * kRowNT;
+  int rb = sizeof(T) == 8 ? 4 : 8;
+  while (rb > 1 && rb * n > emax) rb >>= 1;
+  if (rb > n) rb = n;
+  return rb;
+}
+
+template <typename T>
+int fft_make_plan(FftPlan<T>& p, int n, int L, hipStream_t s) {
+  p.n = n;
+  p.L = L;
+  const int m2 = 2 * n;
+  std::vector<cplx<T>> h(m2);
+  for (int k = 0; k < m2; ++k) {
+    const long double ang = -2.0L * 3.14159265358979323846264338327950288L * k / m2;
+    h[k] = {T(cosl(ang)), T(sinl(ang))};
+  }
+  MUFFIN_HIP_CHECK(hipMalloc(&p.tw, sizeof(cplx<T>) * m2));
+  MUFFIN_HIP_CHECK(hipMemcpyAsync(p.tw, h.data(), sizeof(cplx<T>) * m2,
+                                  hipMemcpyHostToDevice, s));
+  MUFFIN_HIP_CHECK(hipStreamSynchronize(s));
+  MUFFIN_HIP_CHECK(hipMalloc(&p.Kh, sizeof(cplx<T>) * (size_t)L * (n + 1) * m2));
+  return 0;
+}
+
+template <typename T>
+void fft_free_plan(FftPlan<T>& p) {
+  if (p.tw) (void)hipFree(p.tw);
+  if (p.Kh) (void)hipFree(p.Kh);
+  p.tw = nullptr;
+  p.Kh = nullptr;
+}
+
+template <typename T, int RB, int IN, int OUT>
+static int launch_row_rb(RowArgs<T>& a, int nsets, hipStream_t s) {
+  const int n = a.n;
+  a.nblocks = a.L * (a.rows / RB);
+  const size_t shm = sizeof(cplx<T>) * (size_t)RB * (n + 1);
+  dim3 grid(xcd_grid(a.nblocks), nsets);
+  MUFFIN_ALLOW_BIG_LDS((row_pass<T, RB, kRowNT, IN, OUT>));
+  row_pass<T, RB, kRowNT, IN, OUT><<<grid, kRowNT, shm, s>>>(a);
+  MUFFIN_HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+template <typename T, int IN, int OUT>
+static int launch_row(RowArgs<T>& a, int nsets, hipStream_t s) {
+  switch (row_rb<T>(a.n)) {
+    case 8: return launch_row_rb<T, 8, IN, OUT>(a, nsets, s);
+    case 4: return launch_row_rb<T, 4, IN, OUT>(a, nsets, s);
+    case 2: return launch_row_rb<T, 2, IN, OUT>(a, nsets, s);
+    default: return launch_row_rb<T, 1, IN, OUT>(a, nsets, s);
+  }
+}
+
+int fft_res_blocks(int n, int L, int elem_bytes) {
+  const int emax = (elem_bytes == 8 ? 16 : 32) * kRowNT;
+  int rb = elem_bytes == 8 ? 4 : 8;
+  while (rb > 1 && rb * n > emax) rb >>= 1;
+  if (rb > n) rb = n;
+  return L * (n / rb);
+}
+
+template <typename T>
+static int launch_col(const FftPlan<T>& p, const cplx<T>* const* in, cplx<T>* const* out,
+                      int nsets, int conj, hipStream_t s) {
+  ColArgs<T> a{};
+  for (int i = 0; i < nsets; ++i) {
+    a.in[i] = in[i];
+    a.out[i] = out[i];
+  }
+  a.Kh = p.Kh;
+  a.tw = p.tw;
+  a.n = p.n;
+  a.logn = 31 - __builtin_clz(p.n);
+  a.L = p.L;
+  a.B = std::max(1, 2048 / (2 * p.n));
+  if (a.B > p.n) a.B = p.n;
+  a.conj = conj;
+  a.nblocks = p.L * (p.n / a.B);
+  const size_t shm = sizeof(cplx<T>) * (size_t)a.B * 2 * p.n;
+  dim3 grid(xcd_grid(a.nblocks), nsets);
+  MUFFIN_ALLOW_BIG_LDS((col_pass<T, kColNT>));
+  col_pass<T, kColNT><<<grid, kColNT, shm, s>>>(a);
+  MUFFIN_HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+template <typename T>
+int fft_psf_spectrum(FftPlan<T>& p, const T* psf, cplx<T>* tmp, hipStream_t s) {
+  RowArgs<T> a{};
+  a.in[0] = psf;
+  a.out_spec[0] = tmp;
+  a.tw = p.tw;
+  a.n = p.n;
+  a.logn = 31 - __builtin_clz(p.n);
+  a.L = p.L;
+  a.rows = 2 * p.n;
+  int rc = launch_row<T, IN_PSF, OUT_PSFTMP>(a, 1, s);
+  if (rc) return rc;
+  const size_t shm = sizeof(cplx<T>) * 2 * p.n;
+  MUFFIN_ALLOW_BIG_LDS((psf_cols<T, kColNT>));
+  psf_cols<T, kColNT><<<dim3(p.n + 1, p.L), kColNT, shm, s>>>(tmp, p.Kh, p.tw, p.n, a.logn);
+  MUFFIN_HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+template <typename T>
+int fft_chain(const FftPlan<T>& p, const ChainIO<T>& io, int op, hipStream_t s) {
+  const int ns = io.nsets;
+  RowArgs<T> a{};
+  a.tw = p.tw;
+  a.n = p.n;
+  a.logn = 31 - __builtin_clz(p.n);
+  a.L = p.L;
+  a.rows = p.n;
+  // row forward from the images into specA
+  for (int i = 0; i < ns; ++i) {
+    a.in[i] = io.in[i];
+    a.out_spec[i] = io.specA[i];
+  }
+  int rc = launch_row<T, IN_REAL, OUT_SPEC>(a, ns, s);
+  if (rc) return rc;
+  const cplx<T>* cin[kMaxSets];
+  cplx<T>* cout[kMaxSets];
+  for (int i = 0; i < ns; ++i) {
+    cin[i] = io.specA[i];
+    cout[i] = io.specB[i];
+  }
+  rc = launch_col<T>(p, cin, cout, ns, op == 1 ? 1 : 0, s);
+  if (rc) return rc;
+  if (op == 2) {
+    // inverse rows, crop, (residual), pad, forward rows: specB -> specA
+    RowArgs<T> b = a;
+    for (int i = 0; i < ns; ++i) {
+      b.in_spec[i] = io.specB[i];
+      b.out_spec[i] = io.specA[i];
+    }
+    b.y = io.y;
+    b.partials = io.res_partials;
+    rc = launch_row<T, IN_SPEC, OUT_SPEC>(b, ns, s);
+    if (rc) return rc;
+    for (int i = 0; i < ns; ++i) {
+      cin[i] = io.specA[i];
+      cout[i] = io.specB[i];
+    }
+    rc = launch_col<T>(p, cin, cout, ns, 1, s);
+    if (rc) return rc;
+  }
+  RowArgs<T> c = a;
+  for (int i = 0; i < ns; ++i) {
+    c.in_spec[i] = io.specB[i];
+    c.out[i] = io.out[i];
+  }
+  return launch_row<T, IN_SPEC, OUT_REAL>(c, ns, s);
+}
+
+template int fft_make_plan<double>(FftPlan<double>&, int, int, hipStream_t);
+template int fft_make_plan<float>(FftPlan<float>&, int, int, hipStream_t);
+template void fft_free_plan<double>(FftPlan<double>&);
+template void fft_free_plan<float>(FftPlan<float>&);
+template int fft_psf_spectrum<double>(FftPlan<double>&, const double*, cplx<double>*, hipStream_t);
+template int fft_psf_spectrum<float>(FftPlan<float>&, const float*, cplx<float>*, hipStream_t);
+template int fft_chain<double>(const FftPlan<double>&, const ChainIO<double>&, int, hipStream_t);
+template int fft_chain<float>(const FftPlan<float>&, const ChainIO<float>&, int, hipStream_t);
+
+}  // namespace muffin

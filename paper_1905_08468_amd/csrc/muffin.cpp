@@ -1,0 +1,1006 @@
+// libmuffin runtime: handle, workspace, set-up and the iteration driver.
+//
+// One iteration (Algorithm 2; Algorithm 5 with sure = 1) is a fixed
+// sequence of launches on the caller's stream, with no host
+// synchronisation:
+//   1. G_s = H^T H X_s for all state sets          (eq. `grad2`; Algs. 3-4)
+//   2. S_s = beta_l W_s^T(a1 U_s + a2 U_primal)    (eq. `adjointspat2`)
+//   3. X~_s = (X_s - tau (G_s - H^T y + S_s + T_s))_+ and its derivatives
+//                                                  (eqs. `stpm`, `stpx`)
+//   4. U_s <- sat(U_s + sigma beta_l W_s(z_s))    (eqs. `stpp`, `stpu`)
+//   5. V_s <- sat(V_s + sigma alpha_n C z_s), T_s = alpha_n C^T(...)
+//                                                  (eqs. `vt`, `v`, `upt`)
+//   6. X_s <- X~_s (pointer swap)                   (eq. `updatenode2`)
+// State sets: 0 = primal on Y, 1 = primal on Ybar = Y + eps delta,
+// 2/3 = d/dmu, d/dgamma of set 0, 4/5 = the same for set 1.  After every
+// Delta completed iterations, SUGAR is reduced in FP64 from
+// <H^T H X - H^T y, X'> and <H^T delta, Xbar' - X'> (eq. `SUGAR` rewritten
+// with adjoints), theta is updated on the device (eq. `adaptgrad`) and the
+// derivative states restart from zero.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "../../include/muffin.h"
+#include "internal.hpp"
+
+using namespace muffin;
+
+#define RC(expr)                \
+  do {                          \
+    int _rc = (expr);           \
+    if (_rc != 0) return _rc;   \
+  } while (0)
+
+namespace {
+
+// Stages timed with HIP events when timing is on (muffin_set_timing).
+enum Stage {
+  ST_FFT_PRIMAL = 0,   // H^T H X for the primal sets (5 launches)
+  ST_FFT_DERIV,        // H^T H X' for the derivative sets
+  ST_SYN_DEEP,         // synthesis levels J..2
+  ST_SYN_L1,           // synthesis level 1 (one launch, all sets)
+  ST_PRIMAL,           // primal step (one launch)
+  ST_AN_L1_PRIMAL,     // analysis level 1 + dual update, primal sets (one launch)
+  ST_AN_DEEP_PRIMAL,   // analysis levels 2..J, primal sets
+  ST_AN_L1_DERIV,      // analysis level 1, derivative sets (one launch)
+  ST_AN_DEEP_DERIV,    // analysis levels 2..J, derivative sets
+  ST_DCT_PRIMAL,       // spectral DCT update, primal sets (one launch)
+  ST_DCT_DERIV,        // spectral DCT update, derivative sets (one launch)
+  ST_WINDOW,           // SURE/SUGAR reductions, theta update, resets
+  ST_COUNT
+};
+
+const char* const kStageNames[ST_COUNT] = {
+    "fft_chain_primal", "fft_chain_deriv", "synthesis_deep", "synthesis_l1",
+    "primal_step",      "analysis_l1_primal", "analysis_deep_primal", "analysis_l1_deriv",
+    "analysis_deep_deriv", "dct_primal", "dct_deriv", "window_update"};
+
+struct Timer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<int> pending_stage;   // stage of each recorded pair
+  size_t used = 0;                  // events used since the last collect
+  double ms[ST_COUNT] = {};
+  long long calls[ST_COUNT] = {};
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void begin(int stage, hipStream_t s) {
+    if (!on) return;
+    hipEvent_t e = get();
+    if (e) (void)hipEventRecord(e, s);
+    pending_stage.push_back(stage);
+  }
+  void end(hipStream_t s) {
+    if (!on) return;
+    hipEvent_t e = get();
+    if (e) (void)hipEventRecord(e, s);
+  }
+  int collect(hipStream_t s) {
+    if (used == 0) return 0;
+    if (hipStreamSynchronize(s) != hipSuccess) return -5;
+    for (size_t i = 0; i < pending_stage.size() && 2 * i + 1 < used; ++i) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, pool[2 * i], pool[2 * i + 1]) == hipSuccess) {
+        ms[pending_stage[i]] += t;
+        calls[pending_stage[i]] += 1;
+      }
+    }
+    pending_stage.clear();
+    used = 0;
+    return 0;
+  }
+  void reset() {
+    for (int i = 0; i < ST_COUNT; ++i) {
+      ms[i] = 0;
+      calls[i] = 0;
+    }
+  }
+  ~Timer() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int validate(const muffin_config* c) {
+  if (!c) return MUFFIN_E_INVAL;
+  if (!is_pow2(c->n) || c->n < 8 || c->n > 2048) return MUFFIN_E_SHAPE;
+  if (c->L < 1 || c->L > 256) return MUFFIN_E_SHAPE;
+  if (c->n_bases < 1 || c->n_bases > kMaxBases) return MUFFIN_E_SHAPE;
+  if (c->levels < 1 || (c->n >> c->levels) < 1) return MUFFIN_E_SHAPE;
+  if (c->mode < MUFFIN_F64 || c->mode > MUFFIN_F32_BF16DCT) return MUFFIN_E_INVAL;
+  if (!(c->sigma > 0) || !(c->mu >= 0) || !(c->gamma >= 0)) return MUFFIN_E_INVAL;
+  if (c->tau <= 0 && !(c->rho > 0 && c->rho < 1)) return MUFFIN_E_INVAL;
+  if (c->tau_rule != MUFFIN_TAU_OPNORM && c->tau_rule != MUFFIN_TAU_PAPER_SUM)
+    return MUFFIN_E_INVAL;
+  if (!(c->eps_w > 0)) return MUFFIN_E_INVAL;
+  if (c->sure) {
+    if (c->delta_period < 1) return MUFFIN_E_INVAL;
+    if (!(c->eps_fd > 0) || !(c->sigma_w > 0)) return MUFFIN_E_INVAL;
+    if (!(c->eta_mu >= 0) || !(c->eta_gamma >= 0)) return MUFFIN_E_INVAL;
+  }
+  if (c->tau <= 0 && c->pi_iters < 1) return MUFFIN_E_INVAL;
+  return MUFFIN_OK;
+}
+
+struct Dev {
+  std::vector<void*> owned;
+  bool failed = false;
+  template <typename U>
+  U* alloc(size_t count) {
+    if (failed) return nullptr;
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&p, sizeof(U) * count) != hipSuccess) {
+      (void)hipGetLastError();
+      failed = true;
+      return nullptr;
+    }
+    owned.push_back(p);
+    return static_cast<U*>(p);
+  }
+  void release() {
+    for (void* p : owned) (void)hipFree(p);
+    owned.clear();
+  }
+};
+
+struct ImplBase {
+  virtual ~ImplBase() = default;
+  virtual int init() = 0;
+  virtual int set_problem(const void*, const void*, const double*, const double*,
+                          const void*) = 0;
+  virtual int run(int iters) = 0;
+  virtual int report(muffin_report* r) = 0;
+  virtual int get_state(int which, int set, void* out) = 0;
+  virtual int set_state(int which, int set, const void* in) = 0;
+  virtual int history(double* rows, int max_rows) = 0;
+  virtual int weights(double* alpha, double* beta) = 0;
+  virtual int op(int kind, const void* in, void* out) = 0;
+  virtual Timer& timer() = 0;
+  virtual hipStream_t stream() = 0;
+};
+
+size_t workspace_bytes_of(const muffin_config* c) {
+  const size_t n = c->n, L = c->L, P = c->n_bases;
+  const size_t N = n * n, LN = L * N;
+  const size_t es = c->mode == MUFFIN_F64 ? 8 : 4;
+  const size_t nsets = c->sure ? 6 : 1;
+  // per set: X, X~, V, T, G, S + U (P LN) + scratch (4 LN: two spectra, or
+  // the wavelet low-pass temporaries)
+  const size_t per_set = (6 + P + 4) * LN * es;
+  size_t shared = LN * es * (c->sure ? 5 : 2);                  // Y, Ybar, HTy, HTybar, HTd
+  shared += L * (n + 1) * 2 * n * 2 * es;                        // transfer functions
+  shared += c->sure ? 2 * (P + 1) * LN : 0;                      // masks (bytes)
+  shared += (N + L) * 8 + 4096 * 8 + 64 * 1024;                  // weights, partials, params
+  return nsets * per_set + shared;
+}
+
+template <typename T>
+struct Impl final : ImplBase {
+  muffin_config cfg;
+  hipStream_t st;
+  int n, L, P, J, N;
+  size_t LN;
+  int nsets;
+  Dev dev;
+  FftPlan<T> fft;
+  DwtPlan<T> dwt;
+  DctPlan<T> dct;
+  DevParams* dp = nullptr;
+  DevParams hp{};
+  T *X[kMaxSets]{}, *Xt[kMaxSets]{}, *U[kMaxSets]{}, *V[kMaxSets]{}, *Tt[kMaxSets]{};
+  T *G[kMaxSets]{}, *S[kMaxSets]{}, *scr[kMaxSets]{};
+  uint8_t *maskU[2]{}, *maskV[2]{};
+  T *Y = nullptr, *Ybar = nullptr, *HTy = nullptr, *HTybar = nullptr, *HTd = nullptr;
+  double *alpha = nullptr, *beta = nullptr, *partials = nullptr, *hist = nullptr;
+  int* flag = nullptr;
+  int max_hist = 0;
+  bool have_problem = false;
+  int k_done = 0;
+  int n_upd = 0;
+  double beta_H = 0.0;
+  Timer tm;
+
+  Timer& timer() override { return tm; }
+  hipStream_t stream() override { return st; }
+
+  Impl(const muffin_config& c, hipStream_t s) : cfg(c), st(s) {
+    n = c.n;
+    L = c.L;
+    P = c.n_bases;
+    J = c.levels;
+    N = n * n;
+    LN = (size_t)L * N;
+    nsets = c.sure ? 6 : 1;
+  }
+  ~Impl() override {
+    fft_free_plan(fft);
+    dct_free_plan(dct);
+    dev.release();
+  }
+
+  cplx<T>* specA(int s) { return reinterpret_cast<cplx<T>*>(scr[s]); }
+  cplx<T>* specB(int s) { return reinterpret_cast<cplx<T>*>(scr[s] + 2 * LN); }
+  T* tmp0(int s) { return scr[s]; }
+  T* tmp1(int s) { return scr[s] + 2 * LN; }
+
+  int init() override {
+    for (int s = 0; s < nsets; ++s) {
+      X[s] = dev.alloc<T>(LN);
+      Xt[s] = dev.alloc<T>(LN);
+      U[s] = dev.alloc<T>(LN * P);
+      V[s] = dev.alloc<T>(LN);
+      Tt[s] = dev.alloc<T>(LN);
+      G[s] = dev.alloc<T>(LN);
+      S[s] = dev.alloc<T>(LN);
+      scr[s] = dev.alloc<T>(4 * LN);
+    }
+    Y = dev.alloc<T>(LN);
+    HTy = dev.alloc<T>(LN);
+    if (cfg.sure) {
+      Ybar = dev.alloc<T>(LN);
+      HTybar = dev.alloc<T>(LN);
+      HTd = dev.alloc<T>(LN);
+      for (int t = 0; t < 2; ++t) {
+        maskU[t] = dev.alloc<uint8_t>(LN * P);
+        maskV[t] = dev.alloc<uint8_t>(LN);
+      }
+    }
+    alpha = dev.alloc<double>(N);
+    beta = dev.alloc<double>(L);
+    const int nres = fft_res_blocks(n, L, sizeof(T));
+    partials = dev.alloc<double>(std::max({nres, dot_blocks(), 64 * L * 3, 4096}));
+    max_hist = 4096;
+    hist = dev.alloc<double>((size_t)max_hist * kHistCols);
+    dp = dev.alloc<DevParams>(1);
+    flag = dev.alloc<int>(1);
+    if (dev.failed) {
+      dev.release();
+      return MUFFIN_E_NOMEM;
+    }
+    RC(fft_make_plan(fft, n, L, st));
+    dwt.n = n;
+    dwt.L = L;
+    dwt.P = P;
+    dwt.J = J;
+    RC(dwt_upload_filters(P));
+    RC(dct_make_plan(dct, L, N, sizeof(T) == 8 ? DCT_F64 : DCT_F32));
+    hp.sigma = cfg.sigma;
+    hp.mu = cfg.mu;
+    hp.gamma = cfg.gamma;
+    MUFFIN_HIP_CHECK(hipMemcpy(dp, &hp, sizeof(hp), hipMemcpyHostToDevice));
+    return 0;
+  }
+
+  // -- operator helpers ------------------------------------------------
+  int chain(const T* const* in, T* const* out, const int* sets, int ns, int op,
+            const T* y = nullptr, double* res = nullptr) {
+    ChainIO<T> io{};
+    for (int i = 0; i < ns; ++i) {
+      io.in[i] = in[i];
+      io.out[i] = out[i];
+      io.specA[i] = specA(sets[i]);
+      io.specB[i] = specB(sets[i]);
+    }
+    io.y = y;
+    io.res_partials = res;
+    io.nsets = ns;
+    return fft_chain(fft, io, op, st);
+  }
+
+  int chain1(const T* in, T* out, int op) {
+    const int s0 = 0;
+    return chain(&in, &out, &s0, 1, op);
+  }
+
+  // -- power iteration (FP64) ------------------------------------------
+  int power_iteration(const T* psf) {
+    FftPlan<double> f64;
+    FftPlan<double>* pf = nullptr;
+    Dev tmp;
+    double* psf64 = nullptr;
+    if constexpr (sizeof(T) == 8) {
+      pf = reinterpret_cast<FftPlan<double>*>(&fft);
+    } else {
+      RC(fft_make_plan(f64, n, L, st));
+      pf = &f64;
+      psf64 = tmp.alloc<double>((size_t)L * 4 * N);
+      cplx<double>* ktmp = tmp.alloc<cplx<double>>((size_t)L * (n + 1) * 2 * n);
+      if (tmp.failed) {
+        fft_free_plan(f64);
+        tmp.release();
+        return MUFFIN_E_NOMEM;
+      }
+      const float* psf32 = reinterpret_cast<const float*>(psf);
+      const int crc = convert<float, double>(psf64, psf32, (size_t)L * 4 * N, st);
+      RC(crc);
+      RC(fft_psf_spectrum(f64, psf64, ktmp, st));
+    }
+    double* v = tmp.alloc<double>(LN);
+    double* w = tmp.alloc<double>(LN);
+    cplx<double>* sa = tmp.alloc<cplx<double>>(LN);
+    cplx<double>* sb = tmp.alloc<cplx<double>>(LN);
+    double* stats = tmp.alloc<double>((size_t)3 * L);
+    if (tmp.failed) {
+      if (sizeof(T) == 4) fft_free_plan(f64);
+      tmp.release();
+      return MUFFIN_E_NOMEM;
+    }
+    const int bpb = 64;
+    RC(pi_init(v, LN, 0x5EEDull, st));
+    std::vector<double> hs(3 * L);
+    double prev = 0.0, lam = 0.0;
+    int rc = 0;
+    for (int it = 1; it <= cfg.pi_iters; ++it) {
+      ChainIO<double> io{};
+      io.in[0] = v;
+      io.out[0] = w;
+      io.specA[0] = sa;
+      io.specB[0] = sb;
+      io.nsets = 1;
+      if ((rc = fft_chain(*pf, io, 2, st))) break;
+      if ((rc = pi_band_dots(v, w, L, N, partials, bpb, st))) break;
+      if ((rc = pi_band_finish(partials, L, bpb, stats, st))) break;
+      if ((rc = pi_normalise(v, w, stats, L, N, st))) break;
+      if (it % 10 == 0 || it == cfg.pi_iters) {
+        if (hipMemcpyAsync(hs.data(), stats, sizeof(double) * 3 * L, hipMemcpyDeviceToHost,
+                           st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+          rc = MUFFIN_E_HIP;
+          break;
+        }
+        lam = 0.0;
+        for (int l = 0; l < L; ++l) lam = std::max(lam, hs[3 * l] / hs[3 * l + 2]);
+        if (it > 10 && std::fabs(lam - prev) <= cfg.pi_tol * std::fabs(lam)) break;
+        prev = lam;
+      }
+    }
+    (void)hipStreamSynchronize(st);
+    if (sizeof(T) == 4) fft_free_plan(f64);
+    tmp.release();
+    if (rc) return rc;
+    beta_H = lam;
+    return 0;
+  }
+
+  int set_problem(const void* dirty, const void* psf, const double* a_host,
+                  const double* b_host, const void* delta) override {
+    if (!dirty || !psf) return MUFFIN_E_INVAL;
+    if (cfg.sure && !delta) return MUFFIN_E_INVAL;
+    const T* dy = static_cast<const T*>(dirty);
+    const T* ps = static_cast<const T*>(psf);
+    const T* de = static_cast<const T*>(delta);
+    // non-finite inputs
+    MUFFIN_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int), st));
+    RC(count_nonfinite(dy, LN, flag, st));
+    RC(count_nonfinite(ps, (size_t)L * 4 * N, flag, st));
+    if (cfg.sure) RC(count_nonfinite(de, LN, flag, st));
+    int hflag = 0;
+    MUFFIN_HIP_CHECK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    MUFFIN_HIP_CHECK(hipStreamSynchronize(st));
+    if (hflag) return MUFFIN_E_NONFINITE;
+    MUFFIN_HIP_CHECK(hipMemcpyAsync(Y, dy, sizeof(T) * LN, hipMemcpyDeviceToDevice, st));
+    // transfer functions (K-PSF)
+    {
+      Dev tmp;
+      cplx<T>* ktmp = tmp.alloc<cplx<T>>((size_t)L * (n + 1) * 2 * n);
+      if (tmp.failed) return MUFFIN_E_NOMEM;
+      int rc = fft_psf_spectrum(fft, ps, ktmp, st);
+      (void)hipStreamSynchronize(st);
+      tmp.release();
+      RC(rc);
+    }
+    // weights (Section 2.1)
+    std::vector<double> ha(N), hb(L);
+    if (!a_host || !b_host) {
+      RC(weights_from(Y, L, N, cfg.eps_w, alpha, beta, partials, st));
+      MUFFIN_HIP_CHECK(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * N,
+                                      hipMemcpyDeviceToHost, st));
+      MUFFIN_HIP_CHECK(hipMemcpyAsync(hb.data(), beta, sizeof(double) * L,
+                                      hipMemcpyDeviceToHost, st));
+      MUFFIN_HIP_CHECK(hipStreamSynchronize(st));
+    }
+    if (a_host) std::copy(a_host, a_host + N, ha.begin());
+    if (b_host) std::copy(b_host, b_host + L, hb.begin());
+    for (double v : ha)
+      if (!std::isfinite(v) || v < 0) return MUFFIN_E_INVAL;
+    for (double v : hb)
+      if (!std::isfinite(v) || v < 0) return MUFFIN_E_INVAL;
+    MUFFIN_HIP_CHECK(hipMemcpyAsync(alpha, ha.data(), sizeof(double) * N,
+                                    hipMemcpyHostToDevice, st));
+    MUFFIN_HIP_CHECK(hipMemcpyAsync(beta, hb.data(), sizeof(double) * L,
+                                    hipMemcpyHostToDevice, st));
+    double ma = 0, sa = 0, mb = 0, sb = 0;
+    for (double v : ha) {
+      ma = std::max(ma, v * v);
+      sa += v * v;
+    }
+    for (double v : hb) {
+      mb = std::max(mb, v * v);
+      sb += v * v;
+    }
+    // Lipschitz constant and tau (Section 2.2)
+    beta_H = 0.0;
+    if (cfg.tau <= 0 || cfg.pi_iters > 0) RC(power_iteration(ps));
+    hp = DevParams{};
+    hp.mu = cfg.mu;
+    hp.gamma = cfg.gamma;
+    hp.sigma = cfg.sigma;
+    hp.beta_H = beta_H;
+    hp.max_beta2 = mb;
+    hp.sum_beta2 = sb;
+    hp.max_alpha2 = ma;
+    hp.sum_alpha2 = sa;
+    hp.rho = cfg.rho;
+    hp.eta_mu = cfg.eta_mu;
+    hp.eta_gamma = cfg.eta_gamma;
+    hp.eps_fd = cfg.eps_fd;
+    hp.sigma_w = cfg.sigma_w;
+    if (cfg.tau > 0) {
+      hp.tau_rule = -1;
+      hp.tau = cfg.tau;
+    } else {
+      hp.tau_rule = cfg.tau_rule;
+      const double k = cfg.tau_rule == MUFFIN_TAU_OPNORM
+                           ? cfg.mu * cfg.mu * mb + cfg.gamma * cfg.gamma * ma
+                           : cfg.mu * cfg.mu * sb + cfg.gamma * cfg.gamma * sa;
+      hp.tau = cfg.rho / (0.5 * beta_H + cfg.sigma * k);
+    }
+    MUFFIN_HIP_CHECK(hipMemcpyAsync(dp, &hp, sizeof(hp), hipMemcpyHostToDevice, st));
+    // H^T y, and for ADA-PT the perturbed data Ybar = Y + eps delta (Alg. 5)
+    RC(chain1(Y, HTy, 1));
+    if (cfg.sure) {
+      RC(axpy_copy(Ybar, Y, de, cfg.eps_fd, LN, st));
+      RC(chain1(Ybar, HTybar, 1));
+      RC(chain1(de, HTd, 1));
+    }
+    // zero state
+    for (int s = 0; s < nsets; ++s) {
+      RC(fill_zero(X[s], LN, st));
+      RC(fill_zero(U[s], LN * P, st));
+      RC(fill_zero(V[s], LN, st));
+      RC(fill_zero(Tt[s], LN, st));
+    }
+    MUFFIN_HIP_CHECK(hipStreamSynchronize(st));
+    k_done = 0;
+    n_upd = 0;
+    have_problem = true;
+    return 0;
+  }
+
+  // -- one iteration ---------------------------------------------------
+  int iterate() {
+    const bool sure = cfg.sure != 0;
+    // 1. H^T H X for every set
+    {
+      const int sets[2] = {0, 1};
+      const T* in[2] = {X[0], X[1]};
+      T* out[2] = {G[0], G[1]};
+      tm.begin(ST_FFT_PRIMAL, st);
+      RC(chain(in, out, sets, sure ? 2 : 1, 2));
+      tm.end(st);
+      if (sure) {
+        const int ds[4] = {2, 3, 4, 5};
+        const T* din[4] = {X[2], X[3], X[4], X[5]};
+        T* dout[4] = {G[2], G[3], G[4], G[5]};
+        tm.begin(ST_FFT_DERIV, st);
+        RC(chain(din, dout, ds, 4, 2));
+        tm.end(st);
+      }
+    }
+    // 2. synthesis
+    {
+      SynthesisIO<T> io{};
+      io.nsets = nsets;
+      io.beta = beta;
+      for (int s = 0; s < nsets; ++s) {
+        io.Ua[s] = U[s];
+        io.a1_sel[s] = SEL_MU;
+        io.Ub[s] = nullptr;
+        io.a2_sel[s] = SEL_ZERO;
+        io.S[s] = S[s];
+        io.tmp0[s] = tmp0(s);
+        io.tmp1[s] = tmp1(s);
+      }
+      if (sure) {
+        io.Ub[2] = U[0];
+        io.a2_sel[2] = SEL_ONE;
+        io.Ub[4] = U[1];
+        io.a2_sel[4] = SEL_ONE;
+      }
+      if (J >= 2) {
+        tm.begin(ST_SYN_DEEP, st);
+        RC(dwt_synthesis(dwt, io, dp, st, 2, J));
+        tm.end(st);
+      }
+      tm.begin(ST_SYN_L1, st);
+      RC(dwt_synthesis(dwt, io, dp, st, 1, 1));
+      tm.end(st);
+    }
+    // 3. primal step and its derivatives
+    {
+      PrimalIO<T> io{};
+      io.ntraj = sure ? 2 : 1;
+      io.nderiv = sure ? 2 : 0;
+      const int sets[2][3] = {{0, 2, 3}, {1, 4, 5}};
+      for (int t = 0; t < io.ntraj; ++t) {
+        for (int d = 0; d <= io.nderiv; ++d) {
+          const int s = sets[t][d];
+          io.x[t][d] = X[s];
+          io.g[t][d] = G[s];
+          io.s[t][d] = S[s];
+          io.t[t][d] = Tt[s];
+          io.xt[t][d] = Xt[s];
+        }
+        io.hty[t] = t == 0 ? HTy : HTybar;
+      }
+      tm.begin(ST_PRIMAL, st);
+      RC(primal_step(io, LN, dp, st));
+      tm.end(st);
+    }
+    // 4. spatial analysis + dual update
+    {
+      AnalysisIO<T> io{};
+      io.role = ROLE_PRIMAL;
+      io.nsets = sure ? 2 : 1;
+      io.beta = beta;
+      for (int s = 0; s < io.nsets; ++s) {
+        io.xt_a[s] = Xt[s];
+        io.x_a[s] = X[s];
+        io.c1_sel[s] = SEL_MU;
+        io.c2_sel[s] = SEL_ZERO;
+        io.U[s] = U[s];
+        io.mask[s] = sure ? maskU[s] : nullptr;
+        io.tmp0[s] = tmp0(s);
+        io.tmp1[s] = tmp1(s);
+      }
+      tm.begin(ST_AN_L1_PRIMAL, st);
+      RC(dwt_analysis(dwt, io, dp, st, 1, 1));
+      tm.end(st);
+      if (J >= 2) {
+        tm.begin(ST_AN_DEEP_PRIMAL, st);
+        RC(dwt_analysis(dwt, io, dp, st, 2, J));
+        tm.end(st);
+      }
+      if (sure) {
+        AnalysisIO<T> d{};
+        d.role = ROLE_DERIV;
+        d.nsets = 4;
+        d.beta = beta;
+        for (int i = 0; i < 4; ++i) {
+          const int s = 2 + i, prim = i < 2 ? 0 : 1;
+          const bool is_mu = (i % 2) == 0;
+          d.xt_a[i] = Xt[s];
+          d.x_a[i] = X[s];
+          d.c1_sel[i] = SEL_MU;
+          d.xt_b[i] = is_mu ? Xt[prim] : nullptr;
+          d.x_b[i] = is_mu ? X[prim] : nullptr;
+          d.c2_sel[i] = is_mu ? SEL_ONE : SEL_ZERO;
+          d.U[i] = U[s];
+          d.mask[i] = maskU[prim];
+          d.tmp0[i] = tmp0(s);
+          d.tmp1[i] = tmp1(s);
+        }
+        tm.begin(ST_AN_L1_DERIV, st);
+        RC(dwt_analysis(dwt, d, dp, st, 1, 1));
+        tm.end(st);
+        if (J >= 2) {
+          tm.begin(ST_AN_DEEP_DERIV, st);
+          RC(dwt_analysis(dwt, d, dp, st, 2, J));
+          tm.end(st);
+        }
+      }
+    }
+    // 5. spectral DCT + dual update + adjoint
+    {
+      DctIO<T> io{};
+      io.role = ROLE_PRIMAL;
+      io.nsets = sure ? 2 : 1;
+      io.alpha = alpha;
+      for (int s = 0; s < io.nsets; ++s) {
+        io.xt_a[s] = Xt[s];
+        io.x_a[s] = X[s];
+        io.c1_sel[s] = SEL_GAMMA;
+        io.c2_sel[s] = SEL_ZERO;
+        io.V[s] = V[s];
+        io.Vb[s] = nullptr;
+        io.d1_sel[s] = SEL_GAMMA;
+        io.d2_sel[s] = SEL_ZERO;
+        io.Tout[s] = Tt[s];
+        io.mask[s] = sure ? maskV[s] : nullptr;
+      }
+      tm.begin(ST_DCT_PRIMAL, st);
+      RC(dct_update(dct, io, dp, st));
+      tm.end(st);
+      if (sure) {
+        DctIO<T> d{};
+        d.role = ROLE_DERIV;
+        d.nsets = 4;
+        d.alpha = alpha;
+        for (int i = 0; i < 4; ++i) {
+          const int s = 2 + i, prim = i < 2 ? 0 : 1;
+          const bool is_ga = (i % 2) == 1;
+          d.xt_a[i] = Xt[s];
+          d.x_a[i] = X[s];
+          d.c1_sel[i] = SEL_GAMMA;
+          d.xt_b[i] = is_ga ? Xt[prim] : nullptr;
+          d.x_b[i] = is_ga ? X[prim] : nullptr;
+          d.c2_sel[i] = is_ga ? SEL_ONE : SEL_ZERO;
+          d.V[i] = V[s];
+          d.Vb[i] = is_ga ? V[prim] : nullptr;
+          d.d1_sel[i] = SEL_GAMMA;
+          d.d2_sel[i] = is_ga ? SEL_ONE : SEL_ZERO;
+          d.Tout[i] = Tt[s];
+          d.mask[i] = maskV[prim];
+        }
+        tm.begin(ST_DCT_DERIV, st);
+        RC(dct_update(dct, d, dp, st));
+        tm.end(st);
+      }
+    }
+    // 6. X <- X~
+    for (int s = 0; s < nsets; ++s) std::swap(X[s], Xt[s]);
+    ++k_done;
+    if (sure && k_done % cfg.delta_period == 0) {
+      tm.begin(ST_WINDOW, st);
+      RC(window_end());
+      tm.end(st);
+    }
+    return 0;
+  }
+
+  // ADA-PT update after Delta completed iterations (Alg. 5, eq. `adaptgrad`)
+  int window_end() {
+    const int q = n_upd++;
+    // H^T H X^(k) of the Y trajectory, with ||Y - H X||^2 on the way
+    const int nres = fft_res_blocks(n, L, sizeof(T));
+    {
+      const int s0 = 0;
+      const T* in = X[0];
+      T* out = G[0];
+      RC(chain(&in, &out, &s0, 1, 2, Y, partials));
+      RC(reduce_to_slot(partials, nres, dp, SLOT_RES2, st));
+    }
+    const int nb = dot_blocks();
+    RC(dot_partials<T>(G[0], HTy, X[2], LN, partials, nb, st));
+    RC(reduce_to_slot(partials, nb, dp, SLOT_GX_MU, st));
+    RC(dot_partials<T>(G[0], HTy, X[3], LN, partials, nb, st));
+    RC(reduce_to_slot(partials, nb, dp, SLOT_GX_GA, st));
+    RC(dot_partials<T>(X[4], X[2], HTd, LN, partials, nb, st));
+    RC(reduce_to_slot(partials, nb, dp, SLOT_FD_MU, st));
+    RC(dot_partials<T>(X[5], X[3], HTd, LN, partials, nb, st));
+    RC(reduce_to_slot(partials, nb, dp, SLOT_FD_GA, st));
+    RC(dot_partials<T>(X[1], X[0], HTd, LN, partials, nb, st));
+    RC(reduce_to_slot(partials, nb, dp, SLOT_FD_X, st));
+    double* row = q < max_hist ? hist + (size_t)q * kHistCols : nullptr;
+    RC(theta_update(dp, row, k_done, (long long)LN, 1, st));
+    if (cfg.deriv_reset) {
+      for (int s = 2; s < 6; ++s) {
+        RC(fill_zero(X[s], LN, st));
+        RC(fill_zero(U[s], LN * P, st));
+        RC(fill_zero(V[s], LN, st));
+        RC(fill_zero(Tt[s], LN, st));
+      }
+    }
+    return 0;
+  }
+
+  int run(int iters) override {
+    if (!have_problem) return MUFFIN_E_STATE;
+    if (iters < 0) return MUFFIN_E_INVAL;
+    for (int i = 0; i < iters; ++i) {
+      RC(iterate());
+      if (tm.on && tm.used > 4096) RC(tm.collect(st));
+    }
+    return 0;
+  }
+
+  int report(muffin_report* r) override {
+    DevParams h{};
+    MUFFIN_HIP_CHECK(hipMemcpyAsync(&h, dp, sizeof(h), hipMemcpyDeviceToHost, st));
+    MUFFIN_HIP_CHECK(hipStreamSynchronize(st));
+    std::memset(r, 0, sizeof(*r));
+    r->iters_done = k_done;
+    r->theta_updates = h.n_updates;
+    r->mu = h.mu;
+    r->gamma = h.gamma;
+    r->tau = h.tau;
+    r->beta_H = h.beta_H;
+    if (h.n_updates > 0) {
+      const int q = std::min(h.n_updates, max_hist) - 1;
+      double row[kHistCols];
+      MUFFIN_HIP_CHECK(hipMemcpy(row, hist + (size_t)q * kHistCols, sizeof(row),
+                                 hipMemcpyDeviceToHost));
+      r->sugar_mu = row[4];
+      r->sugar_gamma = row[5];
+      r->psure = row[6];
+      r->res2 = row[7];
+    }
+    return 0;
+  }
+
+  T* state_ptr(int which, int set, size_t* count) {
+    if (set < 0 || set >= nsets) return nullptr;
+    *count = which == 1 ? LN * P : LN;
+    switch (which) {
+      case 0: return X[set];
+      case 1: return U[set];
+      case 2: return V[set];
+      case 3: return Tt[set];
+      default: return nullptr;
+    }
+  }
+
+  int get_state(int which, int set, void* out) override {
+    size_t cnt = 0;
+    T* p = state_ptr(which, set, &cnt);
+    if (!p || !out) return MUFFIN_E_INVAL;
+    MUFFIN_HIP_CHECK(hipMemcpyAsync(out, p, sizeof(T) * cnt, hipMemcpyDeviceToDevice, st));
+    return 0;
+  }
+
+  int set_state(int which, int set, const void* in) override {
+    size_t cnt = 0;
+    T* p = state_ptr(which, set, &cnt);
+    if (!p || !in) return MUFFIN_E_INVAL;
+    MUFFIN_HIP_CHECK(hipMemcpyAsync(p, in, sizeof(T) * cnt, hipMemcpyDeviceToDevice, st));
+    return 0;
+  }
+
+  int history(double* rows, int max_rows) override {
+    DevParams h{};
+    MUFFIN_HIP_CHECK(hipMemcpyAsync(&h, dp, sizeof(h), hipMemcpyDeviceToHost, st));
+    MUFFIN_HIP_CHECK(hipStreamSynchronize(st));
+    const int avail = std::min(h.n_updates, max_hist);
+    const int cnt = std::min(avail, std::max(0, max_rows));
+    if (rows && cnt > 0)
+      MUFFIN_HIP_CHECK(hipMemcpy(rows, hist, sizeof(double) * kHistCols * cnt,
+                                 hipMemcpyDeviceToHost));
+    return avail;
+  }
+
+  int weights(double* a, double* b) override {
+    if (!have_problem) return MUFFIN_E_STATE;
+    MUFFIN_HIP_CHECK(hipStreamSynchronize(st));
+    if (a) MUFFIN_HIP_CHECK(hipMemcpy(a, alpha, sizeof(double) * N, hipMemcpyDeviceToHost));
+    if (b) MUFFIN_HIP_CHECK(hipMemcpy(b, beta, sizeof(double) * L, hipMemcpyDeviceToHost));
+    return 0;
+  }
+
+  int op(int kind, const void* in, void* out) override {
+    if (!in || !out) return MUFFIN_E_INVAL;
+    const T* x = static_cast<const T*>(in);
+    T* y = static_cast<T*>(out);
+    switch (kind) {
+      case 0:
+      case 1:
+      case 2:
+        if (!have_problem) return MUFFIN_E_STATE;
+        return chain1(x, y, kind);
+      case 3: {
+        AnalysisIO<T> io{};
+        io.nsets = 1;
+        io.xt_a[0] = x;
+        io.x_a[0] = x;
+        io.c1_sel[0] = SEL_ONE;
+        io.c2_sel[0] = SEL_ZERO;
+        io.U[0] = y;
+        io.tmp0[0] = tmp0(0);
+        io.tmp1[0] = tmp1(0);
+        io.pure = 1;
+        io.pure_scale = 1.0 / std::sqrt((double)P);
+        return dwt_analysis(dwt, io, nullptr, st);
+      }
+      case 4: {
+        SynthesisIO<T> io{};
+        io.nsets = 1;
+        io.Ua[0] = x;
+        io.S[0] = y;
+        io.tmp0[0] = tmp0(0);
+        io.tmp1[0] = tmp1(0);
+        io.pure = 1;
+        return dwt_synthesis(dwt, io, nullptr, st);
+      }
+      case 5:
+      case 6: {
+        DctIO<T> io{};
+        io.nsets = 1;
+        io.x_a[0] = x;
+        io.V[0] = y;
+        io.pure = kind == 5 ? 1 : 2;
+        return dct_update(dct, io, nullptr, st);
+      }
+      default:
+        return MUFFIN_E_INVAL;
+    }
+  }
+};
+
+}  // namespace
+
+struct muffin_handle {
+  muffin_config cfg;
+  hipStream_t stream;
+  std::unique_ptr<ImplBase> impl;
+};
+
+extern "C" {
+
+int muffin_default_config(muffin_config* c, int32_t n, int32_t L) {
+  if (!c) return MUFFIN_E_INVAL;
+  std::memset(c, 0, sizeof(*c));
+  c->n = n;
+  c->L = L;
+  c->n_bases = 8;
+  int J = 3;
+  while (J > 1 && (n >> J) < 1) --J;
+  c->levels = J;
+  c->mode = MUFFIN_F64;
+  c->mu = 1.0;
+  c->gamma = 1.0;
+  c->sigma = 10.0;
+  c->tau = 0.0;
+  c->tau_rule = MUFFIN_TAU_OPNORM;
+  c->rho = 0.99;
+  c->eps_w = 1e-6;
+  c->sure = 0;
+  c->delta_period = 10;
+  c->eta_mu = 1e-3;
+  c->eta_gamma = 1e-3;
+  c->eps_fd = 0.0;
+  c->sigma_w = 0.0;
+  c->deriv_reset = 1;
+  c->pi_iters = 200;
+  c->pi_tol = 1e-10;
+  return MUFFIN_OK;
+}
+
+size_t muffin_workspace_bytes(const muffin_config* c) {
+  if (validate(c) != MUFFIN_OK) return 0;
+  return workspace_bytes_of(c);
+}
+
+int muffin_create(muffin_handle** h, const muffin_config* cfg, void* stream) {
+  if (!h) return MUFFIN_E_INVAL;
+  *h = nullptr;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  std::unique_ptr<muffin_handle> hh(new (std::nothrow) muffin_handle());
+  if (!hh) return MUFFIN_E_NOMEM;
+  hh->cfg = *cfg;
+  hh->stream = static_cast<hipStream_t>(stream);
+  if (cfg->mode == MUFFIN_F64)
+    hh->impl.reset(new (std::nothrow) Impl<double>(*cfg, hh->stream));
+  else
+    hh->impl.reset(new (std::nothrow) Impl<float>(*cfg, hh->stream));
+  if (!hh->impl) return MUFFIN_E_NOMEM;
+  rc = hh->impl->init();
+  if (rc) return rc;
+  *h = hh.release();
+  return MUFFIN_OK;
+}
+
+int muffin_set_problem(muffin_handle* h, const void* dirty, const void* psf, const double* alpha,
+                       const double* beta, const void* delta) {
+  if (!h) return MUFFIN_E_INVAL;
+  return h->impl->set_problem(dirty, psf, alpha, beta, delta);
+}
+
+int muffin_run(muffin_handle* h, int32_t iters, muffin_report* report) {
+  if (!h) return MUFFIN_E_INVAL;
+  int rc = h->impl->run(iters);
+  if (rc) return rc;
+  if (report) return h->impl->report(report);
+  return MUFFIN_OK;
+}
+
+int muffin_get_sky(muffin_handle* h, void* x_out) {
+  if (!h) return MUFFIN_E_INVAL;
+  return h->impl->get_state(0, 0, x_out);
+}
+
+int muffin_get_state(muffin_handle* h, int32_t which, int32_t set, void* out) {
+  if (!h) return MUFFIN_E_INVAL;
+  return h->impl->get_state(which, set, out);
+}
+
+int muffin_set_state(muffin_handle* h, int32_t which, int32_t set, const void* in) {
+  if (!h) return MUFFIN_E_INVAL;
+  return h->impl->set_state(which, set, in);
+}
+
+int muffin_get_history(muffin_handle* h, double* rows, int32_t max_rows) {
+  if (!h) return MUFFIN_E_INVAL;
+  return h->impl->history(rows, max_rows);
+}
+
+int muffin_get_weights(muffin_handle* h, double* alpha, double* beta) {
+  if (!h) return MUFFIN_E_INVAL;
+  return h->impl->weights(alpha, beta);
+}
+
+int muffin_get_report(muffin_handle* h, muffin_report* report) {
+  if (!h || !report) return MUFFIN_E_INVAL;
+  return h->impl->report(report);
+}
+
+int muffin_destroy(muffin_handle* h) {
+  if (!h) return MUFFIN_E_INVAL;
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+  return MUFFIN_OK;
+}
+
+int muffin_set_timing(muffin_handle* h, int32_t on) {
+  if (!h) return MUFFIN_E_INVAL;
+  Timer& t = h->impl->timer();
+  RC(t.collect(h->impl->stream()));
+  t.reset();
+  t.on = on != 0;
+  return MUFFIN_OK;
+}
+
+int muffin_get_timing(muffin_handle* h, double* ms, int64_t* calls, int32_t max_stages) {
+  if (!h) return MUFFIN_E_INVAL;
+  Timer& t = h->impl->timer();
+  RC(t.collect(h->impl->stream()));
+  for (int i = 0; i < ST_COUNT && i < max_stages; ++i) {
+    if (ms) ms[i] = t.ms[i];
+    if (calls) calls[i] = t.calls[i];
+  }
+  return ST_COUNT;
+}
+
+const char* muffin_stage_name(int32_t stage) {
+  return (stage >= 0 && stage < ST_COUNT) ? kStageNames[stage] : "";
+}
+
+const char* muffin_strerror(int code) {
+  switch (code) {
+    case MUFFIN_OK: return "ok";
+    case MUFFIN_E_INVAL: return "invalid argument or configuration";
+    case MUFFIN_E_SHAPE: return "unsupported size";
+    case MUFFIN_E_NOMEM: return "device allocation failed";
+    case MUFFIN_E_NONFINITE: return "non-finite value in an input cube";
+    case MUFFIN_E_HIP: return "HIP runtime error";
+    case MUFFIN_E_STATE: return "call out of order";
+    default: return "unknown error";
+  }
+}
+
+int muffin_op_H(muffin_handle* h, const void* in, void* out) {
+  return h ? h->impl->op(0, in, out) : MUFFIN_E_INVAL;
+}
+int muffin_op_HT(muffin_handle* h, const void* in, void* out) {
+  return h ? h->impl->op(1, in, out) : MUFFIN_E_INVAL;
+}
+int muffin_op_HTH(muffin_handle* h, const void* in, void* out) {
+  return h ? h->impl->op(2, in, out) : MUFFIN_E_INVAL;
+}
+int muffin_op_Ws(muffin_handle* h, const void* in, void* out) {
+  return h ? h->impl->op(3, in, out) : MUFFIN_E_INVAL;
+}
+int muffin_op_WsT(muffin_handle* h, const void* in, void* out) {
+  return h ? h->impl->op(4, in, out) : MUFFIN_E_INVAL;
+}
+int muffin_op_dct(muffin_handle* h, const void* in, void* out) {
+  return h ? h->impl->op(5, in, out) : MUFFIN_E_INVAL;
+}
+int muffin_op_idct(muffin_handle* h, const void* in, void* out) {
+  return h ? h->impl->op(6, in, out) : MUFFIN_E_INVAL;
+}
+
+}  // extern "C"

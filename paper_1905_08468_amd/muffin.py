@@ -1,0 +1,271 @@
+"""ctypes binding of libmuffin (include/muffin.h).
+
+Argument marshalling only: every step of the method runs in the HIP
+library.  Tensors are torch device tensors of the handle's working dtype;
+their data pointers and the current torch stream are passed to the C ABI.
+If the library has not been built this module raises on import -- there is
+no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmuffin.so")
+
+F64, F32, F32_BF16DCT = 0, 1, 2
+TAU_OPNORM, TAU_PAPER_SUM = 0, 1
+
+ERRORS = {0: "ok", -1: "E_INVAL", -2: "E_SHAPE", -3: "E_NOMEM", -4: "E_NONFINITE",
+          -5: "E_HIP", -6: "E_STATE"}
+
+
+class MuffinError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {ERRORS.get(code, code)} ({_lib.muffin_strerror(code).decode()})")
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("L", C.c_int32), ("n_bases", C.c_int32), ("levels", C.c_int32),
+        ("mode", C.c_int32),
+        ("mu", C.c_double), ("gamma", C.c_double), ("sigma", C.c_double), ("tau", C.c_double),
+        ("tau_rule", C.c_int32), ("rho", C.c_double), ("eps_w", C.c_double),
+        ("sure", C.c_int32), ("delta_period", C.c_int32),
+        ("eta_mu", C.c_double), ("eta_gamma", C.c_double),
+        ("eps_fd", C.c_double), ("sigma_w", C.c_double),
+        ("deriv_reset", C.c_int32), ("pi_iters", C.c_int32), ("pi_tol", C.c_double),
+    ]
+
+
+class Report(C.Structure):
+    _fields_ = [
+        ("iters_done", C.c_int32), ("theta_updates", C.c_int32),
+        ("mu", C.c_double), ("gamma", C.c_double), ("tau", C.c_double),
+        ("beta_H", C.c_double), ("psure", C.c_double), ("sugar_mu", C.c_double),
+        ("sugar_gamma", C.c_double), ("res2", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = [
+    "muffin_default_config", "muffin_workspace_bytes", "muffin_create", "muffin_set_problem",
+    "muffin_run", "muffin_get_sky", "muffin_get_state", "muffin_set_state",
+    "muffin_get_history", "muffin_get_weights", "muffin_get_report", "muffin_destroy",
+    "muffin_strerror", "muffin_op_H", "muffin_op_HT", "muffin_op_HTH", "muffin_op_Ws",
+    "muffin_op_WsT", "muffin_op_dct", "muffin_op_idct",
+    "muffin_set_timing", "muffin_get_timing", "muffin_stage_name",
+]
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
+                          "(python paper_1905_08468_amd/build.py)")
+    lib = C.CDLL(path)
+    vp, i32, dp = C.c_void_p, C.c_int32, C.POINTER(C.c_double)
+    cfgp = C.POINTER(Config)
+    sig = {
+        "muffin_default_config": ([cfgp, i32, i32], C.c_int),
+        "muffin_workspace_bytes": ([cfgp], C.c_size_t),
+        "muffin_create": ([C.POINTER(vp), cfgp, vp], C.c_int),
+        "muffin_set_problem": ([vp, vp, vp, dp, dp, vp], C.c_int),
+        "muffin_run": ([vp, i32, C.POINTER(Report)], C.c_int),
+        "muffin_get_sky": ([vp, vp], C.c_int),
+        "muffin_get_state": ([vp, i32, i32, vp], C.c_int),
+        "muffin_set_state": ([vp, i32, i32, vp], C.c_int),
+        "muffin_get_history": ([vp, dp, i32], C.c_int),
+        "muffin_get_weights": ([vp, dp, dp], C.c_int),
+        "muffin_get_report": ([vp, C.POINTER(Report)], C.c_int),
+        "muffin_destroy": ([vp], C.c_int),
+        "muffin_strerror": ([C.c_int], C.c_char_p),
+        "muffin_set_timing": ([vp, i32], C.c_int),
+        "muffin_get_timing": ([vp, dp, C.POINTER(C.c_int64), i32], C.c_int),
+        "muffin_stage_name": ([i32], C.c_char_p),
+    }
+    for name in ["muffin_op_H", "muffin_op_HT", "muffin_op_HTH", "muffin_op_Ws",
+                 "muffin_op_WsT", "muffin_op_dct", "muffin_op_idct"]:
+        sig[name] = ([vp, vp, vp], C.c_int)
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = load_library()
+
+
+def default_config(n: int, L: int, **over) -> Config:
+    c = Config()
+    rc = _lib.muffin_default_config(C.byref(c), n, L)
+    if rc:
+        raise MuffinError(rc, "muffin_default_config")
+    for k, v in over.items():
+        if not hasattr(c, k):
+            raise KeyError(k)
+        setattr(c, k, v)
+    return c
+
+
+def workspace_bytes(cfg: Config) -> int:
+    return int(_lib.muffin_workspace_bytes(C.byref(cfg)))
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dptr(a):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Muffin:
+    """One solve on the current CUDA/HIP device and torch stream."""
+
+    def __init__(self, cfg: Config, stream=None):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        self.dtype = torch.float64 if cfg.mode == F64 else torch.float32
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        h = C.c_void_p()
+        rc = _lib.muffin_create(C.byref(h), C.byref(cfg), C.c_void_p(s.cuda_stream))
+        if rc:
+            raise MuffinError(rc, "muffin_create")
+        self.h = h
+
+    def _check(self, t, shape, name):
+        if tuple(t.shape) != tuple(shape) or t.dtype != self.dtype or not t.is_cuda \
+                or not t.is_contiguous():
+            raise ValueError(f"{name}: expected contiguous {self.dtype} cuda tensor {shape}, "
+                             f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+
+    @property
+    def cube(self):
+        return (self.cfg.L, self.cfg.n, self.cfg.n)
+
+    def set_problem(self, dirty, psf, alpha=None, beta=None, delta=None):
+        n, L = self.cfg.n, self.cfg.L
+        self._check(dirty, (L, n, n), "dirty")
+        self._check(psf, (L, 2 * n, 2 * n), "psf")
+        if delta is not None:
+            self._check(delta, (L, n, n), "delta")
+        a = _dptr(alpha)
+        b = _dptr(beta)
+        if a is not None and a[0].size != n * n:
+            raise ValueError("alpha must have n*n entries")
+        if b is not None and b[0].size != L:
+            raise ValueError("beta must have L entries")
+        self._keep = (dirty, psf, delta)
+        rc = _lib.muffin_set_problem(self.h, _ptr(dirty), _ptr(psf),
+                                     a[1] if a else None, b[1] if b else None, _ptr(delta))
+        if rc:
+            raise MuffinError(rc, "muffin_set_problem")
+
+    def run(self, iters: int, report: bool = True):
+        rep = Report()
+        rc = _lib.muffin_run(self.h, int(iters), C.byref(rep) if report else None)
+        if rc:
+            raise MuffinError(rc, "muffin_run")
+        return rep.as_dict() if report else None
+
+    def report(self):
+        rep = Report()
+        rc = _lib.muffin_get_report(self.h, C.byref(rep))
+        if rc:
+            raise MuffinError(rc, "muffin_get_report")
+        return rep.as_dict()
+
+    def sky(self):
+        out = self.torch.empty(self.cube, dtype=self.dtype, device=self.device)
+        rc = _lib.muffin_get_sky(self.h, _ptr(out))
+        if rc:
+            raise MuffinError(rc, "muffin_get_sky")
+        return out
+
+    def _state_shape(self, which):
+        n, L, P = self.cfg.n, self.cfg.L, self.cfg.n_bases
+        return (L, P, n, n) if which == 1 else (L, n, n)
+
+    def get_state(self, which: int, set_: int = 0):
+        out = self.torch.empty(self._state_shape(which), dtype=self.dtype, device=self.device)
+        rc = _lib.muffin_get_state(self.h, which, set_, _ptr(out))
+        if rc:
+            raise MuffinError(rc, "muffin_get_state")
+        return out
+
+    def set_state(self, which: int, set_: int, t):
+        self._check(t, self._state_shape(which), "state")
+        rc = _lib.muffin_set_state(self.h, which, set_, _ptr(t))
+        if rc:
+            raise MuffinError(rc, "muffin_set_state")
+        self.torch.cuda.current_stream().synchronize()
+
+    def history(self):
+        cnt = _lib.muffin_get_history(self.h, None, 0)
+        if cnt < 0:
+            raise MuffinError(cnt, "muffin_get_history")
+        buf = np.zeros((max(cnt, 1), 8))
+        _lib.muffin_get_history(self.h, buf.ctypes.data_as(C.POINTER(C.c_double)), cnt)
+        return buf[:cnt]
+
+    def weights(self):
+        a = np.zeros(self.cfg.n * self.cfg.n)
+        b = np.zeros(self.cfg.L)
+        rc = _lib.muffin_get_weights(self.h, a.ctypes.data_as(C.POINTER(C.c_double)),
+                                     b.ctypes.data_as(C.POINTER(C.c_double)))
+        if rc:
+            raise MuffinError(rc, "muffin_get_weights")
+        return a, b
+
+    def op(self, name: str, x):
+        n, L, P = self.cfg.n, self.cfg.L, self.cfg.n_bases
+        fn = getattr(_lib, f"muffin_op_{name}")
+        if name == "WsT":
+            self._check(x, (L, P, n, n), "in")
+            out = self.torch.empty((L, n, n), dtype=self.dtype, device=self.device)
+        else:
+            self._check(x, (L, n, n), "in")
+            shape = (L, P, n, n) if name == "Ws" else (L, n, n)
+            out = self.torch.empty(shape, dtype=self.dtype, device=self.device)
+        rc = fn(self.h, _ptr(x), _ptr(out))
+        if rc:
+            raise MuffinError(rc, f"muffin_op_{name}")
+        return out
+
+    def set_timing(self, on: bool = True):
+        rc = _lib.muffin_set_timing(self.h, 1 if on else 0)
+        if rc:
+            raise MuffinError(rc, "muffin_set_timing")
+
+    def timing(self):
+        """{stage: (total_ms, calls)} of the device-timed stages."""
+        ms = (C.c_double * 32)()
+        calls = (C.c_int64 * 32)()
+        cnt = _lib.muffin_get_timing(self.h, ms, calls, 32)
+        if cnt < 0:
+            raise MuffinError(cnt, "muffin_get_timing")
+        return {_lib.muffin_stage_name(i).decode(): (ms[i], calls[i]) for i in range(cnt)}
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.muffin_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -103,25 +103,34 @@ def make_sky(rng: np.random.Generator, n: int, nu: np.ndarray, n_src: int,
     return sky
 
 
-def make_psf(rng: np.random.Generator, n: int, nu: np.ndarray,
-             n_base: int) -> np.ndarray:
-    L = nu.size
-    m = 2 * n
+def _uv_draws(rng: np.random.Generator, n: int, n_base: int):
     rad = 0.45 * n * np.sqrt(rng.uniform(0.0, 1.0, size=n_base))
     ang = rng.uniform(0.0, 2 * np.pi, size=n_base)
-    u0 = rad * np.cos(ang)
-    v0 = rad * np.sin(ang)
+    return rad * np.cos(ang), rad * np.sin(ang)
+
+
+def _uv_mask(u0, v0, n: int, scale: float) -> np.ndarray:
+    m = 2 * n
+    u = np.rint(u0 * scale).astype(np.int64)
+    v = np.rint(v0 * scale).astype(np.int64)
+    mask = np.zeros((m, m))
+    # centred grid: cell (v, u) sits at (n + v, n + u); Hermitian mirror
+    np.add.at(mask, ((n + v) % m, (n + u) % m), 1.0)
+    np.add.at(mask, ((n - v) % m, (n - u) % m), 1.0)
+    return mask
+
+
+def make_psf(rng: np.random.Generator, n: int, nu: np.ndarray, n_base: int,
+             device=None) -> np.ndarray:
+    L = nu.size
+    m = 2 * n
+    u0, v0 = _uv_draws(rng, n, n_base)
+    if device is not None:
+        return _torch_psf(lambda l: _uv_mask(u0, v0, n, nu[l] / nu[0]), L, n, device)
     psf = np.empty((L, m, m))
     for l in range(L):
-        s = nu[l] / nu[0]
-        u = np.rint(u0 * s).astype(np.int64)
-        v = np.rint(v0 * s).astype(np.int64)
-        mask = np.zeros((m, m))
-        # centred grid: cell (v, u) sits at (n + v, n + u); Hermitian mirror
-        np.add.at(mask, ((n + v) % m, (n + u) % m), 1.0)
-        np.add.at(mask, ((n - v) % m, (n - u) % m), 1.0)
-        beam = np.real(scipy.fft.ifft2(scipy.fft.ifftshift(mask),
-                                       workers=_workers()))
+        mask = _uv_mask(u0, v0, n, nu[l] / nu[0])
+        beam = np.real(scipy.fft.ifft2(scipy.fft.ifftshift(mask), workers=_workers()))
         beam = scipy.fft.fftshift(beam)
         psf[l] = beam / beam[n, n]
     return psf
@@ -140,13 +149,45 @@ def observe(psf: np.ndarray, sky: np.ndarray) -> np.ndarray:
     return out
 
 
+def _torch_psf(masks_fn, L, n, device):
+    """PSF cube from gridded uv masks with torch.fft on `device` (FP64)."""
+    import torch
+    m = 2 * n
+    out = np.empty((L, m, m))
+    for l in range(L):
+        mk = torch.from_numpy(masks_fn(l)).to(device)
+        beam = torch.fft.fftshift(torch.fft.ifft2(torch.fft.ifftshift(mk)).real)
+        out[l] = (beam / beam[n, n]).cpu().numpy()
+    return out
+
+
+def _torch_observe(psf: np.ndarray, sky: np.ndarray, device) -> np.ndarray:
+    """Same as observe(), linear convolution by a zero-padded 4n FFT with
+    torch.fft on `device` (FP64), a few bands at a time."""
+    import torch
+    L, n, _ = sky.shape
+    s = (4 * n, 4 * n)
+    out = np.empty_like(sky)
+    chunk = max(1, int(2 ** 31 // (16 * s[0] * s[1])))
+    for l0 in range(0, L, chunk):
+        l1 = min(L, l0 + chunk)
+        P = torch.fft.rfft2(torch.from_numpy(psf[l0:l1]).to(device), s=s)
+        X = torch.fft.rfft2(torch.from_numpy(sky[l0:l1]).to(device), s=s)
+        full = torch.fft.irfft2(P * X, s=s)
+        out[l0:l1] = full[:, n:2 * n, n:2 * n].cpu().numpy()
+        del P, X, full
+    return out
+
+
 def make_problem(n: int, L: int, n_src: int, n_blob: int, n_base: int,
-                 snr_db: float = 20.0, seed: int = 0) -> Problem:
+                 snr_db: float = 20.0, seed: int = 0, device=None) -> Problem:
+    """device: None for scipy on the host, or a torch device on which the PSF
+    synthesis and the observation convolution run (large cubes)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     nu = frequencies(L)
     sky = make_sky(rng, n, nu, n_src, n_blob)
-    psf = make_psf(rng, n, nu, n_base)
-    clean = observe(psf, sky)
+    psf = make_psf(rng, n, nu, n_base, device)
+    clean = observe(psf, sky) if device is None else _torch_observe(psf, sky, device)
     sigma_w = float(np.sqrt(np.sum(clean ** 2) / (clean.size * 10 ** (snr_db / 10))))
     noise = rng.standard_normal(size=sky.shape)
     dirty = clean + sigma_w * noise

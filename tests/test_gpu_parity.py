@@ -1,0 +1,291 @@
+"""GPU path vs the FP64 CPU oracle, through the C ABI.
+
+Inputs come from the seeded generator (synth); the oracle and the GPU get
+the same arrays.  Tolerances: relative L2 <= 1e-12 per FP64 operator,
+<= 1e-10 for FP64 iterations (accumulated rounding over hundreds of
+iterations), <= 1e-5 for the FP32 form.  Step sizes for the parity runs are
+fixed by the test from the PSF's l1 norm (a valid Lipschitz bound by Young's
+inequality), so neither side's power iteration enters the comparison.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import muffin as om
+from oracle import operators as op
+
+pytestmark = pytest.mark.gpu
+
+
+def _mm():
+    from paper_1905_08468_amd import muffin as mm
+    return mm
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def dev(a, dtype=None):
+    torch = _torch()
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to("cuda:0")
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+def rel(a, b):
+    d = np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel())
+    s = np.linalg.norm(np.asarray(b).ravel())
+    return d / s if s > 0 else d
+
+
+def safe_tau(psf, sigma, mu_l, gamma_n, rho=0.9):
+    """tau from an l1 bound on ||H_l|| (Young), usable by both sides."""
+    bound = max(np.abs(psf[l]).sum() for l in range(psf.shape[0])) ** 2
+    return rho / (bound / 2 + sigma * (np.max(mu_l) ** 2 + np.max(gamma_n) ** 2))
+
+
+def _problem(n, L, seed, counts=None):
+    kw = counts or synth.scaled_counts(max(n, 64))
+    return synth.make_problem(n, L, seed=seed, **kw)
+
+
+# ------------------------------------------------------------- operators --
+
+@pytest.mark.parametrize("n,L", [(8, 1), (16, 3), (64, 5), (128, 2), (256, 2)])
+def test_convolution_ops_f64(n, L):
+    mm = _mm()
+    rng = np.random.default_rng(n + L)
+    psf = rng.standard_normal((L, 2 * n, 2 * n))   # non-symmetric: complex K
+    x = rng.standard_normal((L, n, n))
+    K = op.psf_spectrum(psf)
+    cfg = mm.default_config(n, L, mode=mm.F64, tau=1.0, pi_iters=0)
+    h = mm.Muffin(cfg)
+    h.set_problem(dev(x), dev(psf), np.ones(n * n), np.ones(L))
+    assert rel(host(h.op("H", dev(x))), op.H(x, K)) < 1e-12
+    assert rel(host(h.op("HT", dev(x))), op.HT(x, K)) < 1e-12
+    assert rel(host(h.op("HTH", dev(x))), op.HT(op.H(x, K), K)) < 1e-12
+    # adjoint identity on the GPU results
+    y = rng.standard_normal((L, n, n))
+    lhs = np.sum(host(h.op("H", dev(x))) * y)
+    rhs = np.sum(x * host(h.op("HT", dev(y))))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs) + 1e-12
+    h.close()
+
+
+@pytest.mark.parametrize("n,L,P,J", [(8, 2, 8, 3), (16, 3, 8, 3), (64, 2, 8, 3), (64, 1, 3, 2),
+                                     (32, 2, 1, 1), (128, 1, 8, 4), (16, 1, 8, 4)])
+def test_wavelet_ops_f64(n, L, P, J):
+    mm = _mm()
+    rng = np.random.default_rng(7 * n + P)
+    x = rng.standard_normal((L, n, n))
+    u = rng.standard_normal((L, P, n, n))
+    W = op.SpatialDictionary(P, J)
+    cfg = mm.default_config(n, L, mode=mm.F64, n_bases=P, levels=J)
+    h = mm.Muffin(cfg)
+    assert rel(host(h.op("Ws", dev(x))), W.forward(x)) < 1e-12
+    assert rel(host(h.op("WsT", dev(u))), W.adjoint(u)) < 1e-12
+    h.close()
+
+
+@pytest.mark.parametrize("L", [1, 5, 16, 33, 64, 256])
+def test_dct_ops_f64(L):
+    mm = _mm()
+    n = 16
+    x = np.random.default_rng(L).standard_normal((L, n, n))
+    h = mm.Muffin(mm.default_config(n, L, mode=mm.F64))
+    assert rel(host(h.op("dct", dev(x))), op.Wl(x)) < 1e-12
+    assert rel(host(h.op("idct", dev(x))), op.WlT(x)) < 1e-12
+    h.close()
+
+
+def test_ops_f32():
+    mm = _mm()
+    torch = _torch()
+    n, L, P = 64, 8, 8
+    rng = np.random.default_rng(3)
+    prob = _problem(n, L, 3)
+    x = rng.standard_normal((L, n, n))
+    K = op.psf_spectrum(prob.psf)
+    h = mm.Muffin(mm.default_config(n, L, mode=mm.F32, tau=1.0, pi_iters=0))
+    h.set_problem(dev(prob.dirty, torch.float32), dev(prob.psf, torch.float32),
+                  np.ones(n * n), np.ones(L))
+    xf = dev(x, torch.float32)
+    x32 = host(xf)
+    assert rel(host(h.op("HTH", xf)), op.HT(op.H(x32, K), K)) < 2e-6
+    assert rel(host(h.op("Ws", xf)), op.SpatialDictionary(P, 3).forward(x32)) < 2e-6
+    assert rel(host(h.op("dct", xf)), op.Wl(x32)) < 2e-6
+    h.close()
+
+
+# ------------------------------------------------------------ iterations --
+
+def _config(mm, n, L, **kw):
+    return mm.default_config(n, L, **kw)
+
+
+def test_one_iteration_from_random_state_f64():
+    mm = _mm()
+    n, L, P, J = 32, 5, 8, 3
+    prob = _problem(n, L, 11)
+    alpha, beta = synth.random_weights(L, n, 11)
+    X, U, V, T = synth.random_state(L, n, P, 11, scale=float(np.abs(prob.dirty).mean()))
+    mu, gamma = 0.7, 0.3
+    pb = om.make_problem(prob.dirty, prob.psf, P=P, J=J, alpha=alpha, beta=beta)
+    tau = safe_tau(prob.psf, 10.0, mu * beta, gamma * alpha)
+    ref, _ = om.muffin_step(om.State(X, U, V, T), pb.Y, pb, mu, gamma, tau)
+    h = mm.Muffin(_config(mm, n, L, mode=mm.F64, mu=mu, gamma=gamma, tau=tau, pi_iters=0))
+    h.set_problem(dev(prob.dirty), dev(prob.psf), alpha, beta)
+    for which, arr in enumerate([X, U, V, T]):
+        h.set_state(which, 0, dev(arr))
+    h.run(1)
+    for which, arr in enumerate([ref.X, ref.U, ref.V, ref.T]):
+        assert rel(host(h.get_state(which, 0)), arr) < 1e-12, which
+    h.close()
+
+
+def test_c0_plain_f64_200_iterations():
+    """Plain FP64 MUFFIN, 64 x 64 x 8, mu = gamma = 1, 200 iterations."""
+    mm = _mm()
+    n, L = 64, 8
+    prob = synth.make_config("c0", seed=0)
+    alpha, beta = synth.random_weights(L, n, 0)
+    pb = om.make_problem(prob.dirty, prob.psf, P=8, J=3, alpha=alpha, beta=beta)
+    tau = safe_tau(prob.psf, 10.0, beta, alpha)
+    ref = om.run_muffin(pb, 1.0, 1.0, tau, 200)
+    h = mm.Muffin(_config(mm, n, L, mode=mm.F64, mu=1.0, gamma=1.0, tau=tau, pi_iters=0))
+    h.set_problem(dev(prob.dirty), dev(prob.psf), alpha, beta)
+    h.run(200)
+    x = host(h.sky())
+    assert rel(x, ref.X) < 1e-10
+    for which, arr in [(1, ref.U), (2, ref.V), (3, ref.T)]:
+        assert rel(host(h.get_state(which, 0)), arr) < 1e-10
+    h.close()
+
+
+@pytest.mark.parametrize("rule", ["opnorm", "sum"])
+def test_setup_weights_lipschitz_tau_f64(rule):
+    mm = _mm()
+    n, L = 32, 4
+    prob = _problem(n, L, 5)
+    pb = om.make_problem(prob.dirty, prob.psf, P=8, J=3)          # weight rule
+    bh = om.lipschitz(pb.K, n, iters=2000, tol=1e-14)
+    tau_ref = om.tau_rule(bh, 10.0, pb.mu_l(0.8), pb.gamma_n(0.6).ravel(), rule, 0.99)
+    cfg = _config(mm, n, L, mode=mm.F64, mu=0.8, gamma=0.6, pi_iters=2000, pi_tol=1e-14,
+                  tau_rule=mm.TAU_OPNORM if rule == "opnorm" else mm.TAU_PAPER_SUM)
+    h = mm.Muffin(cfg)
+    h.set_problem(dev(prob.dirty), dev(prob.psf))
+    a, b = h.weights()
+    assert rel(a, pb.alpha) < 1e-13 and rel(b, pb.beta) < 1e-13
+    rep = h.report()
+    assert abs(rep["beta_H"] - bh) <= 1e-8 * bh
+    assert abs(rep["tau"] - tau_ref) <= 1e-8 * tau_ref
+    h.close()
+
+
+def _adapt_case(mm, mode, n=32, L=6, iters=12, Delta=3, seed=21, reset=True):
+    prob = _problem(n, L, seed)
+    alpha, beta = synth.random_weights(L, n, seed)
+    mu0, ga0 = 0.5, 0.4
+    eps = 0.05 * prob.sigma_w
+    pb = om.make_problem(prob.dirty, prob.psf, P=8, J=3, alpha=alpha, beta=beta)
+    tau = safe_tau(prob.psf, 10.0, 2 * beta, 2 * alpha)
+    ref = om.run_adapt(pb, mu0, ga0, iters, prob.delta, eps, prob.sigma_w, Delta=Delta,
+                       eta_mu=2e-4, eta_gamma=2e-4, tau=tau, deriv_reset=reset)
+    cfg = _config(mm, n, L, mode=mode, mu=mu0, gamma=ga0, tau=tau, pi_iters=0, sure=1,
+                  delta_period=Delta, eps_fd=eps, sigma_w=prob.sigma_w, eta_mu=2e-4,
+                  eta_gamma=2e-4, deriv_reset=1 if reset else 0)
+    torch = _torch()
+    dt = torch.float64 if mode == mm.F64 else torch.float32
+    h = mm.Muffin(cfg)
+    h.set_problem(dev(prob.dirty, dt), dev(prob.psf, dt), alpha, beta, dev(prob.delta, dt))
+    rep = h.run(iters)
+    return h, rep, ref
+
+
+@pytest.mark.parametrize("reset", [True, False])
+def test_adapt_f64_matches_oracle(reset):
+    mm = _mm()
+    h, rep, ref = _adapt_case(mm, mm.F64, reset=reset)
+    assert rep["theta_updates"] == len(ref.history) == 4
+    hist = h.history()
+    for row, r in zip(hist, ref.history):
+        assert int(row[0]) == r["k"]
+        for j, key in [(4, "sugar_mu"), (5, "sugar_gamma"), (6, "psure")]:
+            assert abs(row[j] - r[key]) <= 1e-9 * max(1.0, abs(r[key])), key
+        assert abs(row[1] - r["mu"]) <= 1e-12 * max(1.0, abs(r["mu"]))
+        assert abs(row[2] - r["gamma"]) <= 1e-12 * max(1.0, abs(r["gamma"]))
+    assert rel(host(h.sky()), ref.X) < 1e-10
+    st = ref.states
+    for s, key in [(1, "Sb"), (2, "Dm"), (3, "Dg"), (4, "Dbm"), (5, "Dbg")]:
+        got = host(h.get_state(0, s))
+        exp = getattr(st[key], "X")
+        assert rel(got, exp) < 1e-9 or np.abs(exp).max() == 0, key
+    h.close()
+
+
+def test_c0_plain_f32_form():
+    mm = _mm()
+    torch = _torch()
+    n, L, iters = 64, 8, 50
+    prob = synth.make_config("c0", seed=1)
+    alpha, beta = synth.random_weights(L, n, 1)
+    pb = om.make_problem(prob.dirty, prob.psf, P=8, J=3, alpha=alpha, beta=beta)
+    tau = safe_tau(prob.psf, 10.0, beta, alpha)
+    ref = om.run_muffin(pb, 1.0, 1.0, tau, iters)
+    h = mm.Muffin(_config(mm, n, L, mode=mm.F32, mu=1.0, gamma=1.0, tau=tau, pi_iters=0))
+    h.set_problem(dev(prob.dirty, torch.float32), dev(prob.psf, torch.float32), alpha, beta)
+    h.run(iters)
+    err = rel(host(h.sky()), ref.X)
+    assert err < 1e-5, err
+    h.close()
+
+
+# ------------------------------------------------------------ edge cases --
+
+def test_single_band_and_zero_gamma():
+    mm = _mm()
+    n, L = 16, 1
+    prob = _problem(n, L, 4)
+    alpha, beta = synth.random_weights(L, n, 4)
+    pb = om.make_problem(prob.dirty, prob.psf, P=8, J=3, alpha=alpha, beta=beta)
+    tau = safe_tau(prob.psf, 10.0, beta, alpha)
+    for mu, gamma in [(0.5, 0.0), (0.0, 0.5), (0.0, 0.0)]:
+        ref = om.run_muffin(pb, mu, gamma, tau, 15)
+        h = mm.Muffin(_config(mm, n, L, mode=mm.F64, mu=mu, gamma=gamma, tau=tau, pi_iters=0))
+        h.set_problem(dev(prob.dirty), dev(prob.psf), alpha, beta)
+        h.run(15)
+        assert rel(host(h.sky()), ref.X) < 1e-11
+        h.close()
+
+
+def test_error_codes():
+    mm = _mm()
+    torch = _torch()
+    with pytest.raises(mm.MuffinError) as e:
+        mm.Muffin(mm.default_config(48, 4))
+    assert e.value.code == -2
+    with pytest.raises(mm.MuffinError) as e:
+        mm.Muffin(mm.default_config(16, 300))
+    assert e.value.code == -2
+    with pytest.raises(mm.MuffinError) as e:
+        mm.Muffin(mm.default_config(16, 4, sure=1))     # eps_fd, sigma_w missing
+    assert e.value.code == -1
+    h = mm.Muffin(mm.default_config(16, 2, tau=0.1, pi_iters=0))
+    with pytest.raises(mm.MuffinError) as e:
+        h.run(1)
+    assert e.value.code == -6
+    bad = torch.zeros((2, 16, 16), dtype=torch.float64, device="cuda:0")
+    bad[1, 3, 3] = float("nan")
+    psf = torch.zeros((2, 32, 32), dtype=torch.float64, device="cuda:0")
+    psf[:, 16, 16] = 1.0
+    with pytest.raises(mm.MuffinError) as e:
+        h.set_problem(bad, psf, np.ones(256), np.ones(2))
+    assert e.value.code == -4
+    h.close()
