@@ -26,14 +26,29 @@ if ROOT not in sys.path:
 METRIC = "primal-dual iters/s at 1024²×256 bands (FP32 vs FP64); served p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes of the level-1 spatial analysis + dual update, per voxel
-# per state set, in working-precision values: read x~ and x (2), read and
-# write the level-1 detail coefficients of the 8 bases (8 * 3/4 each way = 12),
-# write the level-1 low-pass bands (8 * 1/4 = 2); plus the 6 mask bytes of
-# the level-1 details (written by the primal sets, read by the derivative
-# sets).
-AN_L1_VALUES = 16
-AN_L1_MASK_BYTES = 6
+# Algorithmic traffic of the single-launch stages of one ADA-PT iteration,
+# per voxel (all state sets of the launch together): (working-precision
+# values, mask bytes).  Each input and output array is counted once.
+#   synthesis_l1: per set the 6 level-1 detail coefficients of the 8 bases
+#     (8 x 3/4) + the 2 coarse values (8 x 1/4) in, S out; the two d/dmu sets
+#     also read the primal's 6 detail coefficients.  6 sets: 4*9 + 2*15.
+#   analysis_l1_primal: per set x~, x in; 6 detail coefficients read and
+#     written; 2 low-pass values out; 6 mask bytes out.  2 sets.
+#   analysis_l1_deriv: as above with the mask read; the d/dmu sets read the
+#     primal's x~, x too.  4 sets: 2*(4+12+2) + 2*(2+12+2), 24 mask bytes.
+#   dct_primal: x~, x, V in; V, T out; 1 mask byte.  2 sets.
+#   dct_deriv: d/dmu: x~', x', V' in, V', T' out; d/dgamma also x~, x, and
+#     the new primal V.  4 sets: 2*5 + 2*8, 4 mask bytes.
+#   primal_step: per trajectory x, G, H^T y, S, T in, x~ out; each
+#     derivative x', G', S', T' in, x~' out.  2 trajectories: 2*(6+5+5).
+STAGE_TRAFFIC = {
+    "synthesis_l1": (66, 0),
+    "analysis_l1_primal": (32, 12),
+    "analysis_l1_deriv": (68, 24),
+    "dct_primal": (10, 2),
+    "dct_deriv": (26, 4),
+    "primal_step": (32, 0),
+}
 
 
 def log(msg):
@@ -45,11 +60,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", default="f32", choices=["f32", "bf16", "f64"])
+    ap.add_argument("--mode", default="bf16", choices=["f32", "bf16", "f64"])
     ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2"])
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (traffic-counter calibration)")
     return ap.parse_args()
 
 
@@ -137,20 +154,34 @@ def main():
     value = args.steps / el
     log(f"[bench] ADA-PT {args.mode}: {value:.3f} it/s ({1e3 * el / args.steps:.1f} ms/step)")
 
-    # dominant single kernel: level-1 analysis + dual update of the four
-    # derivative sets (one launch per step)
+    # per-stage achieved bandwidth from the live HIP-event timings; the
+    # roofline object reports the single-launch stage that takes longest
     es = 8 if mode == mm.F64 else 4
     tm = main_form["timing"]
-    ms_d, calls_d = tm["analysis_l1_deriv"]
-    bytes_launch = 4 * LN * (AN_L1_VALUES * es + AN_L1_MASK_BYTES)
-    avg_ms = ms_d / max(calls_d, 1)
+    stages = {}
+    for k, (ms, calls) in tm.items():
+        if not calls:
+            continue
+        entry = {"ms_per_step": round(ms / args.steps, 3), "calls": calls}
+        if k in STAGE_TRAFFIC:
+            vals, mbytes = STAGE_TRAFFIC[k]
+            nbytes = LN * (vals * es + mbytes)
+            avg = ms / calls
+            entry["algorithmic_GB"] = round(nbytes / 1e9, 2)
+            entry["GBps"] = round(nbytes / (avg * 1e-3) / 1e9, 1)
+        stages[k] = entry
+    dom = max((k for k in stages if k in STAGE_TRAFFIC), key=lambda k: tm[k][0])
+    vals, mbytes = STAGE_TRAFFIC[dom]
+    bytes_launch = LN * (vals * es + mbytes)
+    avg_ms = tm[dom][0] / tm[dom][1]
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    kernel_of = {"synthesis_l1": "dwt_sy level 1", "analysis_l1_primal": "dwt_an level 1",
+                 "analysis_l1_deriv": "dwt_an level 1", "dct_primal": "dct kernel",
+                 "dct_deriv": "dct kernel", "primal_step": "primal_kernel"}
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "dwt_an level 1 (analysis_l1_deriv)",
-                "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes": bytes_launch}
-    stages = {k: {"ms_per_step": round(v[0] / max(args.steps, 1), 3), "calls": v[1]}
-              for k, v in tm.items() if v[1]}
+                "kernel": f"{kernel_of[dom]} ({dom})", "avg_launch_ms": round(avg_ms, 4),
+                "algorithmic_bytes": bytes_launch}
 
     fp64 = None
     if not args.no_fp64:
@@ -163,6 +194,15 @@ def main():
             log(f"[bench] plain FP64: {fp64['value']} it/s")
         except Exception as e:  # report, do not hide
             fp64 = {"error": str(e)}
+    if args.calib:
+        # plain device copy of a known size, for scaling HBM traffic counters
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] calibration copy: 3 x 1 GiB device copies done")
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(prob)
@@ -179,11 +219,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f32": "f32", "bf16": "f32+bf16x3", "f64": "f64"}[args.mode],
+        "dtype": {"f32": "f32", "bf16": "f32+bf16", "f64": "f64"}[args.mode],
         "data": "synthetic",
         "config": {"workload": f"ADA-PT'ed MUFFIN iteration, {n}x{n} px x {L} bands, "
                                f"PSF {2 * n}x{2 * n}, P=8 Daubechies bases, J=3, DCT, "
-                               "Delta=10", "n": n, "bands": L, "form": args.mode},
+                               "Delta=10", "n": n, "bands": L,
+                   "form": {"f32": "FP32", "bf16": "FP32, DCT on bf16 MFMA hi+lo split",
+                            "f64": "FP64"}[args.mode]},
         "voxel_updates_per_s": round(value * LN, 1),
         "setup_s": round(main_form["setup_s"], 3),
         "theta": {"mu": main_form["report"]["mu"], "gamma": main_form["report"]["gamma"],

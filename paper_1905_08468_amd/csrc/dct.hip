@@ -9,13 +9,15 @@
 // DCT-II matrix.  With the band-major layout the DCT of all pixel spectra is
 // the product C (L x L) times Z (L x pixels): no transpose is needed.
 //
-// A block owns 64 (FP32) or 32 (FP64) pixels and all bands; each wave owns 16 pixel
-// columns and runs the two products on MFMA 16x16x4 tiles (FP64 or FP32),
-// the v update in registers between them.  The pixel tile lives in LDS and is
-// overwritten in place by the adjoint input.
+// A block owns 64 (FP32) or 32 (FP64) pixels and all bands, staged in LDS;
+// its 4 waves split the output rows and run the two products on MFMA
+// 16x16x4 tiles (FP64 or FP32) with the v update in registers between them.
+// The DCT matrix is stored in MFMA fragment order so every operand load is one
+// coalesced 64-lane read.
 #include "internal.hpp"
 
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 namespace muffin {
@@ -62,18 +64,22 @@ struct DctArgs {
   int d1_sel[kMaxSets], d2_sel[kMaxSets];
   T* Tout[kMaxSets];
   uint8_t* mask[kMaxSets];
-  const T* C;          // [Lp][Lp]
+  const T* Cf1;        // C in MFMA A-fragment order:   [kt][ks][lane]
+  const T* Cf2;        // C^T in MFMA A-fragment order: [lt][ks][lane]
   const double* alpha; // [N] or null
   const DevParams* dp;
   int L, Lp, N;
   int role, pure;
 };
 
-// Waves per block (16 pixel columns each): the LDS tile Lp x pixels stays at
-// 64 KB for L = 256 in both precisions.
-template <typename T>
-constexpr int dct_waves() { return sizeof(T) == 8 ? 2 : 4; }
+constexpr int kDctWaves = 4;
 constexpr int kDctMaxKt = 16;  // Lp <= 256
+constexpr int kDctKtPerWave = kDctMaxKt / kDctWaves;
+
+// Column groups (16 pixels each) per block: the LDS tile Lp x pixels is
+// 64 KB at L = 256 in both precisions.
+template <typename T>
+constexpr int dct_groups() { return sizeof(T) == 8 ? 2 : 4; }
 
 // MFMA 16x16x4 operand layout (64 lanes): A[i][k] with i = lane % 16,
 // k = lane / 16; B[k][j] with k = lane / 16, j = lane % 16.  Result r of a
@@ -83,17 +89,21 @@ template <typename T>
 __device__ __forceinline__ int out_row(int lk, int r) {
   return sizeof(T) == 8 ? lk + 4 * r : 4 * lk + r;
 }
+
+// Block = 4 waves x (16 * G) pixels.  Wave w owns the output row tiles
+// w, w + 4, w + 8, w + 12 for every pixel group, so each A fragment (read
+// coalesced from the fragment-ordered matrix) feeds G MFMAs.
 template <typename T>
-__global__ void __launch_bounds__(64 * dct_waves<T>()) dct_kernel(DctArgs<T> a) {
+__global__ void __launch_bounds__(64 * kDctWaves) dct_kernel(DctArgs<T> a) {
   typedef typename Acc4<T>::type acc_t;
-  constexpr int kDctWaves = dct_waves<T>();
-  constexpr int kDctPix = 16 * kDctWaves;
+  constexpr int G = dct_groups<T>();
+  constexpr int PIX = 16 * G;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* Z = reinterpret_cast<T*>(smem_raw);  // [Lp][kDctPix]
+  T* Z = reinterpret_cast<T*>(smem_raw);  // [Lp][PIX]
   const int set = blockIdx.y;
-  const int pix0 = blockIdx.x * kDctPix;
+  const int pix0 = blockIdx.x * PIX;
   const int L = a.L, Lp = a.Lp, N = a.N;
-  const int nkt = Lp >> 4;
+  const int nkt = Lp >> 4, nks = Lp >> 2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const DevParams* dp = a.dp;
@@ -106,8 +116,8 @@ __global__ void __launch_bounds__(64 * dct_waves<T>()) dct_kernel(DctArgs<T> a) 
     const T* xa = a.x_a[set];
     const T* tb = a.xt_b[set];
     const T* xb = a.x_b[set];
-    for (int t = threadIdx.x; t < Lp * kDctPix; t += 64 * kDctWaves) {
-      const int l = t / kDctPix, j = t - l * kDctPix;
+    for (int t = threadIdx.x; t < Lp * PIX; t += 64 * kDctWaves) {
+      const int l = t / PIX, j = t - l * PIX;
       const int pix = pix0 + j;
       T z = T(0);
       if (l < L && pix < N) {
@@ -124,23 +134,25 @@ __global__ void __launch_bounds__(64 * dct_waves<T>()) dct_kernel(DctArgs<T> a) 
   }
   __syncthreads();
 
-  const int jcol = wave * 16 + lr;       // this lane's pixel column in the tile
-  const int pix = pix0 + jcol;
-  const T* C = a.C;
-  acc_t acc[kDctMaxKt];
+  acc_t acc[kDctKtPerWave][G];
 #pragma unroll
-  for (int kt = 0; kt < kDctMaxKt; ++kt) acc[kt] = acc_t{0, 0, 0, 0};
+  for (int i = 0; i < kDctKtPerWave; ++i)
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc[i][g] = acc_t{0, 0, 0, 0};
 
-  // ---- product 1 (or the transposed product for the pure adjoint) ----
-  const bool trans1 = a.pure == 2;
-  for (int l0 = 0; l0 < Lp; l0 += 4) {
-    const T b = Z[(l0 + lk) * kDctPix + jcol];
+  // ---- product 1: C Z (pure == 2: C^T Z) ----
+  const T* A1 = a.pure == 2 ? a.Cf2 : a.Cf1;
+  for (int ks = 0; ks < nks; ++ks) {
+    T b[G];
 #pragma unroll
-    for (int kt = 0; kt < kDctMaxKt; ++kt) {
+    for (int g = 0; g < G; ++g) b[g] = Z[(4 * ks + lk) * PIX + 16 * g + lr];
+#pragma unroll
+    for (int i = 0; i < kDctKtPerWave; ++i) {
+      const int kt = wave + kDctWaves * i;
       if (kt < nkt) {
-        const int row = kt * 16 + lr, col = l0 + lk;
-        const T av = trans1 ? C[(size_t)col * Lp + row] : C[(size_t)row * Lp + col];
-        acc[kt] = mfma16(av, b, acc[kt]);
+        const T av = A1[((size_t)kt * nks + ks) * 64 + lane];
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[i][g] = mfma16(av, b[g], acc[i][g]);
       }
     }
   }
@@ -148,79 +160,341 @@ __global__ void __launch_bounds__(64 * dct_waves<T>()) dct_kernel(DctArgs<T> a) 
   if (a.pure) {
     T* out = a.V[set];
 #pragma unroll
-    for (int kt = 0; kt < kDctMaxKt; ++kt) {
+    for (int i = 0; i < kDctKtPerWave; ++i) {
+      const int kt = wave + kDctWaves * i;
       if (kt < nkt) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int k = kt * 16 + out_row<T>(lk, r);
-          if (k < L && pix < N) out[(size_t)k * N + pix] = acc[kt][r];
+        for (int g = 0; g < G; ++g) {
+          const int pix = pix0 + 16 * g + lr;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int k = kt * 16 + out_row<T>(lk, r);
+            if (k < L && pix < N) out[(size_t)k * N + pix] = acc[i][g][r];
+          }
         }
       }
     }
     return;
   }
 
-  // ---- v update, adjoint input into LDS (own columns only) ----
-  const double al = a.alpha ? (pix < N ? a.alpha[pix] : 0.0) : 1.0;
-  const T sa = T(dp->sigma * al);
+  // ---- v update; the adjoint input d1 v + d2 v_b replaces Z ----
+  __syncthreads();  // every wave is done reading Z
+  const T sg = T(dp->sigma);
   const T d1 = T(dct_coef(a.d1_sel[set], dp));
   const T d2 = T(dct_coef(a.d2_sel[set], dp));
   T* V = a.V[set];
   const T* Vb = a.Vb[set];
   uint8_t* M = a.mask[set];
+  T al[G];
 #pragma unroll
-  for (int kt = 0; kt < kDctMaxKt; ++kt) {
+  for (int g = 0; g < G; ++g) {
+    const int pix = pix0 + 16 * g + lr;
+    al[g] = a.alpha ? (pix < N ? T(a.alpha[pix]) : T(0)) : T(1);
+  }
+#pragma unroll
+  for (int i = 0; i < kDctKtPerWave; ++i) {
+    const int kt = wave + kDctWaves * i;
     if (kt < nkt) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = kt * 16 + out_row<T>(lk, r);
-        T bv = T(0);
-        if (k < L && pix < N) {
-          const size_t idx = (size_t)k * N + pix;
-          const T vt = V[idx] + sa * acc[kt][r];
-          T vn;
-          if (a.role == ROLE_PRIMAL) {
-            vn = vt < T(-1) ? T(-1) : (vt > T(1) ? T(1) : vt);
-            if (M) M[idx] = (vt >= T(-1) && vt <= T(1)) ? 1 : 0;
-          } else {
-            vn = M[idx] ? vt : T(0);
+      for (int g = 0; g < G; ++g) {
+        const int pix = pix0 + 16 * g + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = kt * 16 + out_row<T>(lk, r);
+          T bv = T(0);
+          if (k < L && pix < N) {
+            const size_t idx = (size_t)k * N + pix;
+            const T vt = V[idx] + sg * al[g] * acc[i][g][r];
+            T vn;
+            if (a.role == ROLE_PRIMAL) {
+              vn = vt < T(-1) ? T(-1) : (vt > T(1) ? T(1) : vt);
+              if (M) M[idx] = (vt >= T(-1) && vt <= T(1)) ? 1 : 0;
+            } else {
+              vn = M[idx] ? vt : T(0);
+            }
+            V[idx] = vn;
+            bv = d1 * vn;
+            if (Vb) bv += d2 * Vb[idx];
           }
-          V[idx] = vn;
-          bv = d1 * vn;
-          if (Vb) bv += d2 * Vb[idx];
+          Z[k * PIX + 16 * g + lr] = bv;
         }
-        Z[k * kDctPix + jcol] = bv;
       }
     }
   }
-  // LDS reads and writes of one wave execute in order, and each wave only
-  // touches its own 16 columns, so no block barrier is needed here.
+  __syncthreads();
 
   // ---- product 2: t = alpha C^T b ----
 #pragma unroll
-  for (int kt = 0; kt < kDctMaxKt; ++kt) acc[kt] = acc_t{0, 0, 0, 0};
-  for (int k0 = 0; k0 < Lp; k0 += 4) {
-    const T b = Z[(k0 + lk) * kDctPix + jcol];
+  for (int i = 0; i < kDctKtPerWave; ++i)
 #pragma unroll
-    for (int lt = 0; lt < kDctMaxKt; ++lt) {
+    for (int g = 0; g < G; ++g) acc[i][g] = acc_t{0, 0, 0, 0};
+  for (int ks = 0; ks < nks; ++ks) {
+    T b[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) b[g] = Z[(4 * ks + lk) * PIX + 16 * g + lr];
+#pragma unroll
+    for (int i = 0; i < kDctKtPerWave; ++i) {
+      const int lt = wave + kDctWaves * i;
       if (lt < nkt) {
-        const T av = C[(size_t)(k0 + lk) * Lp + lt * 16 + lr];  // C^T[l][k]
-        acc[lt] = mfma16(av, b, acc[lt]);
+        const T av = a.Cf2[((size_t)lt * nks + ks) * 64 + lane];
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[i][g] = mfma16(av, b[g], acc[i][g]);
       }
     }
   }
-  const T ta = T(al);
   T* To = a.Tout[set];
 #pragma unroll
-  for (int lt = 0; lt < kDctMaxKt; ++lt) {
+  for (int i = 0; i < kDctKtPerWave; ++i) {
+    const int lt = wave + kDctWaves * i;
     if (lt < nkt) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int l = lt * 16 + out_row<T>(lk, r);
-        if (l < L && pix < N) To[(size_t)l * N + pix] = ta * acc[lt][r];
+      for (int g = 0; g < G; ++g) {
+        const int pix = pix0 + 16 * g + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int l = lt * 16 + out_row<T>(lk, r);
+          if (l < L && pix < N) To[(size_t)l * N + pix] = al[g] * acc[i][g][r];
+        }
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 split form: every FP32 operand is x = hi + lo with hi = bf16(x) and
+// lo = bf16(x - hi); a product is hi_a hi_b + lo_a hi_b + hi_a lo_b (the
+// lo lo term, ~2^-18 relative, is dropped) on the 16x16x32 bf16 MFMA with
+// FP32 accumulation.  Operand layout of that instruction (measured on
+// gfx950): A[i][k] with i = lane % 16, k = 8 (lane / 16) + e for the lane's 8
+// values e; B[k][j] with k = 8 (lane / 16) + e, j = lane % 16; result r is
+// D[4 (lane / 16) + r][lane % 16].  The pixel tile is kept in LDS as
+// [pixel][band] (bands contiguous) so a lane's 8 B-operand values are one
+// 16-byte read.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+struct DctBfArgs {
+  const float* xt_a[kMaxSets];
+  const float* x_a[kMaxSets];
+  const float* xt_b[kMaxSets];
+  const float* x_b[kMaxSets];
+  int c1_sel[kMaxSets], c2_sel[kMaxSets];
+  float* V[kMaxSets];
+  const float* Vb[kMaxSets];
+  int d1_sel[kMaxSets], d2_sel[kMaxSets];
+  float* Tout[kMaxSets];
+  uint8_t* mask[kMaxSets];
+  const bf16x8* Ah1;  // C hi,   [kt][ks][lane]
+  const bf16x8* Al1;  // C lo
+  const bf16x8* Ah2;  // C^T hi
+  const bf16x8* Al2;  // C^T lo
+  const double* alpha;
+  const DevParams* dp;
+  int L, Lp, N;
+  int role, pure;
+};
+
+constexpr int kBfPix = 64;   // pixels per block (4 groups of 16)
+constexpr int kBfG = 4;
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+__global__ void __launch_bounds__(64 * kDctWaves) dct_bf16_kernel(DctBfArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int L = a.L, Lp = a.Lp, N = a.N;
+  const int LpS = Lp + 8;  // padded band stride of the [pixel][band] tile
+  __bf16* Zh = reinterpret_cast<__bf16*>(smem_raw);
+  __bf16* Zl = Zh + kBfPix * LpS;
+  const int set = blockIdx.y;
+  const int pix0 = blockIdx.x * kBfPix;
+  const int nkt = Lp >> 4, nks = Lp >> 5;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const DevParams* dp = a.dp;
+  {
+    const double c1 = a.pure ? 1.0 : dct_coef(a.c1_sel[set], dp);
+    const double c2 = a.pure ? 0.0 : dct_coef(a.c2_sel[set], dp);
+    const float* ta = a.xt_a[set];
+    const float* xa = a.x_a[set];
+    const float* tb = a.xt_b[set];
+    const float* xb = a.x_b[set];
+    for (int t = threadIdx.x; t < Lp * kBfPix; t += 64 * kDctWaves) {
+      const int l = t / kBfPix, j = t - l * kBfPix;
+      const int pix = pix0 + j;
+      float z = 0.f;
+      if (l < L && pix < N) {
+        const size_t idx = (size_t)l * N + pix;
+        if (a.pure) {
+          z = xa[idx];
+        } else {
+          z = float(c1) * (2.f * ta[idx] - xa[idx]);
+          if (xb) z += float(c2) * (2.f * tb[idx] - xb[idx]);
+        }
+      }
+      __bf16 h, lo;
+      split_bf16(z, h, lo);
+      Zh[j * LpS + l] = h;
+      Zl[j * LpS + l] = lo;
+    }
+  }
+  __syncthreads();
+  flt4 acc[kDctKtPerWave][kBfG];
+#pragma unroll
+  for (int i = 0; i < kDctKtPerWave; ++i)
+#pragma unroll
+    for (int g = 0; g < kBfG; ++g) acc[i][g] = flt4{0, 0, 0, 0};
+  const bf16x8* Ah = a.pure == 2 ? a.Ah2 : a.Ah1;
+  const bf16x8* Al = a.pure == 2 ? a.Al2 : a.Al1;
+  for (int ks = 0; ks < nks; ++ks) {
+    bf16x8 bh[kBfG], bl[kBfG];
+#pragma unroll
+    for (int g = 0; g < kBfG; ++g) {
+      const int o = (16 * g + lr) * LpS + 32 * ks + 8 * lk;
+      bh[g] = *reinterpret_cast<const bf16x8*>(Zh + o);
+      bl[g] = *reinterpret_cast<const bf16x8*>(Zl + o);
+    }
+#pragma unroll
+    for (int i = 0; i < kDctKtPerWave; ++i) {
+      const int kt = wave + kDctWaves * i;
+      if (kt < nkt) {
+        const size_t f = ((size_t)kt * nks + ks) * 64 + lane;
+        const bf16x8 ah = Ah[f], al = Al[f];
+#pragma unroll
+        for (int g = 0; g < kBfG; ++g) {
+          acc[i][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[g], acc[i][g], 0, 0, 0);
+          acc[i][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[g], acc[i][g], 0, 0, 0);
+          acc[i][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[g], acc[i][g], 0, 0, 0);
+        }
+      }
+    }
+  }
+  if (a.pure) {
+    float* out = a.V[set];
+#pragma unroll
+    for (int i = 0; i < kDctKtPerWave; ++i) {
+      const int kt = wave + kDctWaves * i;
+      if (kt < nkt) {
+#pragma unroll
+        for (int g = 0; g < kBfG; ++g) {
+          const int pix = pix0 + 16 * g + lr;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int k = kt * 16 + 4 * lk + r;
+            if (k < L && pix < N) out[(size_t)k * N + pix] = acc[i][g][r];
+          }
+        }
+      }
+    }
+    return;
+  }
+  __syncthreads();
+  const float sg = float(dp->sigma);
+  const float d1 = float(dct_coef(a.d1_sel[set], dp));
+  const float d2 = float(dct_coef(a.d2_sel[set], dp));
+  float* V = a.V[set];
+  const float* Vb = a.Vb[set];
+  uint8_t* M = a.mask[set];
+  float al[kBfG];
+#pragma unroll
+  for (int g = 0; g < kBfG; ++g) {
+    const int pix = pix0 + 16 * g + lr;
+    al[g] = a.alpha ? (pix < N ? float(a.alpha[pix]) : 0.f) : 1.f;
+  }
+#pragma unroll
+  for (int i = 0; i < kDctKtPerWave; ++i) {
+    const int kt = wave + kDctWaves * i;
+    if (kt < nkt) {
+#pragma unroll
+      for (int g = 0; g < kBfG; ++g) {
+        const int pix = pix0 + 16 * g + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = kt * 16 + 4 * lk + r;
+          float bv = 0.f;
+          if (k < L && pix < N) {
+            const size_t idx = (size_t)k * N + pix;
+            const float vt = V[idx] + sg * al[g] * acc[i][g][r];
+            float vn;
+            if (a.role == ROLE_PRIMAL) {
+              vn = vt < -1.f ? -1.f : (vt > 1.f ? 1.f : vt);
+              if (M) M[idx] = (vt >= -1.f && vt <= 1.f) ? 1 : 0;
+            } else {
+              vn = M[idx] ? vt : 0.f;
+            }
+            V[idx] = vn;
+            bv = d1 * vn;
+            if (Vb) bv += d2 * Vb[idx];
+          }
+          __bf16 h, lo;
+          split_bf16(bv, h, lo);
+          Zh[(16 * g + lr) * LpS + k] = h;
+          Zl[(16 * g + lr) * LpS + k] = lo;
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kDctKtPerWave; ++i)
+#pragma unroll
+    for (int g = 0; g < kBfG; ++g) acc[i][g] = flt4{0, 0, 0, 0};
+  for (int ks = 0; ks < nks; ++ks) {
+    bf16x8 bh[kBfG], bl[kBfG];
+#pragma unroll
+    for (int g = 0; g < kBfG; ++g) {
+      const int o = (16 * g + lr) * LpS + 32 * ks + 8 * lk;
+      bh[g] = *reinterpret_cast<const bf16x8*>(Zh + o);
+      bl[g] = *reinterpret_cast<const bf16x8*>(Zl + o);
+    }
+#pragma unroll
+    for (int i = 0; i < kDctKtPerWave; ++i) {
+      const int lt = wave + kDctWaves * i;
+      if (lt < nkt) {
+        const size_t f = ((size_t)lt * nks + ks) * 64 + lane;
+        const bf16x8 ah = a.Ah2[f], al2 = a.Al2[f];
+#pragma unroll
+        for (int g = 0; g < kBfG; ++g) {
+          acc[i][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[g], acc[i][g], 0, 0, 0);
+          acc[i][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al2, bh[g], acc[i][g], 0, 0, 0);
+          acc[i][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[g], acc[i][g], 0, 0, 0);
+        }
+      }
+    }
+  }
+  float* To = a.Tout[set];
+#pragma unroll
+  for (int i = 0; i < kDctKtPerWave; ++i) {
+    const int lt = wave + kDctWaves * i;
+    if (lt < nkt) {
+#pragma unroll
+      for (int g = 0; g < kBfG; ++g) {
+        const int pix = pix0 + 16 * g + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int l = lt * 16 + 4 * lk + r;
+          if (l < L && pix < N) To[(size_t)l * N + pix] = al[g] * acc[i][g][r];
+        }
+      }
+    }
+  }
+}
+
+// host: round-to-nearest-even float -> bf16 bits
+static uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7FFFu + lsb;
+  return (uint16_t)(u >> 16);
+}
+static float bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
 }
 
 template <typename T>
@@ -228,17 +502,52 @@ int dct_make_plan(DctPlan<T>& p, int L, int N, int kind) {
   if (L < 1 || L > 16 * kDctMaxKt) return -2;
   p.L = L;
   p.N = N;
-  p.Lp = (L + 15) & ~15;
+  p.Lp = kind == DCT_BF16X3 ? (L + 31) & ~31 : (L + 15) & ~15;
   p.kind = kind;
-  std::vector<T> h((size_t)p.Lp * p.Lp, T(0));
+  const int Lp = p.Lp, nkt = Lp / 16, nks = Lp / 4;
+  std::vector<long double> c((size_t)Lp * Lp, 0.0L);  // C[k][l], zero padded
   const long double pi = 3.14159265358979323846264338327950288L;
   for (int k = 0; k < L; ++k) {
     const long double ck = k == 0 ? sqrtl(1.0L / L) : sqrtl(2.0L / L);
-    for (int l = 0; l < L; ++l)
-      h[(size_t)k * p.Lp + l] = T(ck * cosl(pi * (2 * l + 1) * k / (2.0L * L)));
+    for (int l = 0; l < L; ++l) c[(size_t)k * Lp + l] = ck * cosl(pi * (2 * l + 1) * k / (2.0L * L));
   }
-  MUFFIN_HIP_CHECK(hipMalloc(&p.C, sizeof(T) * h.size()));
-  MUFFIN_HIP_CHECK(hipMemcpy(p.C, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+  // fragment order: lane = i + 16 k holds A[i][k] of tile (t, ks)
+  std::vector<T> f1((size_t)Lp * Lp), f2((size_t)Lp * Lp);
+  for (int t = 0; t < nkt; ++t)
+    for (int ks = 0; ks < nks; ++ks)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int i = lane % 16, k = lane / 16;
+        const size_t o = ((size_t)t * nks + ks) * 64 + lane;
+        f1[o] = T(c[(size_t)(t * 16 + i) * Lp + ks * 4 + k]);   // C[row][col]
+        f2[o] = T(c[(size_t)(ks * 4 + k) * Lp + t * 16 + i]);   // C^T[row][col]
+      }
+  MUFFIN_HIP_CHECK(hipMalloc(&p.C, sizeof(T) * 2 * f1.size()));
+  MUFFIN_HIP_CHECK(hipMemcpy(p.C, f1.data(), sizeof(T) * f1.size(), hipMemcpyHostToDevice));
+  MUFFIN_HIP_CHECK(hipMemcpy(p.C + f1.size(), f2.data(), sizeof(T) * f2.size(),
+                             hipMemcpyHostToDevice));
+  if (kind == DCT_BF16X3) {
+    // bf16 hi/lo fragments for the 16x16x32 instruction: [t][ks32][lane][8]
+    const int nk32 = Lp / 32;
+    const size_t cnt = (size_t)nkt * nk32 * 64 * 8;
+    std::vector<uint16_t> h((size_t)4 * cnt);
+    for (int t = 0; t < nkt; ++t)
+      for (int ks = 0; ks < nk32; ++ks)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int e = 0; e < 8; ++e) {
+            const int i = lane % 16, k = 8 * (lane / 16) + e;
+            const size_t o = (((size_t)t * nk32 + ks) * 64 + lane) * 8 + e;
+            const long double v1 = c[(size_t)(t * 16 + i) * Lp + ks * 32 + k];
+            const long double v2 = c[(size_t)(ks * 32 + k) * Lp + t * 16 + i];
+            const uint16_t h1 = bf16_bits((float)v1), h2 = bf16_bits((float)v2);
+            h[o] = h1;
+            h[cnt + o] = bf16_bits((float)(v1 - (long double)bf16_value(h1)));
+            h[2 * cnt + o] = h2;
+            h[3 * cnt + o] = bf16_bits((float)(v2 - (long double)bf16_value(h2)));
+          }
+    MUFFIN_HIP_CHECK(hipMalloc(&p.Chi, sizeof(uint16_t) * h.size()));
+    MUFFIN_HIP_CHECK(hipMemcpy(p.Chi, h.data(), sizeof(uint16_t) * h.size(), hipMemcpyHostToDevice));
+    p.Clo = p.Chi + cnt;
+  }
   return 0;
 }
 
@@ -246,13 +555,54 @@ template <typename T>
 void dct_free_plan(DctPlan<T>& p) {
   if (p.C) (void)hipFree(p.C);
   if (p.Chi) (void)hipFree(p.Chi);
-  if (p.Clo) (void)hipFree(p.Clo);
   p.C = nullptr;
   p.Chi = p.Clo = nullptr;
 }
 
+static int dct_update_bf16(const DctPlan<float>& p, const DctIO<float>& io, const DevParams* dp,
+                           hipStream_t s) {
+  DctBfArgs a{};
+  for (int i = 0; i < io.nsets; ++i) {
+    a.xt_a[i] = io.xt_a[i];
+    a.x_a[i] = io.x_a[i];
+    a.xt_b[i] = io.xt_b[i];
+    a.x_b[i] = io.x_b[i];
+    a.c1_sel[i] = io.c1_sel[i];
+    a.c2_sel[i] = io.c2_sel[i];
+    a.V[i] = io.V[i];
+    a.Vb[i] = io.Vb[i];
+    a.d1_sel[i] = io.d1_sel[i];
+    a.d2_sel[i] = io.d2_sel[i];
+    a.Tout[i] = io.Tout[i];
+    a.mask[i] = io.mask[i];
+  }
+  const int nkt = p.Lp / 16, nk32 = p.Lp / 32;
+  const size_t cnt = (size_t)nkt * nk32 * 64;  // bf16x8 per table
+  const bf16x8* base = reinterpret_cast<const bf16x8*>(p.Chi);
+  a.Ah1 = base;
+  a.Al1 = base + cnt;
+  a.Ah2 = base + 2 * cnt;
+  a.Al2 = base + 3 * cnt;
+  a.alpha = io.alpha;
+  a.dp = dp;
+  a.L = p.L;
+  a.Lp = p.Lp;
+  a.N = p.N;
+  a.role = io.role;
+  a.pure = io.pure;
+  const size_t shm = 2 * sizeof(__bf16) * (size_t)kBfPix * (p.Lp + 8);
+  dim3 grid((p.N + kBfPix - 1) / kBfPix, io.nsets);
+  MUFFIN_ALLOW_BIG_LDS(dct_bf16_kernel);
+  dct_bf16_kernel<<<grid, 64 * kDctWaves, shm, s>>>(a);
+  MUFFIN_HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
 template <typename T>
 int dct_update(const DctPlan<T>& p, const DctIO<T>& io, const DevParams* dp, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (p.kind == DCT_BF16X3) return dct_update_bf16(p, io, dp, s);
+  }
   DctArgs<T> a{};
   for (int i = 0; i < io.nsets; ++i) {
     a.xt_a[i] = io.xt_a[i];
@@ -268,7 +618,8 @@ int dct_update(const DctPlan<T>& p, const DctIO<T>& io, const DevParams* dp, hip
     a.Tout[i] = io.Tout[i];
     a.mask[i] = io.mask[i];
   }
-  a.C = p.C;
+  a.Cf1 = p.C;
+  a.Cf2 = p.C + (size_t)p.Lp * p.Lp;
   a.alpha = io.alpha;
   a.dp = dp;
   a.L = p.L;
@@ -276,11 +627,11 @@ int dct_update(const DctPlan<T>& p, const DctIO<T>& io, const DevParams* dp, hip
   a.N = p.N;
   a.role = io.role;
   a.pure = io.pure;
-  constexpr int kDctPix = 16 * dct_waves<T>();
-  const size_t shm = sizeof(T) * (size_t)p.Lp * kDctPix;
-  dim3 grid((p.N + kDctPix - 1) / kDctPix, io.nsets);
+  constexpr int PIX = 16 * dct_groups<T>();
+  const size_t shm = sizeof(T) * (size_t)p.Lp * PIX;
+  dim3 grid((p.N + PIX - 1) / PIX, io.nsets);
   MUFFIN_ALLOW_BIG_LDS(dct_kernel<T>);
-  dct_kernel<T><<<grid, 64 * dct_waves<T>(), shm, s>>>(a);
+  dct_kernel<T><<<grid, 64 * kDctWaves, shm, s>>>(a);
   MUFFIN_HIP_CHECK(hipGetLastError());
   return 0;
 }

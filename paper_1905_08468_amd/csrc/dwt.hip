@@ -223,63 +223,80 @@ __device__ __forceinline__ void an_rows(const T* in, T* rowbuf, int IN) {
   }
 }
 
-// Column filter + output of basis pidx.
+// Outputs of one thread in the column filter of a basis: rows kr0 + 2 kp + e
+// (e = 0, 1) of column q of the row-filtered tile, low (part 0) and high
+// (part 1) pass.  q < TO are the row-low columns, q >= TO the row-high ones.
+// Index of output (e, part) in the basis plane, or -1 for the low-low band
+// that goes to the next level (or out of range).
+template <int TO>
+__device__ __forceinline__ long an_out_index(int e, int part, int kr0, int kc0, int half, int n,
+                                             bool last) {
+  const int q = threadIdx.x % (2 * TO), kp = threadIdx.x / (2 * TO);
+  const bool dcol = q >= TO;
+  const int kc = kc0 + (dcol ? q - TO : q);
+  const int krow = kr0 + 2 * kp + e;
+  if (krow >= half || kc >= half) return -1;
+  if (part == 0 && !dcol && !last) return -1;
+  const int row = part == 0 ? krow : half + krow;
+  const int colq = dcol ? half + kc : kc;
+  return (long)row * n + colq;
+}
+
+// Column filter of basis PB and the dual update (or low-pass output) of this
+// thread's four outputs; u/m hold the prefetched dual values and masks.
 template <typename T, int TO, int NT, int PB>
 __device__ __forceinline__ void an_cols(const AnArgs<T>& a, const T* rowbuf, int set, int band,
-                                        int pidx, int kr0, int kc0, double scale) {
+                                        int kr0, int kc0, double scale, const T (&u)[4],
+                                        const uint8_t (&m)[4]) {
   constexpr int TAPS = 2 * PB;
   T h[TAPS], g[TAPS];
 #pragma unroll
-  for (int m = 0; m < TAPS; ++m) {
-    h[m] = filt_h<T>(PB - 1, m);
-    g[m] = filt_g<T>(PB - 1, m);
+  for (int k = 0; k < TAPS; ++k) {
+    h[k] = filt_h<T>(PB - 1, k);
+    g[k] = filt_g<T>(PB - 1, k);
   }
+  const int pidx = PB - 1;
   const int n = a.n, half = a.Ms >> 1;
   const size_t plane = (size_t)n * n;
   T* U = a.U[set] + ((size_t)band * a.P + pidx) * plane;
   uint8_t* M = a.mask[set] ? a.mask[set] + ((size_t)band * a.P + pidx) * plane : nullptr;
   T* llo = a.last ? nullptr : a.llout[set] + ((size_t)band * a.P + pidx) * (size_t)half * half;
-  for (int t = threadIdx.x; t < (TO / 2) * (2 * TO); t += NT) {
-    const int q = t % (2 * TO), kp = t / (2 * TO);
-    const int kr = 2 * kp;
-    T w[TAPS + 2];
+  const int q = threadIdx.x % (2 * TO), kp = threadIdx.x / (2 * TO);
+  const bool dcol = q >= TO;
+  const int kc = kc0 + (dcol ? q - TO : q);
+  const int kr = 2 * kp;
+  T w[TAPS + 2];
 #pragma unroll
-    for (int i = 0; i < TAPS + 2; ++i) w[i] = rowbuf[(2 * kr + i) * (2 * TO) + q];
-    const bool dcol = q >= TO;
-    const int kc = kc0 + (dcol ? q - TO : q);
+  for (int i = 0; i < TAPS + 2; ++i) w[i] = rowbuf[(2 * kr + i) * (2 * TO) + q];
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      T lo = T(0), hi = T(0);
+  for (int e = 0; e < 2; ++e) {
+    T lo = T(0), hi = T(0);
 #pragma unroll
-      for (int m = 0; m < TAPS; ++m) {
-        lo += h[m] * w[2 * e + m];
-        hi += g[m] * w[2 * e + m];
+    for (int k = 0; k < TAPS; ++k) {
+      lo += h[k] * w[2 * e + k];
+      hi += g[k] * w[2 * e + k];
+    }
+    const int krow = kr0 + kr + e;
+    if (krow >= half || kc >= half) continue;
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+      const T c = part == 0 ? lo : hi;
+      if (part == 0 && !dcol && !a.last) {
+        llo[(size_t)krow * half + kc] = c;  // LL goes to the next level
+        continue;
       }
-      const int krow = kr0 + kr + e;
-      if (krow >= half || kc >= half) continue;
-      // low-pass rows: (row-low, col-low) = LL, (row-high, col-low) = top right
-      // high-pass rows: bottom left / bottom right
-      const int colq = dcol ? half + kc : kc;
-#pragma unroll
-      for (int part = 0; part < 2; ++part) {
-        const T c = part == 0 ? lo : hi;
-        const int row = part == 0 ? krow : half + krow;
-        if (part == 0 && !dcol && !a.last) {
-          llo[(size_t)krow * half + kc] = c;  // LL goes to the next level
-          continue;
-        }
-        const size_t idx = (size_t)row * n + colq;
-        if (a.pure) {
-          U[idx] = T(a.pure_scale) * c;
-          continue;
-        }
-        const T pv = U[idx] + T(scale) * c;
-        if (a.role == ROLE_PRIMAL) {
-          U[idx] = pv < T(-1) ? T(-1) : (pv > T(1) ? T(1) : pv);
-          if (M) M[idx] = (pv >= T(-1) && pv <= T(1)) ? 1 : 0;
-        } else {
-          U[idx] = M[idx] ? pv : T(0);
-        }
+      const int row = part == 0 ? krow : half + krow;
+      const size_t idx = (size_t)row * n + (dcol ? half + kc : kc);
+      if (a.pure) {
+        U[idx] = T(a.pure_scale) * c;
+        continue;
+      }
+      const T pv = u[2 * e + part] + T(scale) * c;
+      if (a.role == ROLE_PRIMAL) {
+        U[idx] = pv < T(-1) ? T(-1) : (pv > T(1) ? T(1) : pv);
+        if (M) M[idx] = (pv >= T(-1) && pv <= T(1)) ? 1 : 0;
+      } else {
+        U[idx] = m[2 * e + part] ? pv : T(0);
       }
     }
   }
@@ -287,6 +304,7 @@ __device__ __forceinline__ void an_cols(const AnArgs<T>& a, const T* rowbuf, int
 
 template <typename T, int TO, int NT>
 __global__ void __launch_bounds__(NT) dwt_an(AnArgs<T> a) {
+  static_assert((TO / 2) * (2 * TO) == NT, "one thread per column-filter output quad");
   constexpr int IN = 2 * TO + kHalo;
   __shared__ T s_in[IN * IN];
   __shared__ T s_row[IN * 2 * TO];
@@ -298,15 +316,44 @@ __global__ void __launch_bounds__(NT) dwt_an(AnArgs<T> a) {
   const int kr0 = (tile / a.tiles) * TO, kc0 = (tile % a.tiles) * TO;
   const int set = a.level == 1 ? blockIdx.y : blockIdx.y / a.P;
   const int pone = a.level == 1 ? -1 : blockIdx.y % a.P;
-  const int Ms = a.Ms, msk = Ms - 1;
+  const int Ms = a.Ms, msk = Ms - 1, half = Ms >> 1;
   const int n = a.n;
+  const int p0 = a.level == 1 ? 0 : pone;
+  const int p1 = a.level == 1 ? a.P : pone + 1;
+  // ---- prefetch the dual values and masks this thread updates ----
+  T u[kMaxBases][4];
+  uint8_t m[kMaxBases][4];
+  const bool upd = !a.pure;
+  const size_t plane = (size_t)n * n;
+#pragma unroll
+  for (int pb = 0; pb < kMaxBases; ++pb) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      u[pb][i] = T(0);
+      m[pb][i] = 0;
+    }
+    if (upd && pb >= p0 && pb < p1) {
+      const T* U = a.U[set] + ((size_t)band * a.P + pb) * plane;
+      const uint8_t* M = (a.role == ROLE_DERIV && a.mask[set])
+                             ? a.mask[set] + ((size_t)band * a.P + pb) * plane
+                             : nullptr;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const long idx = an_out_index<TO>(i >> 1, i & 1, kr0, kc0, half, n, a.last);
+        if (idx >= 0) {
+          u[pb][i] = U[idx];
+          if (M) m[pb][i] = M[idx];
+        }
+      }
+    }
+  }
   // ---- stage the input tile (periodic wrap) ----
   if (a.level == 1) {
     const double c1 = coef_of(a.c1_sel[set], a.dp), c2 = coef_of(a.c2_sel[set], a.dp);
-    const T* xa = a.x_a[set] + (size_t)band * n * n;
-    const T* ta = a.xt_a[set] + (size_t)band * n * n;
-    const T* xb = a.x_b[set] ? a.x_b[set] + (size_t)band * n * n : nullptr;
-    const T* tb = a.xt_b[set] ? a.xt_b[set] + (size_t)band * n * n : nullptr;
+    const T* xa = a.x_a[set] + (size_t)band * plane;
+    const T* ta = a.xt_a[set] + (size_t)band * plane;
+    const T* xb = a.x_b[set] ? a.x_b[set] + (size_t)band * plane : nullptr;
+    const T* tb = a.xt_b[set] ? a.xt_b[set] + (size_t)band * plane : nullptr;
     for (int t = threadIdx.x; t < IN * IN; t += NT) {
       const int r = t / IN, c = t - r * IN;
       const size_t idx = (size_t)((2 * kr0 + r) & msk) * n + ((2 * kc0 + c) & msk);
@@ -324,28 +371,23 @@ __global__ void __launch_bounds__(NT) dwt_an(AnArgs<T> a) {
   __syncthreads();
   const double beta = a.beta ? a.beta[band] : 1.0;
   const double scale = a.dp ? a.dp->sigma * beta / sqrt((double)a.P) : 0.0;
-  const int p0 = a.level == 1 ? 0 : pone;
-  const int p1 = a.level == 1 ? a.P : pone + 1;
-  for (int pidx = p0; pidx < p1; ++pidx) {
-    switch (pidx + 1) {
-#define MUFFIN_AN_CASE(PB)                                                   \
-  case PB:                                                                   \
-    an_rows<T, TO, NT, PB>(s_in, s_row, IN);                                 \
-    __syncthreads();                                                         \
-    an_cols<T, TO, NT, PB>(a, s_row, set, band, pidx, kr0, kc0, scale);      \
-    break;
-      MUFFIN_AN_CASE(1)
-      MUFFIN_AN_CASE(2)
-      MUFFIN_AN_CASE(3)
-      MUFFIN_AN_CASE(4)
-      MUFFIN_AN_CASE(5)
-      MUFFIN_AN_CASE(6)
-      MUFFIN_AN_CASE(7)
-      MUFFIN_AN_CASE(8)
-#undef MUFFIN_AN_CASE
-    }
-    __syncthreads();
+#define MUFFIN_AN_STEP(PB)                                                      \
+  if (PB - 1 >= p0 && PB - 1 < p1) {                                            \
+    an_rows<T, TO, NT, PB>(s_in, s_row, IN);                                    \
+    __syncthreads();                                                            \
+    an_cols<T, TO, NT, PB>(a, s_row, set, band, kr0, kc0, scale, u[PB - 1],     \
+                           m[PB - 1]);                                          \
+    __syncthreads();                                                            \
   }
+  MUFFIN_AN_STEP(1)
+  MUFFIN_AN_STEP(2)
+  MUFFIN_AN_STEP(3)
+  MUFFIN_AN_STEP(4)
+  MUFFIN_AN_STEP(5)
+  MUFFIN_AN_STEP(6)
+  MUFFIN_AN_STEP(7)
+  MUFFIN_AN_STEP(8)
+#undef MUFFIN_AN_STEP
 }
 
 // ---------------------------------------------------------------------------
@@ -366,11 +408,15 @@ struct SyArgs {
 };
 
 // Column synthesis of basis PB: from the four quadrants (low/high rows of the
-// c and d column halves) into rbuf[2TC][2 (TC + HAL)].
+// c and d column halves) into rbuf[2TC][2 (TC + HAL)].  Each thread slides
+// over APT consecutive coefficient rows, so every LDS value it loads feeds
+// several outputs.
 template <typename T, int TC, int NT, int PB>
 __device__ __forceinline__ void sy_cols(const T* q, T* rbuf) {
-  constexpr int TAPS = 2 * PB;
   constexpr int W = TC + kSHal;
+  constexpr int APT = 4;
+  constexpr int NA = TC / APT;
+  constexpr int NW = APT + PB - 1;
   T he[PB], ho[PB], ge[PB], go[PB];
 #pragma unroll
   for (int e = 0; e < PB; ++e) {
@@ -379,33 +425,45 @@ __device__ __forceinline__ void sy_cols(const T* q, T* rbuf) {
     ge[e] = filt_g<T>(PB - 1, 2 * e);
     go[e] = filt_g<T>(PB - 1, 2 * e + 1);
   }
-  (void)TAPS;
   // q layout: [quad][W][W], quad 0 = low rows / c cols, 1 = high rows / c cols,
   // 2 = low rows / d cols, 3 = high rows / d cols
-  for (int t = threadIdx.x; t < TC * 2 * W; t += NT) {
-    const int col = t % (2 * W), a = t / (2 * W);
-    const int half = col >= W;
-    const int cc = half ? col - W : col;
-    const T* ql = q + (half ? 2 : 0) * W * W + cc;
-    const T* qh = q + (half ? 3 : 1) * W * W + cc;
-    T ev = T(0), od = T(0);
+  for (int t = threadIdx.x; t < NA * 2 * W; t += NT) {
+    const int col = t % (2 * W), a0 = (t / (2 * W)) * APT;
+    const int hf = col >= W;
+    const int cc = hf ? col - W : col;
+    const T* ql = q + (hf ? 2 : 0) * W * W + cc;
+    const T* qh = q + (hf ? 3 : 1) * W * W + cc;
+    // coefficient rows a - e + HAL for a in [a0, a0 + APT), e < PB
+    const int row0 = a0 - PB + 1 + kSHal;
+    T wl[NW], wh[NW];
 #pragma unroll
-    for (int e = 0; e < PB; ++e) {
-      const int row = a - e + kSHal;
-      const T l = ql[row * W], hgh = qh[row * W];
-      ev += he[e] * l + ge[e] * hgh;
-      od += ho[e] * l + go[e] * hgh;
+    for (int i = 0; i < NW; ++i) {
+      wl[i] = ql[(row0 + i) * W];
+      wh[i] = qh[(row0 + i) * W];
     }
-    rbuf[(2 * a) * (2 * W) + col] = ev;
-    rbuf[(2 * a + 1) * (2 * W) + col] = od;
+#pragma unroll
+    for (int a = 0; a < APT; ++a) {
+      T ev = T(0), od = T(0);
+#pragma unroll
+      for (int e = 0; e < PB; ++e) {
+        const T l = wl[a - e + PB - 1], hh = wh[a - e + PB - 1];
+        ev += he[e] * l + ge[e] * hh;
+        od += ho[e] * l + go[e] * hh;
+      }
+      rbuf[(2 * (a0 + a)) * (2 * W) + col] = ev;
+      rbuf[(2 * (a0 + a) + 1) * (2 * W) + col] = od;
+    }
   }
 }
 
-// Row synthesis of basis PB, accumulated into acc[] for this thread's
-// outputs (ri, 2b) and (ri, 2b + 1).
-template <typename T, int TC, int NT, int PB, int NPT>
-__device__ __forceinline__ void sy_rows(const T* rbuf, T (&acc)[NPT][2]) {
+// Row synthesis of basis PB, accumulated into acc[b][0..1] = outputs
+// (ri, 2 (b0 + b)) and (ri, 2 (b0 + b) + 1) of this thread.
+template <typename T, int TC, int NT, int PB>
+__device__ __forceinline__ void sy_rows(const T* rbuf, T (&acc)[2][2]) {
   constexpr int W = TC + kSHal;
+  constexpr int BPT = 2;
+  constexpr int NW = BPT + PB - 1;
+  static_assert(2 * TC * (TC / BPT) == NT, "one thread per output quad");
   T he[PB], ho[PB], ge[PB], go[PB];
 #pragma unroll
   for (int e = 0; e < PB; ++e) {
@@ -414,29 +472,55 @@ __device__ __forceinline__ void sy_rows(const T* rbuf, T (&acc)[NPT][2]) {
     ge[e] = filt_g<T>(PB - 1, 2 * e);
     go[e] = filt_g<T>(PB - 1, 2 * e + 1);
   }
+  const int t = threadIdx.x;
+  const int ri = t / (TC / BPT), b0 = (t % (TC / BPT)) * BPT;
+  const T* rc = rbuf + ri * (2 * W);
+  const T* rd = rc + W;
+  const int c0 = b0 - PB + 1 + kSHal;
+  T wc[NW], wd[NW];
 #pragma unroll
-  for (int i = 0; i < NPT; ++i) {
-    const int t = threadIdx.x + i * NT;
-    const int b = t % TC, ri = t / TC;
-    const T* rc = rbuf + ri * (2 * W);
-    const T* rd = rc + W;
+  for (int i = 0; i < NW; ++i) {
+    wc[i] = rc[c0 + i];
+    wd[i] = rd[c0 + i];
+  }
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
     T ev = T(0), od = T(0);
 #pragma unroll
     for (int e = 0; e < PB; ++e) {
-      const int c = b - e + kSHal;
-      ev += he[e] * rc[c] + ge[e] * rd[c];
-      od += ho[e] * rc[c] + go[e] * rd[c];
+      const T c = wc[b - e + PB - 1], d = wd[b - e + PB - 1];
+      ev += he[e] * c + ge[e] * d;
+      od += ho[e] * c + go[e] * d;
     }
-    acc[i][0] += ev;
-    acc[i][1] += od;
+    acc[b][0] += ev;
+    acc[b][1] += od;
   }
+}
+
+// One value of the quadrant tile of basis pidx for LDS slot t (periodic wrap;
+// the low-low quadrant comes from the coarser level's output when there is one).
+template <typename T, int TC>
+__device__ __forceinline__ T sy_tile_value(const SyArgs<T>& a, int set, int band, int pidx,
+                                           int t, int kr0, int kc0, double a1, double a2) {
+  constexpr int W = TC + kSHal;
+  const int n = a.n, half = a.Ms >> 1, hm = half - 1;
+  const int quad = t / (W * W), rem = t - quad * W * W;
+  const int r = rem / W, c = rem - r * W;
+  const int kr = (kr0 - kSHal + r) & hm, kc = (kc0 - kSHal + c) & hm;
+  if (quad == 0 && a.level < a.J)
+    return a.llin[set][((size_t)band * a.P + pidx) * (size_t)half * half + (size_t)kr * half + kc];
+  const int roff = (quad & 1) ? half : 0, coff = (quad & 2) ? half : 0;
+  const size_t idx = ((size_t)band * a.P + pidx) * ((size_t)n * n) + (size_t)(roff + kr) * n +
+                     (coff + kc);
+  T v = T(a1) * a.Ua[set][idx];
+  if (a.Ub[set]) v += T(a2) * a.Ub[set][idx];
+  return v;
 }
 
 template <typename T, int TC, int NT>
 __global__ void __launch_bounds__(NT) dwt_sy(SyArgs<T> a) {
   constexpr int W = TC + kSHal;
-  constexpr int NPT = (2 * TC * TC) / NT;  // outputs (pairs) per thread
-  static_assert(NPT * NT == 2 * TC * TC, "tile/threads");
+  constexpr int NQ = (4 * W * W + NT - 1) / NT;  // tile values per thread
   __shared__ T s_q[4 * W * W];
   __shared__ T s_r[2 * TC * 2 * W];
   const int lb = xcd_remap_d(blockIdx.x, a.nblocks);
@@ -447,82 +531,72 @@ __global__ void __launch_bounds__(NT) dwt_sy(SyArgs<T> a) {
   const int kr0 = (tile / a.tiles) * TC, kc0 = (tile % a.tiles) * TC;
   const int set = a.level == 1 ? blockIdx.y : blockIdx.y / a.P;
   const int pone = a.level == 1 ? -1 : blockIdx.y % a.P;
-  const int n = a.n, Ms = a.Ms, half = Ms >> 1, hm = half - 1;
+  const int n = a.n, Ms = a.Ms;
   const size_t plane = (size_t)n * n;
   const double a1 = a.pure ? 1.0 : coef_of(a.a1_sel[set], a.dp);
   const double a2 = a.pure ? 0.0 : coef_of(a.a2_sel[set], a.dp);
-  T acc[NPT][2];
-#pragma unroll
-  for (int i = 0; i < NPT; ++i) acc[i][0] = acc[i][1] = T(0);
   const int p0 = a.level == 1 ? 0 : pone;
   const int p1 = a.level == 1 ? a.P : pone + 1;
-  for (int pidx = p0; pidx < p1; ++pidx) {
-    const T* Ua = a.Ua[set] + ((size_t)band * a.P + pidx) * plane;
-    const T* Ub = a.Ub[set] ? a.Ub[set] + ((size_t)band * a.P + pidx) * plane : nullptr;
-    const T* ll = a.level < a.J ? a.llin[set] + ((size_t)band * a.P + pidx) * (size_t)half * half
-                                : nullptr;
-    for (int t = threadIdx.x; t < 4 * W * W; t += NT) {
-      const int quad = t / (W * W), rem = t - quad * W * W;
-      const int r = rem / W, c = rem - r * W;
-      const int kr = (kr0 - kSHal + r) & hm, kc = (kc0 - kSHal + c) & hm;
-      const int roff = (quad & 1) ? half : 0, coff = (quad & 2) ? half : 0;
-      T v;
-      if (quad == 0 && ll) {
-        v = ll[(size_t)kr * half + kc];
-      } else {
-        const size_t idx = (size_t)(roff + kr) * n + (coff + kc);
-        v = T(a1) * Ua[idx];
-        if (Ub) v += T(a2) * Ub[idx];
-      }
-      s_q[t] = v;
-    }
-    __syncthreads();
-    switch (pidx + 1) {
-#define MUFFIN_SY_CASE(PB)                        \
-  case PB:                                        \
-    sy_cols<T, TC, NT, PB>(s_q, s_r);             \
-    __syncthreads();                              \
-    sy_rows<T, TC, NT, PB, NPT>(s_r, acc);        \
-    break;
-      MUFFIN_SY_CASE(1)
-      MUFFIN_SY_CASE(2)
-      MUFFIN_SY_CASE(3)
-      MUFFIN_SY_CASE(4)
-      MUFFIN_SY_CASE(5)
-      MUFFIN_SY_CASE(6)
-      MUFFIN_SY_CASE(7)
-      MUFFIN_SY_CASE(8)
-#undef MUFFIN_SY_CASE
-    }
-    __syncthreads();
+  T acc[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
+  // tile of the first basis straight to LDS
+  for (int t = threadIdx.x; t < 4 * W * W; t += NT)
+    s_q[t] = sy_tile_value<T, TC>(a, set, band, p0, t, kr0, kc0, a1, a2);
+  __syncthreads();
+  T nxt[NQ];
+#define MUFFIN_SY_STEP(PB)                                                        \
+  if (PB - 1 >= p0 && PB - 1 < p1) {                                              \
+    const bool more = PB < p1;                                                    \
+    if (more) {                                                                   \
+      _Pragma("unroll") for (int i = 0; i < NQ; ++i) {                            \
+        const int t = threadIdx.x + i * NT;                                       \
+        if (t < 4 * W * W) nxt[i] = sy_tile_value<T, TC>(a, set, band, PB, t, kr0, kc0, a1, a2); \
+      }                                                                           \
+    }                                                                             \
+    sy_cols<T, TC, NT, PB>(s_q, s_r);                                             \
+    __syncthreads();                                                              \
+    sy_rows<T, TC, NT, PB>(s_r, acc);                                             \
+    if (more) {                                                                   \
+      _Pragma("unroll") for (int i = 0; i < NQ; ++i) {                            \
+        const int t = threadIdx.x + i * NT;                                       \
+        if (t < 4 * W * W) s_q[t] = nxt[i];                                       \
+      }                                                                           \
+    }                                                                             \
+    __syncthreads();                                                              \
   }
-  // ---- store ----
+  MUFFIN_SY_STEP(1)
+  MUFFIN_SY_STEP(2)
+  MUFFIN_SY_STEP(3)
+  MUFFIN_SY_STEP(4)
+  MUFFIN_SY_STEP(5)
+  MUFFIN_SY_STEP(6)
+  MUFFIN_SY_STEP(7)
+  MUFFIN_SY_STEP(8)
+#undef MUFFIN_SY_STEP
+  // ---- store: each thread owns 4 consecutive outputs of one row ----
   const int o0 = 2 * kr0, q0 = 2 * kc0;
-  if (a.level == 1) {
-    const double beta = a.beta ? a.beta[band] : 1.0;
-    const T sc = T(beta / sqrt((double)a.P));
-    T* S = a.S[set] + (size_t)band * plane;
-#pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-      const int t = threadIdx.x + i * NT;
-      const int b = t % TC, ri = t / TC;
-      const int row = o0 + ri, col = q0 + 2 * b;
-      if (row < Ms && col < Ms) {
-        S[(size_t)row * n + col] = sc * acc[i][0];
-        S[(size_t)row * n + col + 1] = sc * acc[i][1];
-      }
+  const int ri = threadIdx.x / (TC / 2), b0 = (threadIdx.x % (TC / 2)) * 2;
+  const int row = o0 + ri, col = q0 + 2 * b0;
+  if (row < Ms && col < Ms) {
+    T* dst;
+    T sc = T(1);
+    if (a.level == 1) {
+      const double beta = a.beta ? a.beta[band] : 1.0;
+      sc = T(beta / sqrt((double)a.P));
+      dst = a.S[set] + (size_t)band * plane + (size_t)row * n + col;
+    } else {
+      dst = a.llout[set] + ((size_t)band * a.P + pone) * (size_t)Ms * Ms + (size_t)row * Ms + col;
     }
-  } else {
-    T* out = a.llout[set] + ((size_t)band * a.P + pone) * (size_t)Ms * Ms;
-#pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-      const int t = threadIdx.x + i * NT;
-      const int b = t % TC, ri = t / TC;
-      const int row = o0 + ri, col = q0 + 2 * b;
-      if (row < Ms && col < Ms) {
-        out[(size_t)row * Ms + col] = acc[i][0];
-        out[(size_t)row * Ms + col + 1] = acc[i][1];
+    if (col + 3 < Ms) {
+      if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4*>(dst) =
+            make_float4(sc * acc[0][0], sc * acc[0][1], sc * acc[1][0], sc * acc[1][1]);
+      } else {
+        reinterpret_cast<double2*>(dst)[0] = make_double2(sc * acc[0][0], sc * acc[0][1]);
+        reinterpret_cast<double2*>(dst)[1] = make_double2(sc * acc[1][0], sc * acc[1][1]);
       }
+    } else {
+      dst[0] = sc * acc[0][0];
+      dst[1] = sc * acc[0][1];
     }
   }
 }

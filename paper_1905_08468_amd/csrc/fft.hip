@@ -78,13 +78,34 @@ __device__ __forceinline__ void dft_small(cplx<T>* v) {
   }
 }
 
+// LDS index swizzle: one padding element every 16 (FP32) or 8 (FP64)
+// complex values, which removes the bank conflicts of the strided Stockham
+// writes (checked with a bank model for every stage of 1024/2048 points).
+template <typename T>
+__device__ __forceinline__ int sw(int x) {
+  return x + (x >> (sizeof(T) == 8 ? 3 : 4));
+}
+template <typename T>
+__host__ __device__ constexpr int sw_stride(int nf) {
+  // padded length of one sequence, +1 so that consecutive sequences start on
+  // different banks (transposed accesses walk across sequences)
+  return nf - 1 + ((nf - 1) >> (sizeof(T) == 8 ? 3 : 4)) + 2;
+}
+
+// Radix schedule shared by the device FFT and the host twiddle tables:
+// 8s, finishing with 4 or 4,4 or 2.
+__host__ __device__ __forceinline__ int radix_log(int rem) {
+  return rem == 1 ? 1 : ((rem == 2 || rem == 4) ? 2 : 3);
+}
+
 // One Stockham stage: input element j + r*nf/R, output (j - k) R + k + r Ns
 // with k = j mod Ns.  Every thread first loads all its butterflies, then the
-// block synchronises and stores, so the stage runs in place.
+// block synchronises and stores, so the stage runs in place.  Twiddles
+// exp(-2 pi i r k / (Ns R)), r = 1..R-1, come from this stage's table stored
+// as [k][r - 1] (consecutive threads read consecutive entries).
 template <typename T, int R, int NT, int EMAX>
 __device__ __forceinline__ void fft_stage(cplx<T>* buf, int lognf, int logNs, int batch,
-                                          int stride, const cplx<T>* __restrict__ tw,
-                                          int logTw) {
+                                          int stride, const cplx<T>* __restrict__ tws) {
   constexpr int MAXQ = (EMAX / R + NT - 1) / NT;
   constexpr int LOGR = R == 2 ? 1 : (R == 4 ? 2 : 3);
   const int lognbf = lognf - LOGR;
@@ -96,15 +117,13 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int lognf, int logNs, in
     const int t = threadIdx.x + q * NT;
     if (t < total) {
       const int b = t >> lognbf, j = t & (nbf - 1);
-      const cplx<T>* src = buf + b * stride + j;
+      const cplx<T>* src = buf + b * stride;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = src[r * nbf];
+      for (int r = 0; r < R; ++r) v[q][r] = src[sw<T>(j + r * nbf)];
     }
   }
   __syncthreads();
   const int Ns = 1 << logNs;
-  // twiddle for (r, k): exp(-2 pi i r k / (Ns R)) = tw[r k 2^(logTw - logNs - LOGR)]
-  const int shift = logTw - logNs - LOGR;
 #pragma unroll
   for (int q = 0; q < MAXQ; ++q) {
     const int t = threadIdx.x + q * NT;
@@ -112,36 +131,34 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int lognf, int logNs, in
       const int b = t >> lognbf, j = t & (nbf - 1);
       const int k = j & (Ns - 1);
       if (logNs > 0) {
+        const cplx<T>* w = tws + k * (R - 1);
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[(r * k) << shift]);
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[r - 1]);
       }
       dft_small<T, R>(v[q]);
-      cplx<T>* dst = buf + b * stride + (j - k) * R + k;
+      cplx<T>* dst = buf + b * stride;
+      const int base = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[r * Ns] = v[q][r];
+      for (int r = 0; r < R; ++r) dst[sw<T>(base + r * Ns)] = v[q][r];
     }
   }
   __syncthreads();
 }
 
-// Forward FFT of `batch` sequences of length 2^lognf held in LDS.  Radix
-// schedule: 8s, finishing with 4 or 4,4 or 2 so no stage is wasted.
+// Forward FFT of `batch` sequences of length 2^lognf held in LDS (swizzled,
+// sequence b at buf + b * stride).  twtab: the stage tables of this length.
 template <typename T, int NT, int EMAX>
 __device__ __forceinline__ void lds_fft(cplx<T>* buf, int lognf, int batch, int stride,
-                        const cplx<T>* __restrict__ tw, int logTw) {
-  int done = 0;
+                                        const cplx<T>* __restrict__ twtab) {
+  int done = 0, off = 0;
   while (done < lognf) {
-    const int rem = lognf - done;
-    if (rem == 1) {
-      fft_stage<T, 2, NT, EMAX>(buf, lognf, done, batch, stride, tw, logTw);
-      done += 1;
-    } else if (rem == 2 || rem == 4) {
-      fft_stage<T, 4, NT, EMAX>(buf, lognf, done, batch, stride, tw, logTw);
-      done += 2;
-    } else {
-      fft_stage<T, 8, NT, EMAX>(buf, lognf, done, batch, stride, tw, logTw);
-      done += 3;
-    }
+    const int lr = radix_log(lognf - done);
+    const cplx<T>* tws = twtab + off;
+    if (lr == 1) fft_stage<T, 2, NT, EMAX>(buf, lognf, done, batch, stride, tws);
+    else if (lr == 2) fft_stage<T, 4, NT, EMAX>(buf, lognf, done, batch, stride, tws);
+    else fft_stage<T, 8, NT, EMAX>(buf, lognf, done, batch, stride, tws);
+    if (done > 0) off += (1 << done) * ((1 << lr) - 1);
+    done += lr;
   }
 }
 
@@ -182,12 +199,13 @@ struct RowArgs {
   const cplx<T>* in_spec[kMaxSets];
   T* out[kMaxSets];
   cplx<T>* out_spec[kMaxSets];
-  const cplx<T>* tw;   // exp(-2 pi i k / 2n)
-  const T* y;          // residual reference for set 0, or null
+  const cplx<T>* tw;    // exp(-2 pi i k / 2n), k < 2n (Hermitian passes)
+  const cplx<T>* twr;   // stage tables of the length-n FFT
+  const T* y;           // residual reference for set 0, or null
   double* partials;
   int n, logn, L;
-  int rows;            // rows per band: n, or 2n for the PSF pass
-  int nblocks;         // logical blocks per set
+  int rows;             // rows per band: n, or 2n for the PSF pass
+  int nblocks;          // logical blocks per set
 };
 
 template <typename T, int RB, int NT, int IN, int OUT>
@@ -196,7 +214,7 @@ __global__ void __launch_bounds__(NT) row_pass(RowArgs<T> a) {
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   __shared__ double red[NT / 64];
   const int n = a.n, logn = a.logn;
-  const int stride = n + 1;  // padded LDS row stride
+  const int stride = sw_stride<T>(n);
   const int lb = xcd_remap(blockIdx.x, a.nblocks);
   if (lb >= a.nblocks) return;
   const int set = blockIdx.y;
@@ -204,7 +222,7 @@ __global__ void __launch_bounds__(NT) row_pass(RowArgs<T> a) {
   const int band = lb / rblocks;
   const int i0 = (lb - band * rblocks) * RB;
   const int half = n >> 1;
-  constexpr int EMAX = (sizeof(T) == 8 ? 16 : 32) * NT;
+  constexpr int EMAX = (sizeof(T) == 8 ? 16 : 32) * 256;
 
   // ---- load ----
   if constexpr (IN == IN_REAL) {
@@ -216,7 +234,7 @@ __global__ void __launch_bounds__(NT) row_pass(RowArgs<T> a) {
         const T* p = x + (size_t)r * n + 2 * m;
         z = {p[0], p[1]};
       }
-      buf[r * stride + m] = z;
+      buf[r * stride + sw<T>(m)] = z;
     }
   } else if constexpr (IN == IN_PSF) {
     // row i of ifftshift(psf): psf[(i + n) mod 2n][(j + n) mod 2n]
@@ -227,14 +245,14 @@ __global__ void __launch_bounds__(NT) row_pass(RowArgs<T> a) {
       const int row = (i0 + r + n) & (m2 - 1);
       const int c0 = (2 * m + n) & (m2 - 1);
       const T* p = ps + (size_t)row * m2;
-      buf[r * stride + m] = {p[c0], p[(c0 + 1) & (m2 - 1)]};
+      buf[r * stride + sw<T>(m)] = {p[c0], p[(c0 + 1) & (m2 - 1)]};
     }
   } else {
     // packed half spectrum, column-major: spec[kx][row]
     const cplx<T>* sp = a.in_spec[set] + (size_t)band * n * n + i0;
     for (int t = threadIdx.x; t < RB * n; t += NT) {
       const int kx = t / RB, r = t - kx * RB;
-      buf[r * stride + kx] = sp[(size_t)kx * n + r];
+      buf[r * stride + sw<T>(kx)] = sp[(size_t)kx * n + r];
     }
     __syncthreads();
     // Hermitian pre-pass of the real inverse: with A = X[k], B = conj X[n-k],
@@ -249,21 +267,22 @@ __global__ void __launch_bounds__(NT) row_pass(RowArgs<T> a) {
         row[0] = {a0 + an, -(a0 - an)};  // conj((a0 + an) + i (a0 - an))
       } else {
         const cplx<T> w = cconj(a.tw[k]);  // exp(+i pi k / n)
-        const cplx<T> A = row[k];
-        const cplx<T> B = cconj(row[n - k]);
+        const int ik = sw<T>(k), im = sw<T>(n - k);
+        const cplx<T> A = row[ik];
+        const cplx<T> B = cconj(row[im]);
         const cplx<T> S = cadd(A, B), D = csub(A, B);
         const cplx<T> wD = cmul(w, D);
         const cplx<T> Zk = {S.x - wD.y, S.y + wD.x};
         if (k == half) {
-          row[k] = cconj(Zk);
+          row[ik] = cconj(Zk);
         } else {
           // partner: A' = X[n-k], B' = conj X[k], w' = exp(i pi (n-k)/n) = -conj(w)
           const cplx<T> S2 = cconj(S);  // A' + B' = conj(A + B)
           const cplx<T> D2 = {-D.x, D.y};  // A' - B' = -conj(D)
           const cplx<T> wD2 = cmul(cplx<T>{-w.x, w.y}, D2);
           const cplx<T> Zm = {S2.x - wD2.y, S2.y + wD2.x};
-          row[k] = cconj(Zk);
-          row[n - k] = cconj(Zm);
+          row[ik] = cconj(Zk);
+          row[im] = cconj(Zm);
         }
       }
     }
@@ -271,14 +290,14 @@ __global__ void __launch_bounds__(NT) row_pass(RowArgs<T> a) {
   __syncthreads();
 
   if constexpr (IN == IN_SPEC) {
-    lds_fft<T, NT, EMAX>(buf, logn, RB, stride, a.tw, logn + 1);
+    lds_fft<T, NT, EMAX>(buf, logn, RB, stride, a.twr);
     // z = conj(buf): x[2m] = z.x, x[2m+1] = z.y for m < n/2 (image window)
     double acc = 0.0;
     if constexpr (OUT == OUT_REAL) {
       T* o = a.out[set] + ((size_t)band * n + i0) * n;
       for (int t = threadIdx.x; t < RB * half; t += NT) {
         const int r = t / half, m = t - r * half;
-        const cplx<T> z = buf[r * stride + m];
+        const cplx<T> z = buf[r * stride + sw<T>(m)];
         T* p = o + (size_t)r * n + 2 * m;
         p[0] = z.x;
         p[1] = -z.y;
@@ -289,8 +308,9 @@ __global__ void __launch_bounds__(NT) row_pass(RowArgs<T> a) {
       for (int t = threadIdx.x; t < RB * n; t += NT) {
         const int r = t >> logn, m = t & (n - 1);
         cplx<T> z = {T(0), T(0)};
+        const int im = r * stride + sw<T>(m);
         if (m < half) {
-          const cplx<T> c = buf[r * stride + m];
+          const cplx<T> c = buf[im];
           z = {c.x, -c.y};
           if (y != nullptr) {
             const T* q = y + (size_t)r * n + 2 * m;
@@ -299,7 +319,7 @@ __global__ void __launch_bounds__(NT) row_pass(RowArgs<T> a) {
             acc += e0 * e0 + e1 * e1;
           }
         }
-        buf[r * stride + m] = z;
+        buf[im] = z;
       }
       if (a.partials != nullptr && set == 0) {
         const double s = block_sum<NT>(acc, red);
@@ -310,7 +330,7 @@ __global__ void __launch_bounds__(NT) row_pass(RowArgs<T> a) {
   }
 
   if constexpr (OUT == OUT_SPEC || OUT == OUT_PSFTMP) {
-    lds_fft<T, NT, EMAX>(buf, logn, RB, stride, a.tw, logn + 1);
+    lds_fft<T, NT, EMAX>(buf, logn, RB, stride, a.twr);
     // Hermitian post-pass of the real forward transform:
     // X[k] = (Z[k] + conj Z[n-k]) / 2 - (i / 2) exp(-i pi k / n) (Z[k] - conj Z[n-k])
     for (int t = threadIdx.x; t < RB * (half + 1); t += NT) {
@@ -321,21 +341,22 @@ __global__ void __launch_bounds__(NT) row_pass(RowArgs<T> a) {
         row[0] = {z.x + z.y, z.x - z.y};  // (X[0], X[n]), both real
       } else {
         const cplx<T> w = a.tw[k];
-        const cplx<T> A = row[k];
-        const cplx<T> B = cconj(row[n - k]);
+        const int ik = sw<T>(k), im = sw<T>(n - k);
+        const cplx<T> A = row[ik];
+        const cplx<T> B = cconj(row[im]);
         const cplx<T> S = cadd(A, B), D = csub(A, B);
         const cplx<T> wD = cmul(w, D);
         // X = S/2 - (i/2) wD = (S.x + wD.y, S.y - wD.x) / 2
         const cplx<T> Xk = {T(0.5) * (S.x + wD.y), T(0.5) * (S.y - wD.x)};
         if (k == half) {
-          row[k] = Xk;
+          row[ik] = Xk;
         } else {
           // partner twiddle exp(-i pi (n-k)/n) = -conj(w)
           const cplx<T> S2 = cconj(S);
           const cplx<T> D2 = {-D.x, D.y};
           const cplx<T> wD2 = cmul(cplx<T>{-w.x, w.y}, D2);
-          row[n - k] = {T(0.5) * (S2.x + wD2.y), T(0.5) * (S2.y - wD2.x)};
-          row[k] = Xk;
+          row[im] = {T(0.5) * (S2.x + wD2.y), T(0.5) * (S2.y - wD2.x)};
+          row[ik] = Xk;
         }
       }
     }
@@ -344,7 +365,7 @@ __global__ void __launch_bounds__(NT) row_pass(RowArgs<T> a) {
       cplx<T>* sp = a.out_spec[set] + (size_t)band * n * n + i0;
       for (int t = threadIdx.x; t < RB * n; t += NT) {
         const int kx = t / RB, r = t - kx * RB;
-        sp[(size_t)kx * n + r] = buf[r * stride + kx];
+        sp[(size_t)kx * n + r] = buf[r * stride + sw<T>(kx)];
       }
     } else {
       // unpacked n+1 columns of 2n rows: tmp[band][kx][row]
@@ -355,7 +376,7 @@ __global__ void __launch_bounds__(NT) row_pass(RowArgs<T> a) {
         cplx<T> v;
         if (kx == 0) v = {buf[r * stride].x, T(0)};
         else if (kx == n) v = {buf[r * stride].y, T(0)};
-        else v = buf[r * stride + kx];
+        else v = buf[r * stride + sw<T>(kx)];
         sp[(size_t)kx * m2 + r] = v;
       }
     }
@@ -370,7 +391,7 @@ struct ColArgs {
   const cplx<T>* in[kMaxSets];
   cplx<T>* out[kMaxSets];
   const cplx<T>* Kh;   // [L][n+1][2n]
-  const cplx<T>* tw;
+  const cplx<T>* twc;  // stage tables of the length-2n FFT
   int n, logn, L;
   int B;               // columns per block
   int conj;            // use conj(K)
@@ -382,34 +403,53 @@ __global__ void __launch_bounds__(NT) col_pass(ColArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n = a.n, m2 = 2 * n, B = a.B;
+  const int stride = sw_stride<T>(m2);
   const int lb = xcd_remap(blockIdx.x, a.nblocks);
   if (lb >= a.nblocks) return;
   const int set = blockIdx.y;
   const int cpb = n / B;  // column groups per band
   const int band = lb / cpb;
   const int kx0 = (lb - band * cpb) * B;
-  constexpr int EMAX = 16 * NT;  // B * 2n <= 4096
+  constexpr int EMAX = 8 * NT;  // B * 2n <= 8 NT (launcher's choice of NT)
+  constexpr int KPT = EMAX / NT;
   const cplx<T>* src = a.in[set] + ((size_t)band * n + kx0) * n;
   for (int t = threadIdx.x; t < B * m2; t += NT) {
     const int b = t / m2, i = t - b * m2;
-    buf[b * m2 + i] = i < n ? src[(size_t)b * n + i] : cplx<T>{T(0), T(0)};
+    buf[b * stride + sw<T>(i)] = i < n ? src[(size_t)b * n + i] : cplx<T>{T(0), T(0)};
+  }
+  // prefetch the transfer function of this thread's products (columns kx != 0)
+  const cplx<T>* Kb = a.Kh + (size_t)band * (n + 1) * m2;
+  cplx<T> kr[KPT];
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if (t < B * m2) {
+      const int b = t / m2, ky = t - b * m2;
+      const int kx = kx0 + b;
+      if (kx != 0) {
+        cplx<T> K = Kb[(size_t)kx * m2 + ky];
+        kr[q] = a.conj ? cconj(K) : K;
+      }
+    }
   }
   __syncthreads();
-  lds_fft<T, NT, EMAX>(buf, a.logn + 1, B, m2, a.tw, a.logn + 1);
-  const cplx<T>* Kb = a.Kh + (size_t)band * (n + 1) * m2;
-  for (int t = threadIdx.x; t < B * m2; t += NT) {
+  lds_fft<T, NT, EMAX>(buf, a.logn + 1, B, stride, a.twc);
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if (t >= B * m2) continue;
     const int b = t / m2, ky = t - b * m2;
     const int kx = kx0 + b;
-    cplx<T>* col = buf + b * m2;
+    cplx<T>* col = buf + b * stride;
     if (kx != 0) {
-      cplx<T> K = Kb[(size_t)kx * m2 + ky];
-      if (a.conj) K = cconj(K);
-      col[ky] = cconj(cmul(col[ky], K));
+      const int iy = sw<T>(ky);
+      col[iy] = cconj(cmul(col[iy], kr[q]));
     } else if (ky <= n) {
       // slot 0 packs two real columns (kx = 0 and kx = n) as p + i q;
       // G = 1/2 (F + conj F-) K0 + 1/2 (F - conj F-) Kn, pairs (ky, 2n - ky)
       const int kz = (m2 - ky) & (m2 - 1);
-      const cplx<T> F = col[ky], Fm = col[kz];
+      const int iy = sw<T>(ky), iz = sw<T>(kz);
+      const cplx<T> F = col[iy], Fm = col[iz];
       cplx<T> K0 = Kb[ky], Kn = Kb[(size_t)n * m2 + ky];
       cplx<T> K0m = Kb[kz], Knm = Kb[(size_t)n * m2 + kz];
       if (a.conj) {
@@ -422,17 +462,17 @@ __global__ void __launch_bounds__(NT) col_pass(ColArgs<T> a) {
         const cplx<T> Sm = cadd(Fm, cconj(F)), Dm = csub(Fm, cconj(F));
         cplx<T> Gm = cadd(cmul(Sm, K0m), cmul(Dm, Knm));
         Gm = {T(0.5) * Gm.x, T(0.5) * Gm.y};
-        col[kz] = cconj(Gm);
+        col[iz] = cconj(Gm);
       }
-      col[ky] = cconj(G);
+      col[iy] = cconj(G);
     }
   }
   __syncthreads();
-  lds_fft<T, NT, EMAX>(buf, a.logn + 1, B, m2, a.tw, a.logn + 1);
+  lds_fft<T, NT, EMAX>(buf, a.logn + 1, B, stride, a.twc);
   cplx<T>* dst = a.out[set] + ((size_t)band * n + kx0) * n;
   for (int t = threadIdx.x; t < B * n; t += NT) {
     const int b = t / n, i = t - b * n;
-    dst[(size_t)b * n + i] = cconj(buf[b * m2 + i]);
+    dst[(size_t)b * n + i] = cconj(buf[b * stride + sw<T>(i)]);
   }
 }
 
@@ -440,18 +480,18 @@ __global__ void __launch_bounds__(NT) col_pass(ColArgs<T> a) {
 // scaled by 1/(2n)^2 (the inverse-transform normalisation, folded into K).
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT) psf_cols(const cplx<T>* tmp, cplx<T>* Kh,
-                                               const cplx<T>* tw, int n, int logn) {
+                                               const cplx<T>* twc, int n, int logn) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int m2 = 2 * n;
   const int kx = blockIdx.x, band = blockIdx.y;
   const size_t off = ((size_t)band * (n + 1) + kx) * m2;
-  for (int i = threadIdx.x; i < m2; i += NT) buf[i] = tmp[off + i];
+  for (int i = threadIdx.x; i < m2; i += NT) buf[sw<T>(i)] = tmp[off + i];
   __syncthreads();
-  lds_fft<T, NT, 16 * NT>(buf, logn + 1, 1, m2, tw, logn + 1);
+  lds_fft<T, NT, 8 * NT>(buf, logn + 1, 1, sw_stride<T>(m2), twc);
   const T s = T(1.0 / (4.0 * double(n) * double(n)));
   for (int i = threadIdx.x; i < m2; i += NT) {
-    const cplx<T> v = buf[i];
+    const cplx<T> v = buf[sw<T>(i)];
     Kh[off + i] = {v.x * s, v.y * s};
   }
 }
@@ -459,17 +499,41 @@ __global__ void __launch_bounds__(NT) psf_cols(const cplx<T>* tmp, cplx<T>* Kh,
 // -------------------------------------------------------------------------
 // host side
 // -------------------------------------------------------------------------
-constexpr int kRowNT = 256;
-constexpr int kColNT = 256;
+constexpr int kRowNT = 512;
+// column blocks: 256 threads up to 2n = 2048 points, 512 for 4096 points
+// (8 elements per thread)
 
 template <typename T>
 static int row_rb(int n) {
-  // rows per block: keep RB * n <= 32 * NT and 64-byte transposed segments
-  const int emax = (sizeof(T) == 8 ? 16 : 32) * kRowNT;
+  const int emax = (sizeof(T) == 8 ? 16 : 32) * 256;
   int rb = sizeof(T) == 8 ? 4 : 8;
   while (rb > 1 && rb * n > emax) rb >>= 1;
   if (rb > n) rb = n;
   return rb;
+}
+
+// Stage twiddle tables of a length-2^lognf FFT in the order lds_fft reads
+// them: for every stage after the first, [k < Ns][r = 1..R-1] of
+// exp(-2 pi i r k / (Ns R)), computed in long double.
+template <typename T>
+static std::vector<cplx<T>> stage_tables(int lognf) {
+  std::vector<cplx<T>> out;
+  const long double pi = 3.14159265358979323846264338327950288L;
+  int done = 0;
+  while (done < lognf) {
+    const int lr = radix_log(lognf - done);
+    const int R = 1 << lr, Ns = 1 << done;
+    if (done > 0) {
+      for (int k = 0; k < Ns; ++k)
+        for (int r = 1; r < R; ++r) {
+          const long double ang = -2.0L * pi * (long double)(r * k) / (long double)(Ns * R);
+          out.push_back({T(cosl(ang)), T(sinl(ang))});
+        }
+    }
+    done += lr;
+  }
+  if (out.empty()) out.push_back({T(1), T(0)});
+  return out;
 }
 
 template <typename T>
@@ -477,16 +541,22 @@ int fft_make_plan(FftPlan<T>& p, int n, int L, hipStream_t s) {
   p.n = n;
   p.L = L;
   const int m2 = 2 * n;
+  const int logn = 31 - __builtin_clz(n);
   std::vector<cplx<T>> h(m2);
   for (int k = 0; k < m2; ++k) {
     const long double ang = -2.0L * 3.14159265358979323846264338327950288L * k / m2;
     h[k] = {T(cosl(ang)), T(sinl(ang))};
   }
-  MUFFIN_HIP_CHECK(hipMalloc(&p.tw, sizeof(cplx<T>) * m2));
-  MUFFIN_HIP_CHECK(hipMemcpyAsync(p.tw, h.data(), sizeof(cplx<T>) * m2,
-                                  hipMemcpyHostToDevice, s));
-  MUFFIN_HIP_CHECK(hipStreamSynchronize(s));
+  const std::vector<cplx<T>> tr = stage_tables<T>(logn);
+  const std::vector<cplx<T>> tc = stage_tables<T>(logn + 1);
+  MUFFIN_HIP_CHECK(hipMalloc(&p.tw, sizeof(cplx<T>) * (m2 + tr.size() + tc.size())));
+  p.twr = p.tw + m2;
+  p.twc = p.twr + tr.size();
+  MUFFIN_HIP_CHECK(hipMemcpy(p.tw, h.data(), sizeof(cplx<T>) * m2, hipMemcpyHostToDevice));
+  MUFFIN_HIP_CHECK(hipMemcpy(p.twr, tr.data(), sizeof(cplx<T>) * tr.size(), hipMemcpyHostToDevice));
+  MUFFIN_HIP_CHECK(hipMemcpy(p.twc, tc.data(), sizeof(cplx<T>) * tc.size(), hipMemcpyHostToDevice));
   MUFFIN_HIP_CHECK(hipMalloc(&p.Kh, sizeof(cplx<T>) * (size_t)L * (n + 1) * m2));
+  (void)s;
   return 0;
 }
 
@@ -494,7 +564,7 @@ template <typename T>
 void fft_free_plan(FftPlan<T>& p) {
   if (p.tw) (void)hipFree(p.tw);
   if (p.Kh) (void)hipFree(p.Kh);
-  p.tw = nullptr;
+  p.tw = p.twr = p.twc = nullptr;
   p.Kh = nullptr;
 }
 
@@ -502,7 +572,7 @@ template <typename T, int RB, int IN, int OUT>
 static int launch_row_rb(RowArgs<T>& a, int nsets, hipStream_t s) {
   const int n = a.n;
   a.nblocks = a.L * (a.rows / RB);
-  const size_t shm = sizeof(cplx<T>) * (size_t)RB * (n + 1);
+  const size_t shm = sizeof(cplx<T>) * (size_t)RB * sw_stride<T>(n);
   dim3 grid(xcd_grid(a.nblocks), nsets);
   MUFFIN_ALLOW_BIG_LDS((row_pass<T, RB, kRowNT, IN, OUT>));
   row_pass<T, RB, kRowNT, IN, OUT><<<grid, kRowNT, shm, s>>>(a);
@@ -521,7 +591,7 @@ static int launch_row(RowArgs<T>& a, int nsets, hipStream_t s) {
 }
 
 int fft_res_blocks(int n, int L, int elem_bytes) {
-  const int emax = (elem_bytes == 8 ? 16 : 32) * kRowNT;
+  const int emax = (elem_bytes == 8 ? 16 : 32) * 256;
   int rb = elem_bytes == 8 ? 4 : 8;
   while (rb > 1 && rb * n > emax) rb >>= 1;
   if (rb > n) rb = n;
@@ -537,7 +607,7 @@ static int launch_col(const FftPlan<T>& p, const cplx<T>* const* in, cplx<T>* co
     a.out[i] = out[i];
   }
   a.Kh = p.Kh;
-  a.tw = p.tw;
+  a.twc = p.twc;
   a.n = p.n;
   a.logn = 31 - __builtin_clz(p.n);
   a.L = p.L;
@@ -545,10 +615,15 @@ static int launch_col(const FftPlan<T>& p, const cplx<T>* const* in, cplx<T>* co
   if (a.B > p.n) a.B = p.n;
   a.conj = conj;
   a.nblocks = p.L * (p.n / a.B);
-  const size_t shm = sizeof(cplx<T>) * (size_t)a.B * 2 * p.n;
+  const size_t shm = sizeof(cplx<T>) * (size_t)a.B * sw_stride<T>(2 * p.n);
   dim3 grid(xcd_grid(a.nblocks), nsets);
-  MUFFIN_ALLOW_BIG_LDS((col_pass<T, kColNT>));
-  col_pass<T, kColNT><<<grid, kColNT, shm, s>>>(a);
+  if (2 * p.n <= 2048) {
+    MUFFIN_ALLOW_BIG_LDS((col_pass<T, 256>));
+    col_pass<T, 256><<<grid, 256, shm, s>>>(a);
+  } else {
+    MUFFIN_ALLOW_BIG_LDS((col_pass<T, 512>));
+    col_pass<T, 512><<<grid, 512, shm, s>>>(a);
+  }
   MUFFIN_HIP_CHECK(hipGetLastError());
   return 0;
 }
@@ -559,15 +634,21 @@ int fft_psf_spectrum(FftPlan<T>& p, const T* psf, cplx<T>* tmp, hipStream_t s) {
   a.in[0] = psf;
   a.out_spec[0] = tmp;
   a.tw = p.tw;
+  a.twr = p.twr;
   a.n = p.n;
   a.logn = 31 - __builtin_clz(p.n);
   a.L = p.L;
   a.rows = 2 * p.n;
   int rc = launch_row<T, IN_PSF, OUT_PSFTMP>(a, 1, s);
   if (rc) return rc;
-  const size_t shm = sizeof(cplx<T>) * 2 * p.n;
-  MUFFIN_ALLOW_BIG_LDS((psf_cols<T, kColNT>));
-  psf_cols<T, kColNT><<<dim3(p.n + 1, p.L), kColNT, shm, s>>>(tmp, p.Kh, p.tw, p.n, a.logn);
+  const size_t shm = sizeof(cplx<T>) * sw_stride<T>(2 * p.n);
+  if (2 * p.n <= 2048) {
+    MUFFIN_ALLOW_BIG_LDS((psf_cols<T, 256>));
+    psf_cols<T, 256><<<dim3(p.n + 1, p.L), 256, shm, s>>>(tmp, p.Kh, p.twc, p.n, a.logn);
+  } else {
+    MUFFIN_ALLOW_BIG_LDS((psf_cols<T, 512>));
+    psf_cols<T, 512><<<dim3(p.n + 1, p.L), 512, shm, s>>>(tmp, p.Kh, p.twc, p.n, a.logn);
+  }
   MUFFIN_HIP_CHECK(hipGetLastError());
   return 0;
 }
@@ -577,6 +658,7 @@ int fft_chain(const FftPlan<T>& p, const ChainIO<T>& io, int op, hipStream_t s) 
   const int ns = io.nsets;
   RowArgs<T> a{};
   a.tw = p.tw;
+  a.twr = p.twr;
   a.n = p.n;
   a.logn = 31 - __builtin_clz(p.n);
   a.L = p.L;

@@ -62,6 +62,8 @@ struct FftPlan {
   int n = 0;
   int L = 0;
   cplx<T>* tw = nullptr;   // tw[k] = exp(-2 pi i k / (2n)), k < 2n
+  cplx<T>* twr = nullptr;  // stage twiddle tables, length-n FFT (inside tw's block)
+  cplx<T>* twc = nullptr;  // stage twiddle tables, length-2n FFT
   cplx<T>* Kh = nullptr;   // [L][n+1][2n] transfer function / (4 n^2)
 };
 
@@ -158,8 +160,8 @@ struct DctPlan {
   int L = 0, Lp = 0, N = 0;
   int kind = 0;
   T* C = nullptr;            // [Lp][Lp] padded DCT-II matrix (row k, column l)
-  uint16_t* Chi = nullptr;   // bf16 split of C (BF16X3 only)
-  uint16_t* Clo = nullptr;
+  uint16_t* Chi = nullptr;   // bf16 hi/lo fragments of C and C^T (BF16X3 only)
+  uint16_t* Clo = nullptr;   // (inside Chi's allocation)
 };
 
 template <typename T>

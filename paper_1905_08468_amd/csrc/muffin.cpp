@@ -277,7 +277,9 @@ struct Impl final : ImplBase {
     dwt.P = P;
     dwt.J = J;
     RC(dwt_upload_filters(P));
-    RC(dct_make_plan(dct, L, N, sizeof(T) == 8 ? DCT_F64 : DCT_F32));
+    RC(dct_make_plan(dct, L, N,
+                      sizeof(T) == 8 ? DCT_F64
+                                     : (cfg.mode == MUFFIN_F32_BF16DCT ? DCT_BF16X3 : DCT_F32)));
     hp.sigma = cfg.sigma;
     hp.mu = cfg.mu;
     hp.gamma = cfg.gamma;

@@ -289,3 +289,101 @@ def test_error_codes():
         h.set_problem(bad, psf, np.ones(256), np.ones(2))
     assert e.value.code == -4
     h.close()
+
+
+# ---------------------------------------------- full-size launch configs --
+
+@pytest.mark.parametrize("mode", ["f64", "f32"])
+def test_full_side_operators(mode):
+    """n = 1024 (the benchmark's FFT, wavelet and tile configuration) on two
+    bands, element by element against the oracle."""
+    mm = _mm()
+    torch = _torch()
+    n, L = 1024, 2
+    m = mm.F64 if mode == "f64" else mm.F32
+    dt = torch.float64 if mode == "f64" else torch.float32
+    tol = 1e-12 if mode == "f64" else 3e-6
+    rng = np.random.default_rng(101)
+    prob = synth.make_problem(n, L, n_src=500, n_blob=20, n_base=20000, seed=101)
+    x = np.abs(rng.standard_normal((L, n, n)))
+    h = mm.Muffin(mm.default_config(n, L, mode=m, tau=1.0, pi_iters=0))
+    h.set_problem(dev(prob.dirty, dt), dev(prob.psf, dt), np.ones(n * n), np.ones(L))
+    xd = dev(x, dt)
+    xr = host(xd)
+    psf = host(dev(prob.psf, dt))
+    K = op.psf_spectrum(psf)
+    assert rel(host(h.op("HTH", xd)), op.HT(op.H(xr, K), K)) < tol
+    W = op.SpatialDictionary(8, 3)
+    u = h.op("Ws", xd)
+    assert rel(host(u), W.forward(xr)) < tol
+    assert rel(host(h.op("WsT", u)), W.adjoint(host(u))) < tol
+    h.close()
+
+
+def test_full_cube_dct_sampled_f32():
+    """1024^2 pixels x 256 bands (the benchmark's DCT configuration); sampled
+    pixel spectra against the oracle's DCT."""
+    mm = _mm()
+    torch = _torch()
+    n, L = 1024, 256
+    g = torch.Generator(device="cuda:0").manual_seed(5)
+    x = torch.randn((L, n, n), generator=g, device="cuda:0", dtype=torch.float32)
+    h = mm.Muffin(mm.default_config(n, L, mode=mm.F32))
+    y = h.op("dct", x)
+    z = h.op("idct", x)
+    idx = np.random.default_rng(6).choice(n * n, size=512, replace=False)
+    ii = torch.from_numpy(idx).to("cuda:0")
+    xs = x.reshape(L, -1)[:, ii].double().cpu().numpy()
+    ys = y.reshape(L, -1)[:, ii].double().cpu().numpy()
+    zs = z.reshape(L, -1)[:, ii].double().cpu().numpy()
+    assert rel(ys, op.Wl(xs)) < 3e-6
+    assert rel(zs, op.WlT(xs)) < 3e-6
+    h.close()
+
+
+# --------------------------------------------------------- precision forms --
+
+@pytest.mark.parametrize("L", [1, 7, 32, 40, 256])
+def test_dct_ops_bf16_split(L):
+    """BF16 hi+lo split DCT: ~2^-17 relative per product."""
+    mm = _mm()
+    torch = _torch()
+    n = 16
+    x = np.random.default_rng(L + 1).standard_normal((L, n, n))
+    h = mm.Muffin(mm.default_config(n, L, mode=mm.F32_BF16DCT))
+    xf = dev(x, torch.float32)
+    x32 = host(xf)
+    assert rel(host(h.op("dct", xf)), op.Wl(x32)) < 3e-5
+    assert rel(host(h.op("idct", xf)), op.WlT(x32)) < 3e-5
+    h.close()
+
+
+def test_c0_plain_bf16_form():
+    mm = _mm()
+    torch = _torch()
+    n, L, iters = 64, 8, 50
+    prob = synth.make_config("c0", seed=2)
+    alpha, beta = synth.random_weights(L, n, 2)
+    pb = om.make_problem(prob.dirty, prob.psf, P=8, J=3, alpha=alpha, beta=beta)
+    tau = safe_tau(prob.psf, 10.0, beta, alpha)
+    ref = om.run_muffin(pb, 1.0, 1.0, tau, iters)
+    h = mm.Muffin(_config(mm, n, L, mode=mm.F32_BF16DCT, mu=1.0, gamma=1.0, tau=tau, pi_iters=0))
+    h.set_problem(dev(prob.dirty, torch.float32), dev(prob.psf, torch.float32), alpha, beta)
+    h.run(iters)
+    err = rel(host(h.sky()), ref.X)
+    assert err < 1e-3, err
+    h.close()
+
+
+@pytest.mark.parametrize("form", ["f32", "bf16"])
+def test_adapt_reduced_precision_forms(form):
+    mm = _mm()
+    mode = mm.F32 if form == "f32" else mm.F32_BF16DCT
+    h, rep, ref = _adapt_case(mm, mode)
+    tol = 1e-5 if form == "f32" else 1e-3
+    assert rel(host(h.sky()), ref.X) < tol
+    # theta after the updates; SUGAR's finite-difference term amplifies
+    # rounding by 1/eps, so theta is compared at a looser bound
+    assert abs(rep["mu"] - ref.mu) <= 1e-3 * abs(ref.mu)
+    assert abs(rep["gamma"] - ref.gamma) <= 1e-3 * abs(ref.gamma)
+    h.close()
