@@ -14,8 +14,9 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-OUT = os.path.join(HERE, "libmuffin.so")
-BUILD = os.path.join(ROOT, "_build")
+OUT = os.environ.get("MUFFIN_BUILD_OUT", os.path.join(HERE, "libmuffin.so"))
+BUILD = os.environ.get("MUFFIN_BUILD_DIR", os.path.join(ROOT, "_build"))
+EXTRA = os.environ.get("MUFFIN_EXTRA_FLAGS", "").split()
 SOURCES = ["fft.hip", "dwt.hip", "dct.hip", "ew.hip", "muffin.cpp"]
 ARCH = os.environ.get("MUFFIN_ARCH", "gfx950")
 
@@ -36,7 +37,7 @@ def _hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), *FLAGS, *EXTRA, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-6000:]}")

@@ -27,6 +27,12 @@
 #include <cmath>
 #include <vector>
 
+// Row passes fetch the next state set's rows into registers while the
+// current set is transformed (1) or load each set when it is reached (0).
+#ifndef MUFFIN_ROW_PREFETCH
+#define MUFFIN_ROW_PREFETCH 0
+#endif
+
 namespace muffin {
 
 // -------------------------------------------------------------------------
@@ -87,9 +93,13 @@ __device__ __forceinline__ int sw(int x) {
 }
 template <typename T>
 __host__ __device__ constexpr int sw_stride(int nf) {
-  // padded length of one sequence, +1 so that consecutive sequences start on
-  // different banks (transposed accesses walk across sequences)
-  return nf - 1 + ((nf - 1) >> (sizeof(T) == 8 ? 3 : 4)) + 2;
+  // padded length of one sequence, rounded up to 8 mod 32 (FP32) or 4 mod
+  // 16 (FP64) complex values: the transposed accesses of the row passes
+  // (consecutive threads walk across sequences, then along them) then hit
+  // distinct banks
+  const int need = nf + ((nf - 1) >> (sizeof(T) == 8 ? 3 : 4));
+  const int mod = sizeof(T) == 8 ? 16 : 32, want = sizeof(T) == 8 ? 4 : 8;
+  return need + ((want - need % mod) + mod) % mod;
 }
 
 // Radix schedule shared by the device FFT and the host twiddle tables:
@@ -205,11 +215,49 @@ struct RowArgs {
   double* partials;
   int n, logn, L;
   int rows;             // rows per band: n, or 2n for the PSF pass
-  int nblocks;          // logical blocks per set
+  int nblocks;          // logical blocks (row blocks of all bands)
+  int nsets;            // state sets, processed in turn by every block
 };
 
+// Input element q of this thread for the row block (band, i0) of one set,
+// already in the layout the LDS buffer takes (IN_REAL: (x[2m], x[2m+1]) pairs
+// with the zero-padded half; IN_SPEC: packed spectrum read column-major).
+template <typename T, int RB, int NT, int IN>
+__device__ __forceinline__ cplx<T> row_input(const RowArgs<T>& a, int set, int band, int i0,
+                                             int t) {
+  const int n = a.n, logn = a.logn, half = n >> 1;
+  if constexpr (IN == IN_REAL) {
+    const int r = t >> logn, m = t & (n - 1);
+    if (m >= half) return {T(0), T(0)};
+    const T* p = a.in[set] + ((size_t)band * n + i0 + r) * n + 2 * m;
+    return {p[0], p[1]};
+  } else if constexpr (IN == IN_PSF) {
+    // row i of ifftshift(psf): psf[(i + n) mod 2n][(j + n) mod 2n]
+    const int m2 = 2 * n;
+    const int r = t >> logn, m = t & (n - 1);
+    const int row = (i0 + r + n) & (m2 - 1);
+    const int c0 = (2 * m + n) & (m2 - 1);
+    const T* p = a.in[set] + (size_t)band * m2 * m2 + (size_t)row * m2;
+    return {p[c0], p[(c0 + 1) & (m2 - 1)]};
+  } else {
+    const int kx = t / RB, r = t - kx * RB;
+    return a.in_spec[set][(size_t)band * n * n + (size_t)kx * n + i0 + r];
+  }
+}
+
+template <typename T, int RB, int IN>
+__device__ __forceinline__ int row_slot(int t, int n, int logn, int stride) {
+  if constexpr (IN == IN_SPEC) {
+    const int kx = t / RB, r = t - kx * RB;
+    return r * stride + sw<T>(kx);
+  } else {
+    return (t >> logn) * stride + sw<T>(t & (n - 1));
+  }
+}
+
+// two 512-thread blocks per CU (the LDS limit): at most 128 VGPRs
 template <typename T, int RB, int NT, int IN, int OUT>
-__global__ void __launch_bounds__(NT) row_pass(RowArgs<T> a) {
+__global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   __shared__ double red[NT / 64];
@@ -217,168 +265,168 @@ __global__ void __launch_bounds__(NT) row_pass(RowArgs<T> a) {
   const int stride = sw_stride<T>(n);
   const int lb = xcd_remap(blockIdx.x, a.nblocks);
   if (lb >= a.nblocks) return;
-  const int set = blockIdx.y;
   const int rblocks = a.rows / RB;
   const int band = lb / rblocks;
   const int i0 = (lb - band * rblocks) * RB;
   const int half = n >> 1;
   constexpr int EMAX = (sizeof(T) == 8 ? 16 : 32) * 256;
-
-  // ---- load ----
-  if constexpr (IN == IN_REAL) {
-    const T* x = a.in[set] + ((size_t)band * n + i0) * n;
-    for (int t = threadIdx.x; t < RB * n; t += NT) {
-      const int r = t >> logn, m = t & (n - 1);
-      cplx<T> z = {T(0), T(0)};
-      if (m < half) {
-        const T* p = x + (size_t)r * n + 2 * m;
-        z = {p[0], p[1]};
-      }
-      buf[r * stride + sw<T>(m)] = z;
-    }
-  } else if constexpr (IN == IN_PSF) {
-    // row i of ifftshift(psf): psf[(i + n) mod 2n][(j + n) mod 2n]
-    const int m2 = 2 * n;
-    const T* ps = a.in[set] + (size_t)band * m2 * m2;
-    for (int t = threadIdx.x; t < RB * n; t += NT) {
-      const int r = t >> logn, m = t & (n - 1);
-      const int row = (i0 + r + n) & (m2 - 1);
-      const int c0 = (2 * m + n) & (m2 - 1);
-      const T* p = ps + (size_t)row * m2;
-      buf[r * stride + sw<T>(m)] = {p[c0], p[(c0 + 1) & (m2 - 1)]};
-    }
-  } else {
-    // packed half spectrum, column-major: spec[kx][row]
-    const cplx<T>* sp = a.in_spec[set] + (size_t)band * n * n + i0;
-    for (int t = threadIdx.x; t < RB * n; t += NT) {
-      const int kx = t / RB, r = t - kx * RB;
-      buf[r * stride + sw<T>(kx)] = sp[(size_t)kx * n + r];
+  constexpr int EPT = (EMAX + NT - 1) / NT;  // staged input values per thread
+  const int nel = RB * n;
+  // the first set's input, then each set's input is fetched while the
+  // previous set is transformed
+#if MUFFIN_ROW_PREFETCH
+  cplx<T> pre[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if (t < nel) pre[q] = row_input<T, RB, NT, IN>(a, 0, band, i0, t);
+  }
+#endif
+  for (int set = 0; set < a.nsets; ++set) {
+#if MUFFIN_ROW_PREFETCH
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int t = threadIdx.x + q * NT;
+      if (t < nel) buf[row_slot<T, RB, IN>(t, n, logn, stride)] = pre[q];
     }
     __syncthreads();
-    // Hermitian pre-pass of the real inverse: with A = X[k], B = conj X[n-k],
-    // Z[k] = (A + B) + i exp(i pi k / n) (A - B); store conj Z for the
-    // inverse-by-forward FFT.  Pairs (k, n-k) are owned by one thread.
-    for (int t = threadIdx.x; t < RB * (half + 1); t += NT) {
-      const int r = t / (half + 1), k = t - r * (half + 1);
-      cplx<T>* row = buf + r * stride;
-      if (k == 0) {
-        const cplx<T> s = row[0];  // (X[0], X[n]) both real
-        const T a0 = s.x, an = s.y;
-        row[0] = {a0 + an, -(a0 - an)};  // conj((a0 + an) + i (a0 - an))
-      } else {
-        const cplx<T> w = cconj(a.tw[k]);  // exp(+i pi k / n)
-        const int ik = sw<T>(k), im = sw<T>(n - k);
-        const cplx<T> A = row[ik];
-        const cplx<T> B = cconj(row[im]);
-        const cplx<T> S = cadd(A, B), D = csub(A, B);
-        const cplx<T> wD = cmul(w, D);
-        const cplx<T> Zk = {S.x - wD.y, S.y + wD.x};
-        if (k == half) {
-          row[ik] = cconj(Zk);
-        } else {
-          // partner: A' = X[n-k], B' = conj X[k], w' = exp(i pi (n-k)/n) = -conj(w)
-          const cplx<T> S2 = cconj(S);  // A' + B' = conj(A + B)
-          const cplx<T> D2 = {-D.x, D.y};  // A' - B' = -conj(D)
-          const cplx<T> wD2 = cmul(cplx<T>{-w.x, w.y}, D2);
-          const cplx<T> Zm = {S2.x - wD2.y, S2.y + wD2.x};
-          row[ik] = cconj(Zk);
-          row[im] = cconj(Zm);
-        }
+    if (set + 1 < a.nsets) {
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int t = threadIdx.x + q * NT;
+        if (t < nel) pre[q] = row_input<T, RB, NT, IN>(a, set + 1, band, i0, t);
       }
     }
-  }
-  __syncthreads();
-
-  if constexpr (IN == IN_SPEC) {
-    lds_fft<T, NT, EMAX>(buf, logn, RB, stride, a.twr);
-    // z = conj(buf): x[2m] = z.x, x[2m+1] = z.y for m < n/2 (image window)
-    double acc = 0.0;
-    if constexpr (OUT == OUT_REAL) {
-      T* o = a.out[set] + ((size_t)band * n + i0) * n;
-      for (int t = threadIdx.x; t < RB * half; t += NT) {
-        const int r = t / half, m = t - r * half;
-        const cplx<T> z = buf[r * stride + sw<T>(m)];
-        T* p = o + (size_t)r * n + 2 * m;
-        p[0] = z.x;
-        p[1] = -z.y;
-      }
-      return;
-    } else {
-      const T* y = (a.y != nullptr && set == 0) ? a.y + ((size_t)band * n + i0) * n : nullptr;
-      for (int t = threadIdx.x; t < RB * n; t += NT) {
-        const int r = t >> logn, m = t & (n - 1);
-        cplx<T> z = {T(0), T(0)};
-        const int im = r * stride + sw<T>(m);
-        if (m < half) {
-          const cplx<T> c = buf[im];
-          z = {c.x, -c.y};
-          if (y != nullptr) {
-            const T* q = y + (size_t)r * n + 2 * m;
-            const double e0 = double(z.x) - double(q[0]);
-            const double e1 = double(z.y) - double(q[1]);
-            acc += e0 * e0 + e1 * e1;
+#else
+    for (int t = threadIdx.x; t < nel; t += NT)
+      buf[row_slot<T, RB, IN>(t, n, logn, stride)] = row_input<T, RB, NT, IN>(a, set, band, i0, t);
+    __syncthreads();
+#endif
+    if constexpr (IN == IN_SPEC) {
+      // Hermitian pre-pass of the real inverse: with A = X[k], B = conj X[n-k],
+      // Z[k] = (A + B) + i exp(i pi k / n) (A - B); store conj Z for the
+      // inverse-by-forward FFT.  Pairs (k, n-k) are owned by one thread.
+      for (int t = threadIdx.x; t < RB * (half + 1); t += NT) {
+        const int r = t / (half + 1), k = t - r * (half + 1);
+        cplx<T>* row = buf + r * stride;
+        if (k == 0) {
+          const cplx<T> sv = row[0];  // (X[0], X[n]) both real
+          const T a0 = sv.x, an = sv.y;
+          row[0] = {a0 + an, -(a0 - an)};  // conj((a0 + an) + i (a0 - an))
+        } else {
+          const cplx<T> w = cconj(a.tw[k]);  // exp(+i pi k / n)
+          const int ik = sw<T>(k), im = sw<T>(n - k);
+          const cplx<T> A = row[ik];
+          const cplx<T> B = cconj(row[im]);
+          const cplx<T> S = cadd(A, B), D = csub(A, B);
+          const cplx<T> wD = cmul(w, D);
+          const cplx<T> Zk = {S.x - wD.y, S.y + wD.x};
+          if (k == half) {
+            row[ik] = cconj(Zk);
+          } else {
+            // partner: A' = X[n-k], B' = conj X[k], w' = exp(i pi (n-k)/n) = -conj(w)
+            const cplx<T> S2 = cconj(S);     // A' + B' = conj(A + B)
+            const cplx<T> D2 = {-D.x, D.y};  // A' - B' = -conj(D)
+            const cplx<T> wD2 = cmul(cplx<T>{-w.x, w.y}, D2);
+            const cplx<T> Zm = {S2.x - wD2.y, S2.y + wD2.x};
+            row[ik] = cconj(Zk);
+            row[im] = cconj(Zm);
           }
         }
-        buf[im] = z;
-      }
-      if (a.partials != nullptr && set == 0) {
-        const double s = block_sum<NT>(acc, red);
-        if (threadIdx.x == 0) a.partials[lb] = s;
       }
       __syncthreads();
-    }
-  }
-
-  if constexpr (OUT == OUT_SPEC || OUT == OUT_PSFTMP) {
-    lds_fft<T, NT, EMAX>(buf, logn, RB, stride, a.twr);
-    // Hermitian post-pass of the real forward transform:
-    // X[k] = (Z[k] + conj Z[n-k]) / 2 - (i / 2) exp(-i pi k / n) (Z[k] - conj Z[n-k])
-    for (int t = threadIdx.x; t < RB * (half + 1); t += NT) {
-      const int r = t / (half + 1), k = t - r * (half + 1);
-      cplx<T>* row = buf + r * stride;
-      if (k == 0) {
-        const cplx<T> z = row[0];
-        row[0] = {z.x + z.y, z.x - z.y};  // (X[0], X[n]), both real
+      lds_fft<T, NT, EMAX>(buf, logn, RB, stride, a.twr);
+      // z = conj(buf): x[2m] = z.x, x[2m+1] = z.y for m < n/2 (image window)
+      if constexpr (OUT == OUT_REAL) {
+        T* o = a.out[set] + ((size_t)band * n + i0) * n;
+        for (int t = threadIdx.x; t < RB * half; t += NT) {
+          const int r = t / half, m = t - r * half;
+          const cplx<T> z = buf[r * stride + sw<T>(m)];
+          T* p = o + (size_t)r * n + 2 * m;
+          p[0] = z.x;
+          p[1] = -z.y;
+        }
+        __syncthreads();
+        continue;
       } else {
-        const cplx<T> w = a.tw[k];
-        const int ik = sw<T>(k), im = sw<T>(n - k);
-        const cplx<T> A = row[ik];
-        const cplx<T> B = cconj(row[im]);
-        const cplx<T> S = cadd(A, B), D = csub(A, B);
-        const cplx<T> wD = cmul(w, D);
-        // X = S/2 - (i/2) wD = (S.x + wD.y, S.y - wD.x) / 2
-        const cplx<T> Xk = {T(0.5) * (S.x + wD.y), T(0.5) * (S.y - wD.x)};
-        if (k == half) {
-          row[ik] = Xk;
+        double acc = 0.0;
+        const T* y = (a.y != nullptr && set == 0) ? a.y + ((size_t)band * n + i0) * n : nullptr;
+        for (int t = threadIdx.x; t < RB * n; t += NT) {
+          const int r = t >> logn, m = t & (n - 1);
+          cplx<T> z = {T(0), T(0)};
+          const int im = r * stride + sw<T>(m);
+          if (m < half) {
+            const cplx<T> c = buf[im];
+            z = {c.x, -c.y};
+            if (y != nullptr) {
+              const T* q = y + (size_t)r * n + 2 * m;
+              const double e0 = double(z.x) - double(q[0]);
+              const double e1 = double(z.y) - double(q[1]);
+              acc += e0 * e0 + e1 * e1;
+            }
+          }
+          buf[im] = z;
+        }
+        if (a.partials != nullptr && set == 0) {
+          const double sum = block_sum<NT>(acc, red);
+          if (threadIdx.x == 0) a.partials[lb] = sum;
+        }
+        __syncthreads();
+      }
+    }
+
+    if constexpr (OUT == OUT_SPEC || OUT == OUT_PSFTMP) {
+      lds_fft<T, NT, EMAX>(buf, logn, RB, stride, a.twr);
+      // Hermitian post-pass of the real forward transform:
+      // X[k] = (Z[k] + conj Z[n-k]) / 2 - (i / 2) exp(-i pi k / n) (Z[k] - conj Z[n-k])
+      for (int t = threadIdx.x; t < RB * (half + 1); t += NT) {
+        const int r = t / (half + 1), k = t - r * (half + 1);
+        cplx<T>* row = buf + r * stride;
+        if (k == 0) {
+          const cplx<T> z = row[0];
+          row[0] = {z.x + z.y, z.x - z.y};  // (X[0], X[n]), both real
         } else {
-          // partner twiddle exp(-i pi (n-k)/n) = -conj(w)
-          const cplx<T> S2 = cconj(S);
-          const cplx<T> D2 = {-D.x, D.y};
-          const cplx<T> wD2 = cmul(cplx<T>{-w.x, w.y}, D2);
-          row[im] = {T(0.5) * (S2.x + wD2.y), T(0.5) * (S2.y - wD2.x)};
-          row[ik] = Xk;
+          const cplx<T> w = a.tw[k];
+          const int ik = sw<T>(k), im = sw<T>(n - k);
+          const cplx<T> A = row[ik];
+          const cplx<T> B = cconj(row[im]);
+          const cplx<T> S = cadd(A, B), D = csub(A, B);
+          const cplx<T> wD = cmul(w, D);
+          // X = S/2 - (i/2) wD = (S.x + wD.y, S.y - wD.x) / 2
+          const cplx<T> Xk = {T(0.5) * (S.x + wD.y), T(0.5) * (S.y - wD.x)};
+          if (k == half) {
+            row[ik] = Xk;
+          } else {
+            // partner twiddle exp(-i pi (n-k)/n) = -conj(w)
+            const cplx<T> S2 = cconj(S);
+            const cplx<T> D2 = {-D.x, D.y};
+            const cplx<T> wD2 = cmul(cplx<T>{-w.x, w.y}, D2);
+            row[im] = {T(0.5) * (S2.x + wD2.y), T(0.5) * (S2.y - wD2.x)};
+            row[ik] = Xk;
+          }
         }
       }
-    }
-    __syncthreads();
-    if constexpr (OUT == OUT_SPEC) {
-      cplx<T>* sp = a.out_spec[set] + (size_t)band * n * n + i0;
-      for (int t = threadIdx.x; t < RB * n; t += NT) {
-        const int kx = t / RB, r = t - kx * RB;
-        sp[(size_t)kx * n + r] = buf[r * stride + sw<T>(kx)];
+      __syncthreads();
+      if constexpr (OUT == OUT_SPEC) {
+        cplx<T>* sp = a.out_spec[set] + (size_t)band * n * n + i0;
+        for (int t = threadIdx.x; t < RB * n; t += NT) {
+          const int kx = t / RB, r = t - kx * RB;
+          sp[(size_t)kx * n + r] = buf[r * stride + sw<T>(kx)];
+        }
+      } else {
+        // unpacked n+1 columns of 2n rows: tmp[band][kx][row]
+        const int m2 = 2 * n;
+        cplx<T>* sp = a.out_spec[set] + (size_t)band * (n + 1) * m2 + i0;
+        for (int t = threadIdx.x; t < RB * (n + 1); t += NT) {
+          const int kx = t / RB, r = t - kx * RB;
+          cplx<T> v;
+          if (kx == 0) v = {buf[r * stride].x, T(0)};
+          else if (kx == n) v = {buf[r * stride].y, T(0)};
+          else v = buf[r * stride + sw<T>(kx)];
+          sp[(size_t)kx * m2 + r] = v;
+        }
       }
-    } else {
-      // unpacked n+1 columns of 2n rows: tmp[band][kx][row]
-      const int m2 = 2 * n;
-      cplx<T>* sp = a.out_spec[set] + (size_t)band * (n + 1) * m2 + i0;
-      for (int t = threadIdx.x; t < RB * (n + 1); t += NT) {
-        const int kx = t / RB, r = t - kx * RB;
-        cplx<T> v;
-        if (kx == 0) v = {buf[r * stride].x, T(0)};
-        else if (kx == n) v = {buf[r * stride].y, T(0)};
-        else v = buf[r * stride + sw<T>(kx)];
-        sp[(size_t)kx * m2 + r] = v;
-      }
+      __syncthreads();
     }
   }
 }
@@ -396,83 +444,92 @@ struct ColArgs {
   int B;               // columns per block
   int conj;            // use conj(K)
   int nblocks;
+  int nsets;           // state sets, processed in turn with the same K
 };
 
 template <typename T, int NT>
-__global__ void __launch_bounds__(NT) col_pass(ColArgs<T> a) {
+__global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 4) col_pass(ColArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n = a.n, m2 = 2 * n, B = a.B;
   const int stride = sw_stride<T>(m2);
   const int lb = xcd_remap(blockIdx.x, a.nblocks);
   if (lb >= a.nblocks) return;
-  const int set = blockIdx.y;
   const int cpb = n / B;  // column groups per band
   const int band = lb / cpb;
   const int kx0 = (lb - band * cpb) * B;
   constexpr int EMAX = 8 * NT;  // B * 2n <= 8 NT (launcher's choice of NT)
-  constexpr int KPT = EMAX / NT;
-  const cplx<T>* src = a.in[set] + ((size_t)band * n + kx0) * n;
-  for (int t = threadIdx.x; t < B * m2; t += NT) {
-    const int b = t / m2, i = t - b * m2;
-    buf[b * stride + sw<T>(i)] = i < n ? src[(size_t)b * n + i] : cplx<T>{T(0), T(0)};
-  }
-  // prefetch the transfer function of this thread's products (columns kx != 0)
+  constexpr int IPT = EMAX / NT / 2;  // input values (the n non-zero rows) per thread
+  const int nin = B * n;
+  // transfer function of this block's columns: read from HBM for the first
+  // state set, from L2 for the following ones (same block, a few microseconds
+  // later)
   const cplx<T>* Kb = a.Kh + (size_t)band * (n + 1) * m2;
-  cplx<T> kr[KPT];
+  cplx<T> pre[IPT];
 #pragma unroll
-  for (int q = 0; q < KPT; ++q) {
+  for (int q = 0; q < IPT; ++q) {
     const int t = threadIdx.x + q * NT;
-    if (t < B * m2) {
+    if (t < nin) pre[q] = a.in[0][((size_t)band * n + kx0) * n + t];
+  }
+  for (int set = 0; set < a.nsets; ++set) {
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+      const int t = threadIdx.x + q * NT;
+      if (t < nin) {
+        const int b = t / n, i = t - b * n;
+        buf[b * stride + sw<T>(i)] = pre[q];
+        buf[b * stride + sw<T>(i + n)] = cplx<T>{T(0), T(0)};
+      }
+    }
+    __syncthreads();
+    if (set + 1 < a.nsets) {
+#pragma unroll
+      for (int q = 0; q < IPT; ++q) {
+        const int t = threadIdx.x + q * NT;
+        if (t < nin) pre[q] = a.in[set + 1][((size_t)band * n + kx0) * n + t];
+      }
+    }
+    lds_fft<T, NT, EMAX>(buf, a.logn + 1, B, stride, a.twc);
+    for (int t = threadIdx.x; t < B * m2; t += NT) {
       const int b = t / m2, ky = t - b * m2;
       const int kx = kx0 + b;
+      cplx<T>* col = buf + b * stride;
       if (kx != 0) {
+        const int iy = sw<T>(ky);
         cplx<T> K = Kb[(size_t)kx * m2 + ky];
-        kr[q] = a.conj ? cconj(K) : K;
+        if (a.conj) K = cconj(K);
+        col[iy] = cconj(cmul(col[iy], K));
+      } else if (ky <= n) {
+        // slot 0 packs two real columns (kx = 0 and kx = n) as p + i q;
+        // G = 1/2 (F + conj F-) K0 + 1/2 (F - conj F-) Kn, pairs (ky, 2n - ky)
+        const int kz = (m2 - ky) & (m2 - 1);
+        const int iy = sw<T>(ky), iz = sw<T>(kz);
+        const cplx<T> F = col[iy], Fm = col[iz];
+        cplx<T> K0 = Kb[ky], Kn = Kb[(size_t)n * m2 + ky];
+        cplx<T> K0m = Kb[kz], Knm = Kb[(size_t)n * m2 + kz];
+        if (a.conj) {
+          K0 = cconj(K0); Kn = cconj(Kn); K0m = cconj(K0m); Knm = cconj(Knm);
+        }
+        const cplx<T> Sp = cadd(F, cconj(Fm)), Dp = csub(F, cconj(Fm));
+        cplx<T> G = cadd(cmul(Sp, K0), cmul(Dp, Kn));
+        G = {T(0.5) * G.x, T(0.5) * G.y};
+        if (kz != ky) {
+          const cplx<T> Sm = cadd(Fm, cconj(F)), Dm = csub(Fm, cconj(F));
+          cplx<T> Gm = cadd(cmul(Sm, K0m), cmul(Dm, Knm));
+          Gm = {T(0.5) * Gm.x, T(0.5) * Gm.y};
+          col[iz] = cconj(Gm);
+        }
+        col[iy] = cconj(G);
       }
     }
-  }
-  __syncthreads();
-  lds_fft<T, NT, EMAX>(buf, a.logn + 1, B, stride, a.twc);
-#pragma unroll
-  for (int q = 0; q < KPT; ++q) {
-    const int t = threadIdx.x + q * NT;
-    if (t >= B * m2) continue;
-    const int b = t / m2, ky = t - b * m2;
-    const int kx = kx0 + b;
-    cplx<T>* col = buf + b * stride;
-    if (kx != 0) {
-      const int iy = sw<T>(ky);
-      col[iy] = cconj(cmul(col[iy], kr[q]));
-    } else if (ky <= n) {
-      // slot 0 packs two real columns (kx = 0 and kx = n) as p + i q;
-      // G = 1/2 (F + conj F-) K0 + 1/2 (F - conj F-) Kn, pairs (ky, 2n - ky)
-      const int kz = (m2 - ky) & (m2 - 1);
-      const int iy = sw<T>(ky), iz = sw<T>(kz);
-      const cplx<T> F = col[iy], Fm = col[iz];
-      cplx<T> K0 = Kb[ky], Kn = Kb[(size_t)n * m2 + ky];
-      cplx<T> K0m = Kb[kz], Knm = Kb[(size_t)n * m2 + kz];
-      if (a.conj) {
-        K0 = cconj(K0); Kn = cconj(Kn); K0m = cconj(K0m); Knm = cconj(Knm);
-      }
-      const cplx<T> Sp = cadd(F, cconj(Fm)), Dp = csub(F, cconj(Fm));
-      cplx<T> G = cadd(cmul(Sp, K0), cmul(Dp, Kn));
-      G = {T(0.5) * G.x, T(0.5) * G.y};
-      if (kz != ky) {
-        const cplx<T> Sm = cadd(Fm, cconj(F)), Dm = csub(Fm, cconj(F));
-        cplx<T> Gm = cadd(cmul(Sm, K0m), cmul(Dm, Knm));
-        Gm = {T(0.5) * Gm.x, T(0.5) * Gm.y};
-        col[iz] = cconj(Gm);
-      }
-      col[iy] = cconj(G);
+    __syncthreads();
+    lds_fft<T, NT, EMAX>(buf, a.logn + 1, B, stride, a.twc);
+    cplx<T>* dst = a.out[set] + ((size_t)band * n + kx0) * n;
+    for (int t = threadIdx.x; t < nin; t += NT) {
+      const int b = t / n, i = t - b * n;
+      dst[(size_t)b * n + i] = cconj(buf[b * stride + sw<T>(i)]);
     }
-  }
-  __syncthreads();
-  lds_fft<T, NT, EMAX>(buf, a.logn + 1, B, stride, a.twc);
-  cplx<T>* dst = a.out[set] + ((size_t)band * n + kx0) * n;
-  for (int t = threadIdx.x; t < B * n; t += NT) {
-    const int b = t / n, i = t - b * n;
-    dst[(size_t)b * n + i] = cconj(buf[b * stride + sw<T>(i)]);
+    __syncthreads();
   }
 }
 
@@ -572,8 +629,9 @@ template <typename T, int RB, int IN, int OUT>
 static int launch_row_rb(RowArgs<T>& a, int nsets, hipStream_t s) {
   const int n = a.n;
   a.nblocks = a.L * (a.rows / RB);
+  a.nsets = nsets;
   const size_t shm = sizeof(cplx<T>) * (size_t)RB * sw_stride<T>(n);
-  dim3 grid(xcd_grid(a.nblocks), nsets);
+  dim3 grid(xcd_grid(a.nblocks), 1);
   MUFFIN_ALLOW_BIG_LDS((row_pass<T, RB, kRowNT, IN, OUT>));
   row_pass<T, RB, kRowNT, IN, OUT><<<grid, kRowNT, shm, s>>>(a);
   MUFFIN_HIP_CHECK(hipGetLastError());
@@ -615,8 +673,9 @@ static int launch_col(const FftPlan<T>& p, const cplx<T>* const* in, cplx<T>* co
   if (a.B > p.n) a.B = p.n;
   a.conj = conj;
   a.nblocks = p.L * (p.n / a.B);
+  a.nsets = nsets;
   const size_t shm = sizeof(cplx<T>) * (size_t)a.B * sw_stride<T>(2 * p.n);
-  dim3 grid(xcd_grid(a.nblocks), nsets);
+  dim3 grid(xcd_grid(a.nblocks), 1);
   if (2 * p.n <= 2048) {
     MUFFIN_ALLOW_BIG_LDS((col_pass<T, 256>));
     col_pass<T, 256><<<grid, 256, shm, s>>>(a);

@@ -41,8 +41,7 @@ namespace {
 
 // Stages timed with HIP events when timing is on (muffin_set_timing).
 enum Stage {
-  ST_FFT_PRIMAL = 0,   // H^T H X for the primal sets (5 launches)
-  ST_FFT_DERIV,        // H^T H X' for the derivative sets
+  ST_FFT = 0,          // H^T H X for all sets (5 launches)
   ST_SYN_DEEP,         // synthesis levels J..2
   ST_SYN_L1,           // synthesis level 1 (one launch, all sets)
   ST_PRIMAL,           // primal step (one launch)
@@ -57,7 +56,7 @@ enum Stage {
 };
 
 const char* const kStageNames[ST_COUNT] = {
-    "fft_chain_primal", "fft_chain_deriv", "synthesis_deep", "synthesis_l1",
+    "fft_chain", "synthesis_deep", "synthesis_l1",
     "primal_step",      "analysis_l1_primal", "analysis_deep_primal", "analysis_l1_deriv",
     "analysis_deep_deriv", "dct_primal", "dct_deriv", "window_update"};
 
@@ -486,22 +485,19 @@ struct Impl final : ImplBase {
   // -- one iteration ---------------------------------------------------
   int iterate() {
     const bool sure = cfg.sure != 0;
-    // 1. H^T H X for every set
+    // 1. H^T H X for every set (one chain: the transfer function is read
+    //    once per column for all sets)
     {
-      const int sets[2] = {0, 1};
-      const T* in[2] = {X[0], X[1]};
-      T* out[2] = {G[0], G[1]};
-      tm.begin(ST_FFT_PRIMAL, st);
-      RC(chain(in, out, sets, sure ? 2 : 1, 2));
-      tm.end(st);
-      if (sure) {
-        const int ds[4] = {2, 3, 4, 5};
-        const T* din[4] = {X[2], X[3], X[4], X[5]};
-        T* dout[4] = {G[2], G[3], G[4], G[5]};
-        tm.begin(ST_FFT_DERIV, st);
-        RC(chain(din, dout, ds, 4, 2));
-        tm.end(st);
+      const int sets[kMaxSets] = {0, 1, 2, 3, 4, 5};
+      const T* in[kMaxSets];
+      T* out[kMaxSets];
+      for (int s = 0; s < nsets; ++s) {
+        in[s] = X[s];
+        out[s] = G[s];
       }
+      tm.begin(ST_FFT, st);
+      RC(chain(in, out, sets, nsets, 2));
+      tm.end(st);
     }
     // 2. synthesis
     {

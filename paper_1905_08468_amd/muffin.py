@@ -14,7 +14,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmuffin.so")
+LIB_PATH = os.environ.get("MUFFIN_LIB", os.path.join(_HERE, "libmuffin.so"))
 
 F64, F32, F32_BF16DCT = 0, 1, 2
 TAU_OPNORM, TAU_PAPER_SUM = 0, 1
