@@ -182,9 +182,9 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_kernel(DctArgs<T> a) {
   const T sg = T(dp->sigma);
   const T d1 = T(dct_coef(a.d1_sel[set], dp));
   const T d2 = T(dct_coef(a.d2_sel[set], dp));
-  T* V = a.V[set];
-  const T* Vb = a.Vb[set];
-  uint8_t* M = a.mask[set];
+  T* __restrict__ V = a.V[set];
+  const T* __restrict__ Vb = a.Vb[set];
+  uint8_t* __restrict__ M = a.mask[set];
   T al[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) {
@@ -195,6 +195,25 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_kernel(DctArgs<T> a) {
   for (int i = 0; i < kDctKtPerWave; ++i) {
     const int kt = wave + kDctWaves * i;
     if (kt < nkt) {
+      T vold[G][4], vbv[G][4];
+      uint8_t mk[G][4];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int pix = pix0 + 16 * g + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = kt * 16 + out_row<T>(lk, r);
+          vold[g][r] = T(0);
+          vbv[g][r] = T(0);
+          mk[g][r] = 0;
+          if (k < L && pix < N) {
+            const size_t idx = (size_t)k * N + pix;
+            vold[g][r] = V[idx];
+            if (Vb) vbv[g][r] = Vb[idx];
+            if (a.role != ROLE_PRIMAL) mk[g][r] = M[idx];
+          }
+        }
+      }
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         const int pix = pix0 + 16 * g + lr;
@@ -204,17 +223,16 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_kernel(DctArgs<T> a) {
           T bv = T(0);
           if (k < L && pix < N) {
             const size_t idx = (size_t)k * N + pix;
-            const T vt = V[idx] + sg * al[g] * acc[i][g][r];
+            const T vt = vold[g][r] + sg * al[g] * acc[i][g][r];
             T vn;
             if (a.role == ROLE_PRIMAL) {
               vn = vt < T(-1) ? T(-1) : (vt > T(1) ? T(1) : vt);
               if (M) M[idx] = (vt >= T(-1) && vt <= T(1)) ? 1 : 0;
             } else {
-              vn = M[idx] ? vt : T(0);
+              vn = mk[g][r] ? vt : T(0);
             }
             V[idx] = vn;
-            bv = d1 * vn;
-            if (Vb) bv += d2 * Vb[idx];
+            bv = d1 * vn + d2 * vbv[g][r];
           }
           Z[k * PIX + 16 * g + lr] = bv;
         }
@@ -272,6 +290,7 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_kernel(DctArgs<T> a) {
 // 16-byte read.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 struct DctBfArgs {
   const float* xt_a[kMaxSets];
@@ -321,23 +340,32 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_bf16_kernel(DctBfArgs a) {
     const float* xa = a.x_a[set];
     const float* tb = a.xt_b[set];
     const float* xb = a.x_b[set];
-    for (int t = threadIdx.x; t < Lp * kBfPix; t += 64 * kDctWaves) {
-      const int l = t / kBfPix, j = t - l * kBfPix;
+    // each thread converts 8 consecutive bands of one pixel and stores them
+    // as one 16-byte hi and one 16-byte lo vector
+    for (int t = threadIdx.x; t < (Lp / 8) * kBfPix; t += 64 * kDctWaves) {
+      const int lg = t / kBfPix, j = t - lg * kBfPix;
       const int pix = pix0 + j;
-      float z = 0.f;
-      if (l < L && pix < N) {
-        const size_t idx = (size_t)l * N + pix;
-        if (a.pure) {
-          z = xa[idx];
-        } else {
-          z = float(c1) * (2.f * ta[idx] - xa[idx]);
-          if (xb) z += float(c2) * (2.f * tb[idx] - xb[idx]);
+      bf16x8 vh, vl;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int l = 8 * lg + e;
+        float z = 0.f;
+        if (l < L && pix < N) {
+          const size_t idx = (size_t)l * N + pix;
+          if (a.pure) {
+            z = xa[idx];
+          } else {
+            z = float(c1) * (2.f * ta[idx] - xa[idx]);
+            if (xb) z += float(c2) * (2.f * tb[idx] - xb[idx]);
+          }
         }
+        __bf16 h, lo;
+        split_bf16(z, h, lo);
+        vh[e] = h;
+        vl[e] = lo;
       }
-      __bf16 h, lo;
-      split_bf16(z, h, lo);
-      Zh[j * LpS + l] = h;
-      Zl[j * LpS + l] = lo;
+      *reinterpret_cast<bf16x8*>(Zh + j * LpS + 8 * lg) = vh;
+      *reinterpret_cast<bf16x8*>(Zl + j * LpS + 8 * lg) = vl;
     }
   }
   __syncthreads();
@@ -394,9 +422,9 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_bf16_kernel(DctBfArgs a) {
   const float sg = float(dp->sigma);
   const float d1 = float(dct_coef(a.d1_sel[set], dp));
   const float d2 = float(dct_coef(a.d2_sel[set], dp));
-  float* V = a.V[set];
-  const float* Vb = a.Vb[set];
-  uint8_t* M = a.mask[set];
+  float* __restrict__ V = a.V[set];
+  const float* __restrict__ Vb = a.Vb[set];
+  uint8_t* __restrict__ M = a.mask[set];
   float al[kBfG];
 #pragma unroll
   for (int g = 0; g < kBfG; ++g) {
@@ -407,32 +435,55 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_bf16_kernel(DctBfArgs a) {
   for (int i = 0; i < kDctKtPerWave; ++i) {
     const int kt = wave + kDctWaves * i;
     if (kt < nkt) {
+      // phase 1: every operand of this k-tile in flight at once
+      float vold[kBfG][4], vbv[kBfG][4];
+      uint8_t mk[kBfG][4];
 #pragma unroll
       for (int g = 0; g < kBfG; ++g) {
         const int pix = pix0 + 16 * g + lr;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int k = kt * 16 + 4 * lk + r;
+          vold[g][r] = 0.f;
+          vbv[g][r] = 0.f;
+          mk[g][r] = 0;
+          if (k < L && pix < N) {
+            const size_t idx = (size_t)k * N + pix;
+            vold[g][r] = V[idx];
+            if (Vb) vbv[g][r] = Vb[idx];
+            if (a.role != ROLE_PRIMAL) mk[g][r] = M[idx];
+          }
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < kBfG; ++g) {
+        const int pix = pix0 + 16 * g + lr;
+        bf16x4 qh, ql;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = kt * 16 + 4 * lk + r;
           float bv = 0.f;
           if (k < L && pix < N) {
             const size_t idx = (size_t)k * N + pix;
-            const float vt = V[idx] + sg * al[g] * acc[i][g][r];
+            const float vt = vold[g][r] + sg * al[g] * acc[i][g][r];
             float vn;
             if (a.role == ROLE_PRIMAL) {
               vn = vt < -1.f ? -1.f : (vt > 1.f ? 1.f : vt);
               if (M) M[idx] = (vt >= -1.f && vt <= 1.f) ? 1 : 0;
             } else {
-              vn = M[idx] ? vt : 0.f;
+              vn = mk[g][r] ? vt : 0.f;
             }
             V[idx] = vn;
-            bv = d1 * vn;
-            if (Vb) bv += d2 * Vb[idx];
+            bv = d1 * vn + d2 * vbv[g][r];
           }
           __bf16 h, lo;
           split_bf16(bv, h, lo);
-          Zh[(16 * g + lr) * LpS + k] = h;
-          Zl[(16 * g + lr) * LpS + k] = lo;
+          qh[r] = h;
+          ql[r] = lo;
         }
+        // the 4 results of a lane are 4 consecutive bands of one pixel
+        *reinterpret_cast<bf16x4*>(Zh + (16 * g + lr) * LpS + kt * 16 + 4 * lk) = qh;
+        *reinterpret_cast<bf16x4*>(Zl + (16 * g + lr) * LpS + kt * 16 + 4 * lk) = ql;
       }
     }
   }

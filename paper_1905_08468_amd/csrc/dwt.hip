@@ -497,26 +497,6 @@ __device__ __forceinline__ void sy_rows(const T* rbuf, T (&acc)[2][2]) {
   }
 }
 
-// One value of the quadrant tile of basis pidx for LDS slot t (periodic wrap;
-// the low-low quadrant comes from the coarser level's output when there is one).
-template <typename T, int TC>
-__device__ __forceinline__ T sy_tile_value(const SyArgs<T>& a, int set, int band, int pidx,
-                                           int t, int kr0, int kc0, double a1, double a2) {
-  constexpr int W = TC + kSHal;
-  const int n = a.n, half = a.Ms >> 1, hm = half - 1;
-  const int quad = t / (W * W), rem = t - quad * W * W;
-  const int r = rem / W, c = rem - r * W;
-  const int kr = (kr0 - kSHal + r) & hm, kc = (kc0 - kSHal + c) & hm;
-  if (quad == 0 && a.level < a.J)
-    return a.llin[set][((size_t)band * a.P + pidx) * (size_t)half * half + (size_t)kr * half + kc];
-  const int roff = (quad & 1) ? half : 0, coff = (quad & 2) ? half : 0;
-  const size_t idx = ((size_t)band * a.P + pidx) * ((size_t)n * n) + (size_t)(roff + kr) * n +
-                     (coff + kc);
-  T v = T(a1) * a.Ua[set][idx];
-  if (a.Ub[set]) v += T(a2) * a.Ub[set][idx];
-  return v;
-}
-
 template <typename T, int TC, int NT>
 __global__ void __launch_bounds__(NT) dwt_sy(SyArgs<T> a) {
   constexpr int W = TC + kSHal;
@@ -531,27 +511,65 @@ __global__ void __launch_bounds__(NT) dwt_sy(SyArgs<T> a) {
   const int kr0 = (tile / a.tiles) * TC, kc0 = (tile % a.tiles) * TC;
   const int set = a.level == 1 ? blockIdx.y : blockIdx.y / a.P;
   const int pone = a.level == 1 ? -1 : blockIdx.y % a.P;
-  const int n = a.n, Ms = a.Ms;
+  const int n = a.n, Ms = a.Ms, half = Ms >> 1, hm = half - 1;
   const size_t plane = (size_t)n * n;
   const double a1 = a.pure ? 1.0 : coef_of(a.a1_sel[set], a.dp);
   const double a2 = a.pure ? 0.0 : coef_of(a.a2_sel[set], a.dp);
   const int p0 = a.level == 1 ? 0 : pone;
   const int p1 = a.level == 1 ? a.P : pone + 1;
+  const bool has_ll = a.level < a.J;
+  // Offsets of this thread's tile values inside one basis plane (periodic
+  // wrap), computed once: the low-low quadrant reads the coarser level's
+  // output (offset in a half x half plane, flagged by a negative value) when
+  // there is one, the other quadrants read U.
+  int off[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const int t = threadIdx.x + i * NT;
+    const int quad = t / (W * W), rem = t - quad * W * W;
+    const int r = rem / W, c = rem - r * W;
+    const int kr = (kr0 - kSHal + r) & hm, kc = (kc0 - kSHal + c) & hm;
+    if (quad == 0 && has_ll) {
+      off[i] = -1 - (kr * half + kc);
+    } else {
+      const int roff = (quad & 1) ? half : 0, coff = (quad & 2) ? half : 0;
+      off[i] = (roff + kr) * n + (coff + kc);
+    }
+  }
+  const T ta1 = T(a1), ta2 = T(a2);
+  auto fetch = [&](int pidx, T (&v)[NQ]) {
+    const T* Ua = a.Ua[set] + ((size_t)band * a.P + pidx) * plane;
+    const T* Ub = a.Ub[set] ? a.Ub[set] + ((size_t)band * a.P + pidx) * plane : nullptr;
+    const T* ll = has_ll ? a.llin[set] + ((size_t)band * a.P + pidx) * (size_t)half * half
+                         : nullptr;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int t = threadIdx.x + i * NT;
+      if (t < 4 * W * W) {
+        const int o = off[i];
+        if (o < 0) {
+          v[i] = ll[-1 - o];
+        } else {
+          T x = ta1 * Ua[o];
+          if (Ub) x += ta2 * Ub[o];
+          v[i] = x;
+        }
+      }
+    }
+  };
   T acc[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
-  // tile of the first basis straight to LDS
-  for (int t = threadIdx.x; t < 4 * W * W; t += NT)
-    s_q[t] = sy_tile_value<T, TC>(a, set, band, p0, t, kr0, kc0, a1, a2);
-  __syncthreads();
   T nxt[NQ];
+  fetch(p0, nxt);
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const int t = threadIdx.x + i * NT;
+    if (t < 4 * W * W) s_q[t] = nxt[i];
+  }
+  __syncthreads();
 #define MUFFIN_SY_STEP(PB)                                                        \
   if (PB - 1 >= p0 && PB - 1 < p1) {                                              \
     const bool more = PB < p1;                                                    \
-    if (more) {                                                                   \
-      _Pragma("unroll") for (int i = 0; i < NQ; ++i) {                            \
-        const int t = threadIdx.x + i * NT;                                       \
-        if (t < 4 * W * W) nxt[i] = sy_tile_value<T, TC>(a, set, band, PB, t, kr0, kc0, a1, a2); \
-      }                                                                           \
-    }                                                                             \
+    if (more) fetch(PB, nxt);                                                     \
     sy_cols<T, TC, NT, PB>(s_q, s_r);                                             \
     __syncthreads();                                                              \
     sy_rows<T, TC, NT, PB>(s_r, acc);                                             \

@@ -36,20 +36,35 @@ __global__ void __launch_bounds__(kEwNT) primal_kernel(PrimalIO<T> io, size_t co
                                                        const DevParams* dp) {
   const int tr = blockIdx.y;
   const T tau = T(dp->tau);
-  const T* x0 = io.x[tr][0];
-  const T* g0 = io.g[tr][0];
-  const T* hy = io.hty[tr];
-  const T* s0 = io.s[tr][0];
-  const T* t0 = io.t[tr][0];
-  T* o0 = io.xt[tr][0];
+  const T* __restrict__ x0 = io.x[tr][0];
+  const T* __restrict__ g0 = io.g[tr][0];
+  const T* __restrict__ hy = io.hty[tr];
+  const T* __restrict__ s0 = io.s[tr][0];
+  const T* __restrict__ t0 = io.t[tr][0];
+  T* __restrict__ o0 = io.xt[tr][0];
+  const int nd = io.nderiv;
   for (size_t i = blockIdx.x * (size_t)kEwNT + threadIdx.x; i < count;
        i += (size_t)gridDim.x * kEwNT) {
+    // all loads of this element first (primal and both derivative sets)
+    T xd[2], gd[2], sd[2], td[2];
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      if (d < nd) {
+        xd[d] = io.x[tr][d + 1][i];
+        gd[d] = io.g[tr][d + 1][i];
+        sd[d] = io.s[tr][d + 1][i];
+        td[d] = io.t[tr][d + 1][i];
+      }
+    }
     const T m = x0[i] - tau * ((g0[i] - hy[i]) + s0[i] + t0[i]);
     const bool pos = m > T(0);
     o0[i] = pos ? m : T(0);
-    for (int d = 1; d <= io.nderiv; ++d) {
-      const T md = io.x[tr][d][i] - tau * (io.g[tr][d][i] + io.s[tr][d][i] + io.t[tr][d][i]);
-      io.xt[tr][d][i] = pos ? md : T(0);
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      if (d < nd) {
+        const T md = xd[d] - tau * (gd[d] + sd[d] + td[d]);
+        io.xt[tr][d + 1][i] = pos ? md : T(0);
+      }
     }
   }
 }

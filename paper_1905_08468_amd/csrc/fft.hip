@@ -121,19 +121,30 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int lognf, int logNs, in
   const int lognbf = lognf - LOGR;
   const int nbf = 1 << lognbf;
   const int total = nbf * batch;
+  const int Ns = 1 << logNs;
+  // With few elements per thread the twiddles are fetched before the
+  // barrier (they depend only on the thread's index, so their L2 latency
+  // overlaps the LDS loads and the barrier); with many, after it, to keep
+  // register pressure down.
+  constexpr bool HOIST = EMAX / NT <= 8;
   cplx<T> v[MAXQ][R];
+  cplx<T> w[HOIST ? MAXQ : 1][R - 1];
 #pragma unroll
   for (int q = 0; q < MAXQ; ++q) {
     const int t = threadIdx.x + q * NT;
     if (t < total) {
       const int b = t >> lognbf, j = t & (nbf - 1);
+      if (HOIST && logNs > 0) {
+        const int k = j & (Ns - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[q][r - 1] = tws[k * (R - 1) + r - 1];
+      }
       const cplx<T>* src = buf + b * stride;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = src[sw<T>(j + r * nbf)];
     }
   }
   __syncthreads();
-  const int Ns = 1 << logNs;
 #pragma unroll
   for (int q = 0; q < MAXQ; ++q) {
     const int t = threadIdx.x + q * NT;
@@ -141,9 +152,14 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int lognf, int logNs, in
       const int b = t >> lognbf, j = t & (nbf - 1);
       const int k = j & (Ns - 1);
       if (logNs > 0) {
-        const cplx<T>* w = tws + k * (R - 1);
+        if constexpr (HOIST) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[r - 1]);
+          for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[q][r - 1]);
+        } else {
+          const cplx<T>* tw = tws + k * (R - 1);
+#pragma unroll
+          for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[r - 1]);
+        }
       }
       dft_small<T, R>(v[q]);
       cplx<T>* dst = buf + b * stride;
