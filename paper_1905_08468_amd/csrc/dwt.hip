@@ -302,7 +302,10 @@ __device__ __forceinline__ void an_cols(const AnArgs<T>& a, const T* rowbuf, int
   }
 }
 
-template <typename T, int TO, int NT>
+// DEEP = false: level 1 (one staged image tile for all bases); true: the
+// coarser levels (one low-low tile per basis).  Separate instantiations keep
+// the level-1 kernel's register budget free of the per-basis staging.
+template <typename T, int TO, int NT, bool DEEP>
 __global__ void __launch_bounds__(NT) dwt_an(AnArgs<T> a) {
   static_assert((TO / 2) * (2 * TO) == NT, "one thread per column-filter output quad");
   constexpr int IN = 2 * TO + kHalo;
@@ -314,12 +317,13 @@ __global__ void __launch_bounds__(NT) dwt_an(AnArgs<T> a) {
   const int band = lb / tiles2;
   const int tile = lb - band * tiles2;
   const int kr0 = (tile / a.tiles) * TO, kc0 = (tile % a.tiles) * TO;
-  const int set = a.level == 1 ? blockIdx.y : blockIdx.y / a.P;
-  const int pone = a.level == 1 ? -1 : blockIdx.y % a.P;
+  const int set = blockIdx.y;
   const int Ms = a.Ms, msk = Ms - 1, half = Ms >> 1;
   const int n = a.n;
-  const int p0 = a.level == 1 ? 0 : pone;
-  const int p1 = a.level == 1 ? a.P : pone + 1;
+  // Every block runs through all bases: at level 1 they filter the same
+  // staged image tile, at the coarser levels each basis filters its own
+  // low-low band (the next one is fetched while the current one is filtered).
+  const int p0 = 0, p1 = a.P;
   // ---- prefetch the dual values and masks this thread updates ----
   T u[kMaxBases][4];
   uint8_t m[kMaxBases][4];
@@ -347,8 +351,27 @@ __global__ void __launch_bounds__(NT) dwt_an(AnArgs<T> a) {
       }
     }
   }
+  // ---- coarser levels: this thread's tile offsets in a basis' LL plane ----
+  constexpr int NI = (IN * IN + NT - 1) / NT;
+  int ioff[NI];
+  T nxt[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int t = threadIdx.x + i * NT;
+    const int r = t / IN, c = t - r * IN;
+    ioff[i] = ((2 * kr0 + r) & msk) * Ms + ((2 * kc0 + c) & msk);
+  }
+  auto fetch_ll = [&](int pidx) {
+    const T* src = a.llin[set] + ((size_t)band * a.P + pidx) * (size_t)Ms * Ms;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int t = threadIdx.x + i * NT;
+      if (t < IN * IN) nxt[i] = src[ioff[i]];
+    }
+  };
+  if constexpr (DEEP) fetch_ll(0);
   // ---- stage the input tile (periodic wrap) ----
-  if (a.level == 1) {
+  if constexpr (!DEEP) {
     const double c1 = coef_of(a.c1_sel[set], a.dp), c2 = coef_of(a.c2_sel[set], a.dp);
     const T* xa = a.x_a[set] + (size_t)band * plane;
     const T* ta = a.xt_a[set] + (size_t)band * plane;
@@ -362,10 +385,10 @@ __global__ void __launch_bounds__(NT) dwt_an(AnArgs<T> a) {
       s_in[t] = z;
     }
   } else {
-    const T* src = a.llin[set] + ((size_t)band * a.P + pone) * (size_t)Ms * Ms;
-    for (int t = threadIdx.x; t < IN * IN; t += NT) {
-      const int r = t / IN, c = t - r * IN;
-      s_in[t] = src[(size_t)((2 * kr0 + r) & msk) * Ms + ((2 * kc0 + c) & msk)];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int t = threadIdx.x + i * NT;
+      if (t < IN * IN) s_in[t] = nxt[i];
     }
   }
   __syncthreads();
@@ -373,10 +396,18 @@ __global__ void __launch_bounds__(NT) dwt_an(AnArgs<T> a) {
   const double scale = a.dp ? a.dp->sigma * beta / sqrt((double)a.P) : 0.0;
 #define MUFFIN_AN_STEP(PB)                                                      \
   if (PB - 1 >= p0 && PB - 1 < p1) {                                            \
+    const bool more = DEEP && PB < p1;                                          \
+    if (more) fetch_ll(PB);                                                     \
     an_rows<T, TO, NT, PB>(s_in, s_row, IN);                                    \
     __syncthreads();                                                            \
     an_cols<T, TO, NT, PB>(a, s_row, set, band, kr0, kc0, scale, u[PB - 1],     \
                            m[PB - 1]);                                          \
+    if (more) {                                                                 \
+      _Pragma("unroll") for (int i = 0; i < NI; ++i) {                          \
+        const int t = threadIdx.x + i * NT;                                     \
+        if (t < IN * IN) s_in[t] = nxt[i];                                      \
+      }                                                                         \
+    }                                                                           \
     __syncthreads();                                                            \
   }
   MUFFIN_AN_STEP(1)
@@ -497,7 +528,27 @@ __device__ __forceinline__ void sy_rows(const T* rbuf, T (&acc)[2][2]) {
   }
 }
 
-template <typename T, int TC, int NT>
+// Stores a thread's output quad (acc[b][e] -> dst[2 b + e]) scaled by sc;
+// only the first pair when the row ends after it.
+template <typename T>
+__device__ __forceinline__ void store4(T* dst, const T (&acc)[2][2], T sc, bool full) {
+  if (full) {
+    if constexpr (sizeof(T) == 4) {
+      *reinterpret_cast<float4*>(dst) =
+          make_float4(sc * acc[0][0], sc * acc[0][1], sc * acc[1][0], sc * acc[1][1]);
+    } else {
+      reinterpret_cast<double2*>(dst)[0] = make_double2(sc * acc[0][0], sc * acc[0][1]);
+      reinterpret_cast<double2*>(dst)[1] = make_double2(sc * acc[1][0], sc * acc[1][1]);
+    }
+  } else {
+    dst[0] = sc * acc[0][0];
+    dst[1] = sc * acc[0][1];
+  }
+}
+
+// DEEP = false: level 1 (the bases' syntheses summed into S); true: the
+// coarser levels (one output per basis).
+template <typename T, int TC, int NT, bool DEEP>
 __global__ void __launch_bounds__(NT) dwt_sy(SyArgs<T> a) {
   constexpr int W = TC + kSHal;
   constexpr int NQ = (4 * W * W + NT - 1) / NT;  // tile values per thread
@@ -509,15 +560,29 @@ __global__ void __launch_bounds__(NT) dwt_sy(SyArgs<T> a) {
   const int band = lb / tiles2;
   const int tile = lb - band * tiles2;
   const int kr0 = (tile / a.tiles) * TC, kc0 = (tile % a.tiles) * TC;
-  const int set = a.level == 1 ? blockIdx.y : blockIdx.y / a.P;
-  const int pone = a.level == 1 ? -1 : blockIdx.y % a.P;
+  const int set = blockIdx.y;
   const int n = a.n, Ms = a.Ms, half = Ms >> 1, hm = half - 1;
   const size_t plane = (size_t)n * n;
   const double a1 = a.pure ? 1.0 : coef_of(a.a1_sel[set], a.dp);
   const double a2 = a.pure ? 0.0 : coef_of(a.a2_sel[set], a.dp);
-  const int p0 = a.level == 1 ? 0 : pone;
-  const int p1 = a.level == 1 ? a.P : pone + 1;
+  // Every block runs through all bases (the next basis' tile is fetched while
+  // the current one is filtered): at level 1 their syntheses are summed, at
+  // the coarser levels each basis has an output of its own.
+  const int p0 = 0, p1 = a.P;
   const bool has_ll = a.level < a.J;
+  // this thread's outputs: 4 consecutive values of one row
+  const int o0 = 2 * kr0, q0 = 2 * kc0;
+  const int ri = threadIdx.x / (TC / 2), b0 = (threadIdx.x % (TC / 2)) * 2;
+  const int row = o0 + ri, col = q0 + 2 * b0;
+  // coarser levels: store the synthesis of basis pidx and clear acc
+  auto store_level = [&](int pidx, T (&acc)[2][2]) {
+    if (row < Ms && col < Ms) {
+      T* dst = a.llout[set] + ((size_t)band * a.P + pidx) * (size_t)Ms * Ms +
+               (size_t)row * Ms + col;
+      store4(dst, acc, T(1), col + 3 < Ms);
+    }
+    acc[0][0] = acc[0][1] = acc[1][0] = acc[1][1] = T(0);
+  };
   // Offsets of this thread's tile values inside one basis plane (periodic
   // wrap), computed once: the low-low quadrant reads the coarser level's
   // output (offset in a half x half plane, flagged by a negative value) when
@@ -573,6 +638,7 @@ __global__ void __launch_bounds__(NT) dwt_sy(SyArgs<T> a) {
     sy_cols<T, TC, NT, PB>(s_q, s_r);                                             \
     __syncthreads();                                                              \
     sy_rows<T, TC, NT, PB>(s_r, acc);                                             \
+    if constexpr (DEEP) store_level(PB - 1, acc);                                 \
     if (more) {                                                                   \
       _Pragma("unroll") for (int i = 0; i < NQ; ++i) {                            \
         const int t = threadIdx.x + i * NT;                                       \
@@ -590,32 +656,11 @@ __global__ void __launch_bounds__(NT) dwt_sy(SyArgs<T> a) {
   MUFFIN_SY_STEP(7)
   MUFFIN_SY_STEP(8)
 #undef MUFFIN_SY_STEP
-  // ---- store: each thread owns 4 consecutive outputs of one row ----
-  const int o0 = 2 * kr0, q0 = 2 * kc0;
-  const int ri = threadIdx.x / (TC / 2), b0 = (threadIdx.x % (TC / 2)) * 2;
-  const int row = o0 + ri, col = q0 + 2 * b0;
-  if (row < Ms && col < Ms) {
-    T* dst;
-    T sc = T(1);
-    if (a.level == 1) {
-      const double beta = a.beta ? a.beta[band] : 1.0;
-      sc = T(beta / sqrt((double)a.P));
-      dst = a.S[set] + (size_t)band * plane + (size_t)row * n + col;
-    } else {
-      dst = a.llout[set] + ((size_t)band * a.P + pone) * (size_t)Ms * Ms + (size_t)row * Ms + col;
-    }
-    if (col + 3 < Ms) {
-      if constexpr (sizeof(T) == 4) {
-        *reinterpret_cast<float4*>(dst) =
-            make_float4(sc * acc[0][0], sc * acc[0][1], sc * acc[1][0], sc * acc[1][1]);
-      } else {
-        reinterpret_cast<double2*>(dst)[0] = make_double2(sc * acc[0][0], sc * acc[0][1]);
-        reinterpret_cast<double2*>(dst)[1] = make_double2(sc * acc[1][0], sc * acc[1][1]);
-      }
-    } else {
-      dst[0] = sc * acc[0][0];
-      dst[1] = sc * acc[0][1];
-    }
+  // ---- level 1: the sum over bases, scaled by beta_l / sqrt(P) ----
+  if (!DEEP && row < Ms && col < Ms) {
+    const double beta = a.beta ? a.beta[band] : 1.0;
+    T* dst = a.S[set] + (size_t)band * plane + (size_t)row * n + col;
+    store4(dst, acc, T(beta / sqrt((double)a.P)), col + 3 < Ms);
   }
 }
 
@@ -659,8 +704,11 @@ int dwt_analysis(const DwtPlan<T>& p, const AnalysisIO<T>& io, const DevParams* 
     a.role = io.role;
     a.pure = io.pure;
     a.pure_scale = io.pure_scale;
-    dim3 grid(xcd_grid_h(a.nblocks), lev == 1 ? io.nsets : io.nsets * p.P);
-    dwt_an<T, kTO, kNT><<<grid, kNT, 0, s>>>(a);
+    dim3 grid(xcd_grid_h(a.nblocks), io.nsets);
+    if (lev == 1)
+      dwt_an<T, kTO, kNT, false><<<grid, kNT, 0, s>>>(a);
+    else
+      dwt_an<T, kTO, kNT, true><<<grid, kNT, 0, s>>>(a);
     MUFFIN_HIP_CHECK(hipGetLastError());
   }
   return 0;
@@ -695,8 +743,11 @@ int dwt_synthesis(const DwtPlan<T>& p, const SynthesisIO<T>& io, const DevParams
     const int half = a.Ms >> 1;
     a.tiles = (half + kTO - 1) / kTO;
     a.nblocks = a.tiles * a.tiles * p.L;
-    dim3 grid(xcd_grid_h(a.nblocks), lev == 1 ? io.nsets : io.nsets * p.P);
-    dwt_sy<T, kTO, kNT><<<grid, kNT, 0, s>>>(a);
+    dim3 grid(xcd_grid_h(a.nblocks), io.nsets);
+    if (lev == 1)
+      dwt_sy<T, kTO, kNT, false><<<grid, kNT, 0, s>>>(a);
+    else
+      dwt_sy<T, kTO, kNT, true><<<grid, kNT, 0, s>>>(a);
     MUFFIN_HIP_CHECK(hipGetLastError());
   }
   return 0;
