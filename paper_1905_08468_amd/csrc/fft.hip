@@ -477,15 +477,24 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 4) col_pass(ColArgs<T
   constexpr int EMAX = 8 * NT;  // B * 2n <= 8 NT (launcher's choice of NT)
   constexpr int IPT = EMAX / NT / 2;  // input values (the n non-zero rows) per thread
   const int nin = B * n;
-  // transfer function of this block's columns: read from HBM for the first
-  // state set, from L2 for the following ones (same block, a few microseconds
-  // later)
+  // The transfer function of this block's columns is staged in LDS once
+  // (after the FFT buffer) and serves every state set; column n, which only
+  // the block holding the packed slot 0 needs, is read from global memory.
+  cplx<T>* Ks = buf + B * stride;
   const cplx<T>* Kb = a.Kh + (size_t)band * (n + 1) * m2;
   cplx<T> pre[IPT];
 #pragma unroll
   for (int q = 0; q < IPT; ++q) {
     const int t = threadIdx.x + q * NT;
     if (t < nin) pre[q] = a.in[0][((size_t)band * n + kx0) * n + t];
+  }
+  {
+    const cplx<T>* src = Kb + (size_t)kx0 * m2;
+#pragma unroll 4
+    for (int t = threadIdx.x; t < B * m2; t += NT) {
+      const cplx<T> k = src[t];
+      Ks[t] = a.conj ? cconj(k) : k;
+    }
   }
   for (int set = 0; set < a.nsets; ++set) {
 #pragma unroll
@@ -512,19 +521,18 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 4) col_pass(ColArgs<T
       cplx<T>* col = buf + b * stride;
       if (kx != 0) {
         const int iy = sw<T>(ky);
-        cplx<T> K = Kb[(size_t)kx * m2 + ky];
-        if (a.conj) K = cconj(K);
-        col[iy] = cconj(cmul(col[iy], K));
+        col[iy] = cconj(cmul(col[iy], Ks[t]));
       } else if (ky <= n) {
         // slot 0 packs two real columns (kx = 0 and kx = n) as p + i q;
         // G = 1/2 (F + conj F-) K0 + 1/2 (F - conj F-) Kn, pairs (ky, 2n - ky)
         const int kz = (m2 - ky) & (m2 - 1);
         const int iy = sw<T>(ky), iz = sw<T>(kz);
         const cplx<T> F = col[iy], Fm = col[iz];
-        cplx<T> K0 = Kb[ky], Kn = Kb[(size_t)n * m2 + ky];
-        cplx<T> K0m = Kb[kz], Knm = Kb[(size_t)n * m2 + kz];
+        // (kx = 0 is the first column of the block: Ks[ky] is K0)
+        const cplx<T> K0 = Ks[ky], K0m = Ks[kz];
+        cplx<T> Kn = Kb[(size_t)n * m2 + ky], Knm = Kb[(size_t)n * m2 + kz];
         if (a.conj) {
-          K0 = cconj(K0); Kn = cconj(Kn); K0m = cconj(K0m); Knm = cconj(Knm);
+          Kn = cconj(Kn); Knm = cconj(Knm);
         }
         const cplx<T> Sp = cadd(F, cconj(Fm)), Dp = csub(F, cconj(Fm));
         cplx<T> G = cadd(cmul(Sp, K0), cmul(Dp, Kn));
@@ -690,7 +698,8 @@ static int launch_col(const FftPlan<T>& p, const cplx<T>* const* in, cplx<T>* co
   a.conj = conj;
   a.nblocks = p.L * (p.n / a.B);
   a.nsets = nsets;
-  const size_t shm = sizeof(cplx<T>) * (size_t)a.B * sw_stride<T>(2 * p.n);
+  // FFT buffer + the block's transfer-function columns
+  const size_t shm = sizeof(cplx<T>) * (size_t)a.B * (sw_stride<T>(2 * p.n) + 2 * p.n);
   dim3 grid(xcd_grid(a.nblocks), 1);
   if (2 * p.n <= 2048) {
     MUFFIN_ALLOW_BIG_LDS((col_pass<T, 256>));
