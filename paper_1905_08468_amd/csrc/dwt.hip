@@ -474,12 +474,15 @@ __device__ __forceinline__ void sy_cols(const T* q, T* rbuf) {
     }
 #pragma unroll
     for (int a = 0; a < APT; ++a) {
+      // explicit FMA chains: two fused operations per tap and output
       T ev = T(0), od = T(0);
 #pragma unroll
       for (int e = 0; e < PB; ++e) {
         const T l = wl[a - e + PB - 1], hh = wh[a - e + PB - 1];
-        ev += he[e] * l + ge[e] * hh;
-        od += ho[e] * l + go[e] * hh;
+        ev = fma(he[e], l, ev);
+        ev = fma(ge[e], hh, ev);
+        od = fma(ho[e], l, od);
+        od = fma(go[e], hh, od);
       }
       rbuf[(2 * (a0 + a)) * (2 * W) + col] = ev;
       rbuf[(2 * (a0 + a) + 1) * (2 * W) + col] = od;
@@ -516,15 +519,15 @@ __device__ __forceinline__ void sy_rows(const T* rbuf, T (&acc)[2][2]) {
   }
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
-    T ev = T(0), od = T(0);
+    // accumulated straight into acc (FMA chains across the bases)
 #pragma unroll
     for (int e = 0; e < PB; ++e) {
       const T c = wc[b - e + PB - 1], d = wd[b - e + PB - 1];
-      ev += he[e] * c + ge[e] * d;
-      od += ho[e] * c + go[e] * d;
+      acc[b][0] = fma(he[e], c, acc[b][0]);
+      acc[b][0] = fma(ge[e], d, acc[b][0]);
+      acc[b][1] = fma(ho[e], c, acc[b][1]);
+      acc[b][1] = fma(go[e], d, acc[b][1]);
     }
-    acc[b][0] += ev;
-    acc[b][1] += od;
   }
 }
 
@@ -602,49 +605,54 @@ __global__ void __launch_bounds__(NT) dwt_sy(SyArgs<T> a) {
     }
   }
   const T ta1 = T(a1), ta2 = T(a2);
-  auto fetch = [&](int pidx, T (&v)[NQ]) {
+  const bool has_ub = a.Ub[set] != nullptr;
+  // Raw tile values of one basis: ra from U (or the coarser level's output
+  // for the low-low quadrant), rb from the second dual array when the set
+  // combines two.  The loads are unconditional (no branch between a load and
+  // its use), so all of them stay in flight while the previous basis is
+  // filtered; the combination is applied when the tile is written to LDS.
+  T ra[NQ], rb[NQ];
+  auto fetch = [&](int pidx) {
     const T* Ua = a.Ua[set] + ((size_t)band * a.P + pidx) * plane;
-    const T* Ub = a.Ub[set] ? a.Ub[set] + ((size_t)band * a.P + pidx) * plane : nullptr;
-    const T* ll = has_ll ? a.llin[set] + ((size_t)band * a.P + pidx) * (size_t)half * half
-                         : nullptr;
+    const T* Ub = has_ub ? a.Ub[set] + ((size_t)band * a.P + pidx) * plane : Ua;
+    const T* ll = has_ll ? a.llin[set] + ((size_t)band * a.P + pidx) * (size_t)half * half : Ua;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
       const int t = threadIdx.x + i * NT;
       if (t < 4 * W * W) {
         const int o = off[i];
-        if (o < 0) {
-          v[i] = ll[-1 - o];
-        } else {
-          T x = ta1 * Ua[o];
-          if (Ub) x += ta2 * Ub[o];
-          v[i] = x;
+        ra[i] = o < 0 ? ll[-1 - o] : Ua[o];
+        if (has_ub) rb[i] = Ub[o < 0 ? 0 : o];
+      }
+    }
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int t = threadIdx.x + i * NT;
+      if (t < 4 * W * W) {
+        T v = ra[i];
+        if (off[i] >= 0) {
+          v = ta1 * v;
+          if (has_ub) v = fma(ta2, rb[i], v);
         }
+        s_q[t] = v;
       }
     }
   };
   T acc[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
-  T nxt[NQ];
-  fetch(p0, nxt);
-#pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    const int t = threadIdx.x + i * NT;
-    if (t < 4 * W * W) s_q[t] = nxt[i];
-  }
+  fetch(p0);
+  commit();
   __syncthreads();
 #define MUFFIN_SY_STEP(PB)                                                        \
   if (PB - 1 >= p0 && PB - 1 < p1) {                                              \
     const bool more = PB < p1;                                                    \
-    if (more) fetch(PB, nxt);                                                     \
+    if (more) fetch(PB);                                                          \
     sy_cols<T, TC, NT, PB>(s_q, s_r);                                             \
     __syncthreads();                                                              \
     sy_rows<T, TC, NT, PB>(s_r, acc);                                             \
     if constexpr (DEEP) store_level(PB - 1, acc);                                 \
-    if (more) {                                                                   \
-      _Pragma("unroll") for (int i = 0; i < NQ; ++i) {                            \
-        const int t = threadIdx.x + i * NT;                                       \
-        if (t < 4 * W * W) s_q[t] = nxt[i];                                       \
-      }                                                                           \
-    }                                                                             \
+    if (more) commit();                                                           \
     __syncthreads();                                                              \
   }
   MUFFIN_SY_STEP(1)
