@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_kernel(DctArgs<T> a) {
       Z[t] = z;
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   acc_t acc[kDctKtPerWave][G];
 #pragma unroll
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_kernel(DctArgs<T> a) {
   }
 
   // ---- v update; the adjoint input d1 v + d2 v_b replaces Z ----
-  __syncthreads();  // every wave is done reading Z
+  lds_barrier();  // every wave is done reading Z
   const T sg = T(dp->sigma);
   const T d1 = T(dct_coef(a.d1_sel[set], dp));
   const T d2 = T(dct_coef(a.d2_sel[set], dp));
@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_kernel(DctArgs<T> a) {
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   // ---- product 2: t = alpha C^T b ----
 #pragma unroll
@@ -368,7 +368,7 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_bf16_kernel(DctBfArgs a) {
       *reinterpret_cast<bf16x8*>(Zl + j * LpS + 8 * lg) = vl;
     }
   }
-  __syncthreads();
+  lds_barrier();
   flt4 acc[kDctKtPerWave][kBfG];
 #pragma unroll
   for (int i = 0; i < kDctKtPerWave; ++i)
@@ -418,7 +418,7 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_bf16_kernel(DctBfArgs a) {
     }
     return;
   }
-  __syncthreads();
+  lds_barrier();
   const float sg = float(dp->sigma);
   const float d1 = float(dct_coef(a.d1_sel[set], dp));
   const float d2 = float(dct_coef(a.d2_sel[set], dp));
@@ -487,7 +487,7 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_bf16_kernel(DctBfArgs a) {
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int i = 0; i < kDctKtPerWave; ++i)
 #pragma unroll

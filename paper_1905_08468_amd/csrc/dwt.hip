@@ -296,7 +296,7 @@ __device__ __forceinline__ void an_cols(const AnArgs<T>& a, const T* rowbuf, int
         U[idx] = pv < T(-1) ? T(-1) : (pv > T(1) ? T(1) : pv);
         if (M) M[idx] = (pv >= T(-1) && pv <= T(1)) ? 1 : 0;
       } else {
-        U[idx] = m[2 * e + part] ? pv : T(0);
+        U[idx] = (M && m[2 * e + part]) ? pv : T(0);
       }
     }
   }
@@ -324,91 +324,102 @@ __global__ void __launch_bounds__(NT) dwt_an(AnArgs<T> a) {
   // staged image tile, at the coarser levels each basis filters its own
   // low-low band (the next one is fetched while the current one is filtered).
   const int p0 = 0, p1 = a.P;
-  // ---- prefetch the dual values and masks this thread updates ----
-  T u[kMaxBases][4];
-  uint8_t m[kMaxBases][4];
-  const bool upd = !a.pure;
   const size_t plane = (size_t)n * n;
+  // ---- dual values and masks this thread updates, one basis ahead ----
+  // Loads are unconditional (clamped to a valid element; values of positions
+  // the thread does not update are ignored) and land in a slot chosen at
+  // compile time, so no register copy makes the wave wait for them before
+  // they are used.
+  int oidx[4];
 #pragma unroll
-  for (int pb = 0; pb < kMaxBases; ++pb) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      u[pb][i] = T(0);
-      m[pb][i] = 0;
-    }
-    if (upd && pb >= p0 && pb < p1) {
-      const T* U = a.U[set] + ((size_t)band * a.P + pb) * plane;
-      const uint8_t* M = (a.role == ROLE_DERIV && a.mask[set])
-                             ? a.mask[set] + ((size_t)band * a.P + pb) * plane
-                             : nullptr;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const long idx = an_out_index<TO>(i >> 1, i & 1, kr0, kc0, half, n, a.last);
-        if (idx >= 0) {
-          u[pb][i] = U[idx];
-          if (M) m[pb][i] = M[idx];
-        }
-      }
-    }
+  for (int i = 0; i < 4; ++i) {
+    const long idx = an_out_index<TO>(i >> 1, i & 1, kr0, kc0, half, n, a.last);
+    oidx[i] = idx < 0 ? 0 : (int)idx;
   }
+  const bool has_m = a.role == ROLE_DERIV && a.mask[set] != nullptr;
+  T u[2][4];
+  uint8_t m[2][4];
+  auto fetch_um = [&](int pidx, T (&uo)[4], uint8_t (&mo)[4]) {
+    const size_t pl = ((size_t)band * a.P + (pidx < a.P ? pidx : a.P - 1)) * plane;
+    const T* U = a.U[set] + pl;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) uo[i] = U[oidx[i]];
+    if (has_m) {  // uniform; mo is only read when has_m
+      const uint8_t* M = a.mask[set] + pl;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) mo[i] = M[oidx[i]];
+    }
+  };
+  fetch_um(0, u[0], m[0]);
   // ---- coarser levels: this thread's tile offsets in a basis' LL plane ----
+  // (wrapped into the plane, so every offset is valid, also for t >= IN^2)
   constexpr int NI = (IN * IN + NT - 1) / NT;
   int ioff[NI];
-  T nxt[NI];
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
     const int t = threadIdx.x + i * NT;
     const int r = t / IN, c = t - r * IN;
     ioff[i] = ((2 * kr0 + r) & msk) * Ms + ((2 * kc0 + c) & msk);
   }
+  T nxt[NI];
   auto fetch_ll = [&](int pidx) {
     const T* src = a.llin[set] + ((size_t)band * a.P + pidx) * (size_t)Ms * Ms;
 #pragma unroll
-    for (int i = 0; i < NI; ++i) {
-      const int t = threadIdx.x + i * NT;
-      if (t < IN * IN) nxt[i] = src[ioff[i]];
-    }
+    for (int i = 0; i < NI; ++i) nxt[i] = src[ioff[i]];
   };
-  if constexpr (DEEP) fetch_ll(0);
   // ---- stage the input tile (periodic wrap) ----
   if constexpr (!DEEP) {
+    // level 1: z = c1 (2 x~ - x) [+ c2 (2 x~b - xb)], all loads issued first
     const double c1 = coef_of(a.c1_sel[set], a.dp), c2 = coef_of(a.c2_sel[set], a.dp);
     const T* xa = a.x_a[set] + (size_t)band * plane;
     const T* ta = a.xt_a[set] + (size_t)band * plane;
-    const T* xb = a.x_b[set] ? a.x_b[set] + (size_t)band * plane : nullptr;
-    const T* tb = a.xt_b[set] ? a.xt_b[set] + (size_t)band * plane : nullptr;
-    for (int t = threadIdx.x; t < IN * IN; t += NT) {
-      const int r = t / IN, c = t - r * IN;
-      const size_t idx = (size_t)((2 * kr0 + r) & msk) * n + ((2 * kc0 + c) & msk);
-      T z = T(c1) * (T(2) * ta[idx] - xa[idx]);
-      if (xb) z += T(c2) * (T(2) * tb[idx] - xb[idx]);
-      s_in[t] = z;
+    const bool has_b = a.x_b[set] != nullptr;
+    const T* xb = has_b ? a.x_b[set] + (size_t)band * plane : xa;
+    const T* tb = has_b ? a.xt_b[set] + (size_t)band * plane : ta;
+    T v0[NI], v1[NI], v2[NI], v3[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      v0[i] = ta[ioff[i]];
+      v1[i] = xa[ioff[i]];
+      if (has_b) {
+        v2[i] = tb[ioff[i]];
+        v3[i] = xb[ioff[i]];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int t = threadIdx.x + i * NT;
+      T z = T(c1) * (T(2) * v0[i] - v1[i]);
+      if (has_b) z += T(c2) * (T(2) * v2[i] - v3[i]);
+      if (t < IN * IN) s_in[t] = z;
     }
   } else {
+    fetch_ll(0);
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
       const int t = threadIdx.x + i * NT;
       if (t < IN * IN) s_in[t] = nxt[i];
     }
   }
-  __syncthreads();
+  lds_barrier();
   const double beta = a.beta ? a.beta[band] : 1.0;
   const double scale = a.dp ? a.dp->sigma * beta / sqrt((double)a.P) : 0.0;
 #define MUFFIN_AN_STEP(PB)                                                      \
   if (PB - 1 >= p0 && PB - 1 < p1) {                                            \
     const bool more = DEEP && PB < p1;                                          \
     if (more) fetch_ll(PB);                                                     \
+    if (PB < p1) fetch_um(PB, u[PB & 1], m[PB & 1]);                            \
     an_rows<T, TO, NT, PB>(s_in, s_row, IN);                                    \
-    __syncthreads();                                                            \
-    an_cols<T, TO, NT, PB>(a, s_row, set, band, kr0, kc0, scale, u[PB - 1],     \
-                           m[PB - 1]);                                          \
+    lds_barrier();                                                            \
+    an_cols<T, TO, NT, PB>(a, s_row, set, band, kr0, kc0, scale, u[(PB - 1) & 1], \
+                           m[(PB - 1) & 1]);                                    \
     if (more) {                                                                 \
       _Pragma("unroll") for (int i = 0; i < NI; ++i) {                          \
         const int t = threadIdx.x + i * NT;                                     \
         if (t < IN * IN) s_in[t] = nxt[i];                                      \
       }                                                                         \
     }                                                                           \
-    __syncthreads();                                                            \
+    lds_barrier();                                                            \
   }
   MUFFIN_AN_STEP(1)
   MUFFIN_AN_STEP(2)
@@ -643,17 +654,17 @@ __global__ void __launch_bounds__(NT) dwt_sy(SyArgs<T> a) {
   T acc[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
   fetch(p0);
   commit();
-  __syncthreads();
+  lds_barrier();
 #define MUFFIN_SY_STEP(PB)                                                        \
   if (PB - 1 >= p0 && PB - 1 < p1) {                                              \
     const bool more = PB < p1;                                                    \
     if (more) fetch(PB);                                                          \
     sy_cols<T, TC, NT, PB>(s_q, s_r);                                             \
-    __syncthreads();                                                              \
+    lds_barrier();                                                              \
     sy_rows<T, TC, NT, PB>(s_r, acc);                                             \
     if constexpr (DEEP) store_level(PB - 1, acc);                                 \
     if (more) commit();                                                           \
-    __syncthreads();                                                              \
+    lds_barrier();                                                              \
   }
   MUFFIN_SY_STEP(1)
   MUFFIN_SY_STEP(2)

@@ -144,7 +144,7 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int lognf, int logNs, in
       for (int r = 0; r < R; ++r) v[q][r] = src[sw<T>(j + r * nbf)];
     }
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int q = 0; q < MAXQ; ++q) {
     const int t = threadIdx.x + q * NT;
@@ -168,7 +168,7 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int lognf, int logNs, in
       for (int r = 0; r < R; ++r) dst[sw<T>(base + r * Ns)] = v[q][r];
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // Forward FFT of `batch` sequences of length 2^lognf held in LDS (swizzled,
@@ -205,7 +205,7 @@ __device__ double block_sum(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) sh[w] = v;
-  __syncthreads();
+  lds_barrier();
   double s = 0.0;
   if (threadIdx.x == 0) {
     for (int i = 0; i < NT / 64; ++i) s += sh[i];
@@ -305,7 +305,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
       const int t = threadIdx.x + q * NT;
       if (t < nel) buf[row_slot<T, RB, IN>(t, n, logn, stride)] = pre[q];
     }
-    __syncthreads();
+    lds_barrier();
     if (set + 1 < a.nsets) {
 #pragma unroll
       for (int q = 0; q < EPT; ++q) {
@@ -316,7 +316,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
 #else
     for (int t = threadIdx.x; t < nel; t += NT)
       buf[row_slot<T, RB, IN>(t, n, logn, stride)] = row_input<T, RB, NT, IN>(a, set, band, i0, t);
-    __syncthreads();
+    lds_barrier();
 #endif
     if constexpr (IN == IN_SPEC) {
       // Hermitian pre-pass of the real inverse: with A = X[k], B = conj X[n-k],
@@ -350,7 +350,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
           }
         }
       }
-      __syncthreads();
+      lds_barrier();
       lds_fft<T, NT, EMAX>(buf, logn, RB, stride, a.twr);
       // z = conj(buf): x[2m] = z.x, x[2m+1] = z.y for m < n/2 (image window)
       if constexpr (OUT == OUT_REAL) {
@@ -362,7 +362,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
           p[0] = z.x;
           p[1] = -z.y;
         }
-        __syncthreads();
+        lds_barrier();
         continue;
       } else {
         double acc = 0.0;
@@ -387,7 +387,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
           const double sum = block_sum<NT>(acc, red);
           if (threadIdx.x == 0) a.partials[lb] = sum;
         }
-        __syncthreads();
+        lds_barrier();
       }
     }
 
@@ -422,7 +422,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
           }
         }
       }
-      __syncthreads();
+      lds_barrier();
       if constexpr (OUT == OUT_SPEC) {
         cplx<T>* sp = a.out_spec[set] + (size_t)band * n * n + i0;
         for (int t = threadIdx.x; t < RB * n; t += NT) {
@@ -442,7 +442,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
           sp[(size_t)kx * m2 + r] = v;
         }
       }
-      __syncthreads();
+      lds_barrier();
     }
   }
 }
@@ -506,7 +506,7 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 4) col_pass(ColArgs<T
         buf[b * stride + sw<T>(i + n)] = cplx<T>{T(0), T(0)};
       }
     }
-    __syncthreads();
+    lds_barrier();
     if (set + 1 < a.nsets) {
 #pragma unroll
       for (int q = 0; q < IPT; ++q) {
@@ -546,14 +546,14 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 4) col_pass(ColArgs<T
         col[iy] = cconj(G);
       }
     }
-    __syncthreads();
+    lds_barrier();
     lds_fft<T, NT, EMAX>(buf, a.logn + 1, B, stride, a.twc);
     cplx<T>* dst = a.out[set] + ((size_t)band * n + kx0) * n;
     for (int t = threadIdx.x; t < nin; t += NT) {
       const int b = t / n, i = t - b * n;
       dst[(size_t)b * n + i] = cconj(buf[b * stride + sw<T>(i)]);
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -568,7 +568,7 @@ __global__ void __launch_bounds__(NT) psf_cols(const cplx<T>* tmp, cplx<T>* Kh,
   const int kx = blockIdx.x, band = blockIdx.y;
   const size_t off = ((size_t)band * (n + 1) + kx) * m2;
   for (int i = threadIdx.x; i < m2; i += NT) buf[sw<T>(i)] = tmp[off + i];
-  __syncthreads();
+  lds_barrier();
   lds_fft<T, NT, 8 * NT>(buf, logn + 1, 1, sw_stride<T>(m2), twc);
   const T s = T(1.0 / (4.0 * double(n) * double(n)));
   for (int i = threadIdx.x; i < m2; i += NT) {

@@ -243,6 +243,16 @@ int pi_normalise(double* v, const double* w, const double* stats, int L, int N,
 }  // namespace muffin
 
 // Kernels whose dynamic LDS can exceed 64 KB opt in to the CU's full LDS.
+// Workgroup barrier for LDS hand-offs between the waves of a block: waits
+// for this wave's LDS (and scalar-load) operations only.  __syncthreads() is
+// a workgroup-scope fence that also drains every outstanding global load and
+// store, which would expose the latency of loads issued ahead of time (the
+// next tile, the next state set) at every barrier.  Global memory written by
+// a block is never read back by the same block within a kernel here.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 #define MUFFIN_ALLOW_BIG_LDS(kernel)                                                  \
   do {                                                                                \
     static bool _done = false;                                                        \
