@@ -94,7 +94,7 @@ __device__ __forceinline__ int out_row(int lk, int r) {
 // w, w + 4, w + 8, w + 12 for every pixel group, so each A fragment (read
 // coalesced from the fragment-ordered matrix) feeds G MFMAs.
 template <typename T>
-__global__ void __launch_bounds__(64 * kDctWaves) dct_kernel(DctArgs<T> a) {
+__global__ void __launch_bounds__(64 * kDctWaves, 2) dct_kernel(DctArgs<T> a) {
   typedef typename Acc4<T>::type acc_t;
   constexpr int G = dct_groups<T>();
   constexpr int PIX = 16 * G;
@@ -112,24 +112,48 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_kernel(DctArgs<T> a) {
   {
     const double c1 = a.pure ? 1.0 : dct_coef(a.c1_sel[set], dp);
     const double c2 = a.pure ? 0.0 : dct_coef(a.c2_sel[set], dp);
-    const T* ta = a.xt_a[set];
+    // Operands of U items are loaded unconditionally (indices clamped into
+    // the cube; out-of-range items are zeroed afterwards) before any is
+    // used, so they are all in flight together.
     const T* xa = a.x_a[set];
-    const T* tb = a.xt_b[set];
-    const T* xb = a.x_b[set];
-    for (int t = threadIdx.x; t < Lp * PIX; t += 64 * kDctWaves) {
-      const int l = t / PIX, j = t - l * PIX;
-      const int pix = pix0 + j;
-      T z = T(0);
-      if (l < L && pix < N) {
-        const size_t idx = (size_t)l * N + pix;
-        if (a.pure) {
-          z = xa[idx];
-        } else {
-          z = T(c1) * (T(2) * ta[idx] - xa[idx]);
-          if (xb) z += T(c2) * (T(2) * tb[idx] - xb[idx]);
+    const T* ta = a.pure ? xa : a.xt_a[set];
+    const bool has_b = !a.pure && a.x_b[set] != nullptr;
+    const T* xb = has_b ? a.x_b[set] : xa;
+    const T* tb = has_b ? a.xt_b[set] : xa;
+    constexpr int U = 8;
+    constexpr int NT = 64 * kDctWaves;
+    const int total = Lp * PIX;
+    for (int t0 = threadIdx.x; t0 < total; t0 += U * NT) {
+      T v0[U], v1[U], v2[U], v3[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = min(t0 + u * NT, total - 1);
+        const int l = t / PIX, j = t - l * PIX;
+        const size_t idx = (size_t)min(l, L - 1) * N + min(pix0 + j, N - 1);
+        v0[u] = ta[idx];
+        v1[u] = xa[idx];
+        if (has_b) {
+          v2[u] = tb[idx];
+          v3[u] = xb[idx];
         }
       }
-      Z[t] = z;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = t0 + u * NT;
+        if (t < total) {
+          const int l = t / PIX, j = t - l * PIX;
+          T z = T(0);
+          if (l < L && pix0 + j < N) {
+            if (a.pure) {
+              z = v1[u];
+            } else {
+              z = T(c1) * (T(2) * v0[u] - v1[u]);
+              if (has_b) z += T(c2) * (T(2) * v2[u] - v3[u]);
+            }
+          }
+          Z[t] = z;
+        }
+      }
     }
   }
   lds_barrier();
@@ -185,6 +209,8 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_kernel(DctArgs<T> a) {
   T* __restrict__ V = a.V[set];
   const T* __restrict__ Vb = a.Vb[set];
   uint8_t* __restrict__ M = a.mask[set];
+  const bool has_vb = Vb != nullptr;
+  const bool has_mk = a.role != ROLE_PRIMAL;  // the derivative roles read the mask
   T al[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) {
@@ -195,23 +221,20 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_kernel(DctArgs<T> a) {
   for (int i = 0; i < kDctKtPerWave; ++i) {
     const int kt = wave + kDctWaves * i;
     if (kt < nkt) {
+      // every operand of this k-tile in flight at once: clamped,
+      // unconditional loads (values outside the cube are not used)
       T vold[G][4], vbv[G][4];
       uint8_t mk[G][4];
 #pragma unroll
       for (int g = 0; g < G; ++g) {
-        const int pix = pix0 + 16 * g + lr;
+        const int pix = min(pix0 + 16 * g + lr, N - 1);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int k = kt * 16 + out_row<T>(lk, r);
-          vold[g][r] = T(0);
-          vbv[g][r] = T(0);
-          mk[g][r] = 0;
-          if (k < L && pix < N) {
-            const size_t idx = (size_t)k * N + pix;
-            vold[g][r] = V[idx];
-            if (Vb) vbv[g][r] = Vb[idx];
-            if (a.role != ROLE_PRIMAL) mk[g][r] = M[idx];
-          }
+          const int k = min(kt * 16 + out_row<T>(lk, r), L - 1);
+          const size_t idx = (size_t)k * N + pix;
+          vold[g][r] = V[idx];
+          if (has_vb) vbv[g][r] = Vb[idx];
+          if (has_mk) mk[g][r] = M[idx];
         }
       }
 #pragma unroll
@@ -232,7 +255,8 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_kernel(DctArgs<T> a) {
               vn = mk[g][r] ? vt : T(0);
             }
             V[idx] = vn;
-            bv = d1 * vn + d2 * vbv[g][r];
+            bv = d1 * vn;
+            if (has_vb) bv += d2 * vbv[g][r];
           }
           Z[k * PIX + 16 * g + lr] = bv;
         }
@@ -321,7 +345,7 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
-__global__ void __launch_bounds__(64 * kDctWaves) dct_bf16_kernel(DctBfArgs a) {
+__global__ void __launch_bounds__(64 * kDctWaves, 2) dct_bf16_kernel(DctBfArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int L = a.L, Lp = a.Lp, N = a.N;
   const int LpS = Lp + 8;  // padded band stride of the [pixel][band] tile
@@ -336,27 +360,41 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_bf16_kernel(DctBfArgs a) {
   {
     const double c1 = a.pure ? 1.0 : dct_coef(a.c1_sel[set], dp);
     const double c2 = a.pure ? 0.0 : dct_coef(a.c2_sel[set], dp);
-    const float* ta = a.xt_a[set];
     const float* xa = a.x_a[set];
-    const float* tb = a.xt_b[set];
-    const float* xb = a.x_b[set];
+    const float* ta = a.pure ? xa : a.xt_a[set];
+    const bool has_b = !a.pure && a.x_b[set] != nullptr;
+    const float* xb = has_b ? a.x_b[set] : xa;
+    const float* tb = has_b ? a.xt_b[set] : xa;
     // each thread converts 8 consecutive bands of one pixel and stores them
-    // as one 16-byte hi and one 16-byte lo vector
-    for (int t = threadIdx.x; t < (Lp / 8) * kBfPix; t += 64 * kDctWaves) {
+    // as one 16-byte hi and one 16-byte lo vector; the operands of the 8
+    // bands are loaded unconditionally (clamped indices) before any is used
+    const int total = (Lp / 8) * kBfPix;
+    for (int t = threadIdx.x; t < total; t += 64 * kDctWaves) {
       const int lg = t / kBfPix, j = t - lg * kBfPix;
       const int pix = pix0 + j;
+      const int pc = min(pix, N - 1);
+      float v0[8], v1[8], v2[8], v3[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const size_t idx = (size_t)min(8 * lg + e, L - 1) * N + pc;
+        v0[e] = ta[idx];
+        v1[e] = xa[idx];
+        if (has_b) {
+          v2[e] = tb[idx];
+          v3[e] = xb[idx];
+        }
+      }
       bf16x8 vh, vl;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int l = 8 * lg + e;
         float z = 0.f;
         if (l < L && pix < N) {
-          const size_t idx = (size_t)l * N + pix;
           if (a.pure) {
-            z = xa[idx];
+            z = v1[e];
           } else {
-            z = float(c1) * (2.f * ta[idx] - xa[idx]);
-            if (xb) z += float(c2) * (2.f * tb[idx] - xb[idx]);
+            z = float(c1) * (2.f * v0[e] - v1[e]);
+            if (has_b) z += float(c2) * (2.f * v2[e] - v3[e]);
           }
         }
         __bf16 h, lo;
@@ -425,6 +463,8 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_bf16_kernel(DctBfArgs a) {
   float* __restrict__ V = a.V[set];
   const float* __restrict__ Vb = a.Vb[set];
   uint8_t* __restrict__ M = a.mask[set];
+  const bool has_vb = Vb != nullptr;
+  const bool has_mk = a.role != ROLE_PRIMAL;  // the derivative roles read the mask
   float al[kBfG];
 #pragma unroll
   for (int g = 0; g < kBfG; ++g) {
@@ -440,19 +480,14 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_bf16_kernel(DctBfArgs a) {
       uint8_t mk[kBfG][4];
 #pragma unroll
       for (int g = 0; g < kBfG; ++g) {
-        const int pix = pix0 + 16 * g + lr;
+        const int pix = min(pix0 + 16 * g + lr, N - 1);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int k = kt * 16 + 4 * lk + r;
-          vold[g][r] = 0.f;
-          vbv[g][r] = 0.f;
-          mk[g][r] = 0;
-          if (k < L && pix < N) {
-            const size_t idx = (size_t)k * N + pix;
-            vold[g][r] = V[idx];
-            if (Vb) vbv[g][r] = Vb[idx];
-            if (a.role != ROLE_PRIMAL) mk[g][r] = M[idx];
-          }
+          const int k = min(kt * 16 + 4 * lk + r, L - 1);
+          const size_t idx = (size_t)k * N + pix;
+          vold[g][r] = V[idx];
+          if (has_vb) vbv[g][r] = Vb[idx];
+          if (has_mk) mk[g][r] = M[idx];
         }
       }
 #pragma unroll
@@ -474,7 +509,8 @@ __global__ void __launch_bounds__(64 * kDctWaves) dct_bf16_kernel(DctBfArgs a) {
               vn = mk[g][r] ? vt : 0.f;
             }
             V[idx] = vn;
-            bv = d1 * vn + d2 * vbv[g][r];
+            bv = d1 * vn;
+            if (has_vb) bv += d2 * vbv[g][r];
           }
           __bf16 h, lo;
           split_bf16(bv, h, lo);
