@@ -314,8 +314,50 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
       }
     }
 #else
-    for (int t = threadIdx.x; t < nel; t += NT)
-      buf[row_slot<T, RB, IN>(t, n, logn, stride)] = row_input<T, RB, NT, IN>(a, set, band, i0, t);
+    if constexpr (IN == IN_REAL) {
+      // image rows: (x[2m], x[2m+1]) pairs for m < n/2, zeros above (the
+      // padding); the loads of several pairs are issued before any is stored
+      constexpr int U = 4;
+      const int nin = RB * half;
+      for (int t0 = threadIdx.x; t0 < nin; t0 += U * NT) {
+        cplx<T> v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int t = min(t0 + u * NT, nin - 1);
+          const int r = t / half, m = t - r * half;
+          const T* p = a.in[set] + ((size_t)band * n + i0 + r) * n + 2 * m;
+          v[u] = *reinterpret_cast<const cplx<T>*>(p);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int t = t0 + u * NT;
+          if (t < nin) {
+            const int r = t / half, m = t - r * half;
+            buf[r * stride + sw<T>(m)] = v[u];
+          }
+        }
+      }
+      for (int t = threadIdx.x; t < nin; t += NT) {
+        const int r = t / half, m = t - r * half;
+        buf[r * stride + sw<T>(m + half)] = cplx<T>{T(0), T(0)};
+      }
+    } else if constexpr (IN == IN_SPEC) {
+      constexpr int U = 4;
+      for (int t0 = threadIdx.x; t0 < nel; t0 += U * NT) {
+        cplx<T> v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          v[u] = row_input<T, RB, NT, IN>(a, set, band, i0, min(t0 + u * NT, nel - 1));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int t = t0 + u * NT;
+          if (t < nel) buf[row_slot<T, RB, IN>(t, n, logn, stride)] = v[u];
+        }
+      }
+    } else {
+      for (int t = threadIdx.x; t < nel; t += NT)
+        buf[row_slot<T, RB, IN>(t, n, logn, stride)] = row_input<T, RB, NT, IN>(a, set, band, i0, t);
+    }
     lds_barrier();
 #endif
     if constexpr (IN == IN_SPEC) {
