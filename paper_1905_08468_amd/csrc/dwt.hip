@@ -166,6 +166,11 @@ __device__ __forceinline__ int xcd_remap_d(int b, int nb) {
 }
 static inline int xcd_grid_h(int nb) { return ((nb + 7) >> 3) << 3; }
 
+#ifndef MUFFIN_DWT_MIN_WAVES
+#define MUFFIN_DWT_MIN_WAVES 1
+#endif
+// minimum waves per SIMD the wavelet kernels are compiled for (register cap)
+constexpr int kDwtMinWaves = MUFFIN_DWT_MIN_WAVES;
 constexpr int kHalo = 14;  // 2 * 8 - 2: longest filter
 constexpr int kSHal = 7;   // synthesis halo (8 - 1)
 
@@ -305,8 +310,11 @@ __device__ __forceinline__ void an_cols(const AnArgs<T>& a, const T* rowbuf, int
 // DEEP = false: level 1 (one staged image tile for all bases); true: the
 // coarser levels (one low-low tile per basis).  Separate instantiations keep
 // the level-1 kernel's register budget free of the per-basis staging.
-template <typename T, int TO, int NT, bool DEEP>
-__global__ void __launch_bounds__(NT) dwt_an(AnArgs<T> a) {
+// PN: number of bases when known at compile time (8, the paper's union of
+// db1..db8), or 0 to take it from the arguments; with it known, every basis
+// step and every prefetch is unconditional.
+template <typename T, int TO, int NT, bool DEEP, int PN>
+__global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_an(AnArgs<T> a) {
   static_assert((TO / 2) * (2 * TO) == NT, "one thread per column-filter output quad");
   constexpr int IN = 2 * TO + kHalo;
   __shared__ T s_in[IN * IN];
@@ -323,7 +331,7 @@ __global__ void __launch_bounds__(NT) dwt_an(AnArgs<T> a) {
   // Every block runs through all bases: at level 1 they filter the same
   // staged image tile, at the coarser levels each basis filters its own
   // low-low band (the next one is fetched while the current one is filtered).
-  const int p0 = 0, p1 = a.P;
+  const int p0 = 0, p1 = PN ? PN : a.P;
   const size_t plane = (size_t)n * n;
   // ---- dual values and masks this thread updates, one basis ahead ----
   // Loads are unconditional (clamped to a valid element; values of positions
@@ -562,8 +570,9 @@ __device__ __forceinline__ void store4(T* dst, const T (&acc)[2][2], T sc, bool 
 
 // DEEP = false: level 1 (the bases' syntheses summed into S); true: the
 // coarser levels (one output per basis).
-template <typename T, int TC, int NT, bool DEEP>
-__global__ void __launch_bounds__(NT) dwt_sy(SyArgs<T> a) {
+// PN: number of bases when known at compile time, or 0 (see dwt_an).
+template <typename T, int TC, int NT, bool DEEP, int PN>
+__global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_sy(SyArgs<T> a) {
   constexpr int W = TC + kSHal;
   constexpr int NQ = (4 * W * W + NT - 1) / NT;  // tile values per thread
   __shared__ T s_q[4 * W * W];
@@ -582,7 +591,7 @@ __global__ void __launch_bounds__(NT) dwt_sy(SyArgs<T> a) {
   // Every block runs through all bases (the next basis' tile is fetched while
   // the current one is filtered): at level 1 their syntheses are summed, at
   // the coarser levels each basis has an output of its own.
-  const int p0 = 0, p1 = a.P;
+  const int p0 = 0, p1 = PN ? PN : a.P;
   const bool has_ll = a.level < a.J;
   // this thread's outputs: 4 consecutive values of one row
   const int o0 = 2 * kr0, q0 = 2 * kc0;
@@ -724,10 +733,17 @@ int dwt_analysis(const DwtPlan<T>& p, const AnalysisIO<T>& io, const DevParams* 
     a.pure = io.pure;
     a.pure_scale = io.pure_scale;
     dim3 grid(xcd_grid_h(a.nblocks), io.nsets);
-    if (lev == 1)
-      dwt_an<T, kTO, kNT, false><<<grid, kNT, 0, s>>>(a);
-    else
-      dwt_an<T, kTO, kNT, true><<<grid, kNT, 0, s>>>(a);
+    if (p.P == 8) {
+      if (lev == 1)
+        dwt_an<T, kTO, kNT, false, 8><<<grid, kNT, 0, s>>>(a);
+      else
+        dwt_an<T, kTO, kNT, true, 8><<<grid, kNT, 0, s>>>(a);
+    } else {
+      if (lev == 1)
+        dwt_an<T, kTO, kNT, false, 0><<<grid, kNT, 0, s>>>(a);
+      else
+        dwt_an<T, kTO, kNT, true, 0><<<grid, kNT, 0, s>>>(a);
+    }
     MUFFIN_HIP_CHECK(hipGetLastError());
   }
   return 0;
@@ -763,10 +779,12 @@ int dwt_synthesis(const DwtPlan<T>& p, const SynthesisIO<T>& io, const DevParams
     a.tiles = (half + kTO - 1) / kTO;
     a.nblocks = a.tiles * a.tiles * p.L;
     dim3 grid(xcd_grid_h(a.nblocks), io.nsets);
+    // (the basis count stays a run-time value here: compiled for P = 8 the
+    // fully unrolled kernel needs 137 VGPRs and runs at half the occupancy)
     if (lev == 1)
-      dwt_sy<T, kTO, kNT, false><<<grid, kNT, 0, s>>>(a);
+      dwt_sy<T, kTO, kNT, false, 0><<<grid, kNT, 0, s>>>(a);
     else
-      dwt_sy<T, kTO, kNT, true><<<grid, kNT, 0, s>>>(a);
+      dwt_sy<T, kTO, kNT, true, 0><<<grid, kNT, 0, s>>>(a);
     MUFFIN_HIP_CHECK(hipGetLastError());
   }
   return 0;
