@@ -108,6 +108,18 @@ __host__ __device__ __forceinline__ int radix_log(int rem) {
   return rem == 1 ? 1 : ((rem == 2 || rem == 4) ? 2 : 3);
 }
 
+// Number of entries in the stage twiddle tables of a length-2^lognf FFT
+// (every stage after the first holds Ns (R - 1) entries; at least one).
+__host__ __device__ __forceinline__ int stage_table_len(int lognf) {
+  int done = 0, len = 0;
+  while (done < lognf) {
+    const int lr = radix_log(lognf - done);
+    if (done > 0) len += (1 << done) * ((1 << lr) - 1);
+    done += lr;
+  }
+  return len > 0 ? len : 1;
+}
+
 // One Stockham stage: input element j + r*nf/R, output (j - k) R + k + r Ns
 // with k = j mod Ns.  Every thread first loads all its butterflies, then the
 // block synchronises and stores, so the stage runs in place.  Twiddles
@@ -188,6 +200,126 @@ __device__ __forceinline__ void lds_fft(cplx<T>* buf, int lognf, int batch, int 
   }
 }
 
+// ---- the same transform with the length known at compile time ----
+// Every stage parameter is a constant, so the block/sequence indices of a
+// thread fold into constants and, when the stride between a butterfly's
+// elements is a multiple of the swizzle period, sw(x + c) = sw(x) + c + c/P
+// turns the R addresses of a butterfly into one swizzle plus immediate
+// offsets of the LDS instructions.
+constexpr int radix_log_c(int rem) { return rem == 1 ? 1 : ((rem == 2 || rem == 4) ? 2 : 3); }
+
+template <typename T>
+constexpr int sw_shift() { return sizeof(T) == 8 ? 3 : 4; }
+
+template <typename T, int C>
+__device__ __forceinline__ int sw_plus(int x, int swx) {
+  // sw(x + C), using sw(x) when C is a multiple of the swizzle period
+  constexpr int S = sw_shift<T>();
+  if constexpr ((C & ((1 << S) - 1)) == 0)
+    return swx + C + (C >> S);
+  else
+    return sw<T>(x + C);
+}
+
+template <typename T, int R, int NT, int EMAX, int LOGNF, int LOGNS>
+__device__ __forceinline__ void fft_stage_ct(cplx<T>* buf, int batch, int stride,
+                                             const cplx<T>* __restrict__ tws) {
+  constexpr int MAXQ = (EMAX / R + NT - 1) / NT;
+  constexpr int LOGR = R == 2 ? 1 : (R == 4 ? 2 : 3);
+  constexpr int LOGNBF = LOGNF - LOGR;
+  constexpr int NBF = 1 << LOGNBF;
+  constexpr int NS = 1 << LOGNS;
+  constexpr bool HOIST = EMAX / NT <= 8;
+  const int total = NBF * batch;
+  cplx<T> v[MAXQ][R];
+  cplx<T> w[HOIST ? MAXQ : 1][R - 1];
+#pragma unroll
+  for (int q = 0; q < MAXQ; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if (t < total) {
+      const int b = t >> LOGNBF, j = t & (NBF - 1);
+      if constexpr (HOIST && LOGNS > 0) {
+        const cplx<T>* tw = tws + (j & (NS - 1)) * (R - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[q][r - 1] = tw[r - 1];
+      }
+      const cplx<T>* src = buf + b * stride;
+      const int sj = sw<T>(j);
+      v[q][0] = src[sj];
+      if constexpr (R > 1) v[q][1] = src[sw_plus<T, 1 * NBF>(j, sj)];
+      if constexpr (R > 2) {
+        v[q][2] = src[sw_plus<T, 2 * NBF>(j, sj)];
+        v[q][3] = src[sw_plus<T, 3 * NBF>(j, sj)];
+      }
+      if constexpr (R > 4) {
+        v[q][4] = src[sw_plus<T, 4 * NBF>(j, sj)];
+        v[q][5] = src[sw_plus<T, 5 * NBF>(j, sj)];
+        v[q][6] = src[sw_plus<T, 6 * NBF>(j, sj)];
+        v[q][7] = src[sw_plus<T, 7 * NBF>(j, sj)];
+      }
+    }
+  }
+  lds_barrier();
+#pragma unroll
+  for (int q = 0; q < MAXQ; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if (t < total) {
+      const int b = t >> LOGNBF, j = t & (NBF - 1);
+      const int k = j & (NS - 1);
+      if constexpr (LOGNS > 0) {
+        if constexpr (HOIST) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[q][r - 1]);
+        } else {
+          const cplx<T>* tw = tws + k * (R - 1);
+#pragma unroll
+          for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[r - 1]);
+        }
+      }
+      dft_small<T, R>(v[q]);
+      cplx<T>* dst = buf + b * stride;
+      const int base = ((j >> LOGNS) << (LOGNS + LOGR)) + k;
+      const int sb = sw<T>(base);
+      dst[sb] = v[q][0];
+      if constexpr (R > 1) dst[sw_plus<T, 1 * NS>(base, sb)] = v[q][1];
+      if constexpr (R > 2) {
+        dst[sw_plus<T, 2 * NS>(base, sb)] = v[q][2];
+        dst[sw_plus<T, 3 * NS>(base, sb)] = v[q][3];
+      }
+      if constexpr (R > 4) {
+        dst[sw_plus<T, 4 * NS>(base, sb)] = v[q][4];
+        dst[sw_plus<T, 5 * NS>(base, sb)] = v[q][5];
+        dst[sw_plus<T, 6 * NS>(base, sb)] = v[q][6];
+        dst[sw_plus<T, 7 * NS>(base, sb)] = v[q][7];
+      }
+    }
+  }
+  lds_barrier();
+}
+
+// Forward FFT of `batch` sequences of length 2^LOGNF (as lds_fft).
+template <typename T, int NT, int EMAX, int LOGNF, int DONE = 0, int OFF = 0>
+__device__ __forceinline__ void lds_fft_ct(cplx<T>* buf, int batch, int stride,
+                                           const cplx<T>* __restrict__ twtab) {
+  if constexpr (DONE < LOGNF) {
+    constexpr int LR = radix_log_c(LOGNF - DONE);
+    fft_stage_ct<T, (1 << LR), NT, EMAX, LOGNF, DONE>(buf, batch, stride, twtab + OFF);
+    constexpr int NOFF = DONE > 0 ? OFF + (1 << DONE) * ((1 << LR) - 1) : OFF;
+    lds_fft_ct<T, NT, EMAX, LOGNF, DONE + LR, NOFF>(buf, batch, stride, twtab);
+  }
+}
+
+// Length-2^lognf FFT; LOGNF > 0 selects the compile-time form (lognf must
+// then equal it).
+template <typename T, int NT, int EMAX, int LOGNF>
+__device__ __forceinline__ void lds_fft_any(cplx<T>* buf, int lognf, int batch, int stride,
+                                            const cplx<T>* __restrict__ twtab) {
+  if constexpr (LOGNF > 0)
+    lds_fft_ct<T, NT, EMAX, LOGNF>(buf, batch, stride, twtab);
+  else
+    lds_fft<T, NT, EMAX>(buf, lognf, batch, stride, twtab);
+}
+
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 
 // Blocks are handed to the 8 XCDs round-robin; remap so that each XCD gets a
@@ -240,8 +372,8 @@ struct RowArgs {
 // with the zero-padded half; IN_SPEC: packed spectrum read column-major).
 template <typename T, int RB, int NT, int IN>
 __device__ __forceinline__ cplx<T> row_input(const RowArgs<T>& a, int set, int band, int i0,
-                                             int t) {
-  const int n = a.n, logn = a.logn, half = n >> 1;
+                                             int t, int n, int logn) {
+  const int half = n >> 1;
   if constexpr (IN == IN_REAL) {
     const int r = t >> logn, m = t & (n - 1);
     if (m >= half) return {T(0), T(0)};
@@ -271,13 +403,33 @@ __device__ __forceinline__ int row_slot(int t, int n, int logn, int stride) {
   }
 }
 
-// two 512-thread blocks per CU (the LDS limit): at most 128 VGPRs
-template <typename T, int RB, int NT, int IN, int OUT>
+// Copies the stage twiddle tables into LDS (once per block; the loads of
+// several entries are issued before they are stored).  Twiddles read from
+// LDS leave the global-load counter to the data prefetched for the next row
+// block or state set, which then stays in flight through the FFT stages.
+template <typename T, int NT>
+__device__ __forceinline__ void tables_to_lds(cplx<T>* dst, const cplx<T>* src, int len) {
+  constexpr int U = 4;
+  for (int t0 = threadIdx.x; t0 < len; t0 += U * NT) {
+    cplx<T> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = src[min(t0 + u * NT, len - 1)];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (t0 + u * NT < len) dst[t0 + u * NT] = v[u];
+  }
+}
+
+// two 512-thread blocks per CU (the LDS limit): at most 128 VGPRs.
+// TWL: stage twiddles staged in LDS after the row buffer.  LOGN > 0: the row
+// length n = 2^LOGN is a compile-time constant (a.n must equal it).
+template <typename T, int RB, int NT, int IN, int OUT, bool TWL, int LOGN>
 __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   __shared__ double red[NT / 64];
-  const int n = a.n, logn = a.logn;
+  const int logn = LOGN > 0 ? LOGN : a.logn;
+  const int n = 1 << logn;
   const int stride = sw_stride<T>(n);
   const int lb = xcd_remap(blockIdx.x, a.nblocks);
   if (lb >= a.nblocks) return;
@@ -288,6 +440,14 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
   constexpr int EMAX = (sizeof(T) == 8 ? 16 : 32) * 256;
   constexpr int EPT = (EMAX + NT - 1) / NT;  // staged input values per thread
   const int nel = RB * n;
+  const cplx<T>* twr;
+  if constexpr (TWL) {
+    cplx<T>* twl = buf + RB * stride;
+    tables_to_lds<T, NT>(twl, a.twr, stage_table_len(logn));
+    twr = twl;  // made visible by the barrier after the first input
+  } else {
+    twr = a.twr;
+  }
   // the first set's input, then each set's input is fetched while the
   // previous set is transformed
 #if MUFFIN_ROW_PREFETCH
@@ -295,7 +455,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
     const int t = threadIdx.x + q * NT;
-    if (t < nel) pre[q] = row_input<T, RB, NT, IN>(a, 0, band, i0, t);
+    if (t < nel) pre[q] = row_input<T, RB, NT, IN>(a, 0, band, i0, t, n, logn);
   }
 #endif
   for (int set = 0; set < a.nsets; ++set) {
@@ -310,7 +470,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
 #pragma unroll
       for (int q = 0; q < EPT; ++q) {
         const int t = threadIdx.x + q * NT;
-        if (t < nel) pre[q] = row_input<T, RB, NT, IN>(a, set + 1, band, i0, t);
+        if (t < nel) pre[q] = row_input<T, RB, NT, IN>(a, set + 1, band, i0, t, n, logn);
       }
     }
 #else
@@ -347,7 +507,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
         cplx<T> v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-          v[u] = row_input<T, RB, NT, IN>(a, set, band, i0, min(t0 + u * NT, nel - 1));
+          v[u] = row_input<T, RB, NT, IN>(a, set, band, i0, min(t0 + u * NT, nel - 1), n, logn);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int t = t0 + u * NT;
@@ -356,7 +516,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
       }
     } else {
       for (int t = threadIdx.x; t < nel; t += NT)
-        buf[row_slot<T, RB, IN>(t, n, logn, stride)] = row_input<T, RB, NT, IN>(a, set, band, i0, t);
+        buf[row_slot<T, RB, IN>(t, n, logn, stride)] = row_input<T, RB, NT, IN>(a, set, band, i0, t, n, logn);
     }
     lds_barrier();
 #endif
@@ -393,7 +553,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
         }
       }
       lds_barrier();
-      lds_fft<T, NT, EMAX>(buf, logn, RB, stride, a.twr);
+      lds_fft_any<T, NT, EMAX, LOGN>(buf, logn, RB, stride, twr);
       // z = conj(buf): x[2m] = z.x, x[2m+1] = z.y for m < n/2 (image window)
       if constexpr (OUT == OUT_REAL) {
         T* o = a.out[set] + ((size_t)band * n + i0) * n;
@@ -434,7 +594,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
     }
 
     if constexpr (OUT == OUT_SPEC || OUT == OUT_PSFTMP) {
-      lds_fft<T, NT, EMAX>(buf, logn, RB, stride, a.twr);
+      lds_fft_any<T, NT, EMAX, LOGN>(buf, logn, RB, stride, twr);
       // Hermitian post-pass of the real forward transform:
       // X[k] = (Z[k] + conj Z[n-k]) / 2 - (i / 2) exp(-i pi k / n) (Z[k] - conj Z[n-k])
       for (int t = threadIdx.x; t < RB * (half + 1); t += NT) {
@@ -505,11 +665,15 @@ struct ColArgs {
   int nsets;           // state sets, processed in turn with the same K
 };
 
-template <typename T, int NT>
+// TWL: stage twiddles staged in LDS after the transfer-function columns.
+// LOGN > 0: n = 2^LOGN at compile time (a.n and a.B must match).
+template <typename T, int NT, bool TWL, int LOGN>
 __global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 4) col_pass(ColArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int n = a.n, m2 = 2 * n, B = a.B;
+  constexpr int BC = LOGN > 0 ? ((2048 >> (LOGN + 1)) > 1 ? (2048 >> (LOGN + 1)) : 1) : 0;
+  const int logn = LOGN > 0 ? LOGN : a.logn;
+  const int n = 1 << logn, m2 = 2 * n, B = LOGN > 0 ? BC : a.B;
   const int stride = sw_stride<T>(m2);
   const int lb = xcd_remap(blockIdx.x, a.nblocks);
   if (lb >= a.nblocks) return;
@@ -524,6 +688,14 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 4) col_pass(ColArgs<T
   // the block holding the packed slot 0 needs, is read from global memory.
   cplx<T>* Ks = buf + B * stride;
   const cplx<T>* Kb = a.Kh + (size_t)band * (n + 1) * m2;
+  const cplx<T>* twc;
+  if constexpr (TWL) {
+    cplx<T>* twl = Ks + B * m2;
+    tables_to_lds<T, NT>(twl, a.twc, stage_table_len(logn + 1));
+    twc = twl;  // made visible by the barrier after the first input
+  } else {
+    twc = a.twc;
+  }
   cplx<T> pre[IPT];
 #pragma unroll
   for (int q = 0; q < IPT; ++q) {
@@ -556,7 +728,7 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 4) col_pass(ColArgs<T
         if (t < nin) pre[q] = a.in[set + 1][((size_t)band * n + kx0) * n + t];
       }
     }
-    lds_fft<T, NT, EMAX>(buf, a.logn + 1, B, stride, a.twc);
+    lds_fft_any<T, NT, EMAX, (LOGN > 0 ? LOGN + 1 : 0)>(buf, logn + 1, B, stride, twc);
     for (int t = threadIdx.x; t < B * m2; t += NT) {
       const int b = t / m2, ky = t - b * m2;
       const int kx = kx0 + b;
@@ -589,7 +761,7 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 4) col_pass(ColArgs<T
       }
     }
     lds_barrier();
-    lds_fft<T, NT, EMAX>(buf, a.logn + 1, B, stride, a.twc);
+    lds_fft_any<T, NT, EMAX, (LOGN > 0 ? LOGN + 1 : 0)>(buf, logn + 1, B, stride, twc);
     cplx<T>* dst = a.out[set] + ((size_t)band * n + kx0) * n;
     for (int t = threadIdx.x; t < nin; t += NT) {
       const int b = t / n, i = t - b * n;
@@ -672,6 +844,9 @@ int fft_make_plan(FftPlan<T>& p, int n, int L, hipStream_t s) {
   }
   const std::vector<cplx<T>> tr = stage_tables<T>(logn);
   const std::vector<cplx<T>> tc = stage_tables<T>(logn + 1);
+  // the kernels size their LDS copies of the tables with stage_table_len
+  if ((int)tr.size() != stage_table_len(logn) || (int)tc.size() != stage_table_len(logn + 1))
+    return -2; /* E_SHAPE */
   MUFFIN_HIP_CHECK(hipMalloc(&p.tw, sizeof(cplx<T>) * (m2 + tr.size() + tc.size())));
   p.twr = p.tw + m2;
   p.twc = p.twr + tr.size();
@@ -698,8 +873,26 @@ static int launch_row_rb(RowArgs<T>& a, int nsets, hipStream_t s) {
   a.nsets = nsets;
   const size_t shm = sizeof(cplx<T>) * (size_t)RB * sw_stride<T>(n);
   dim3 grid(xcd_grid(a.nblocks), 1);
-  MUFFIN_ALLOW_BIG_LDS((row_pass<T, RB, kRowNT, IN, OUT>));
-  row_pass<T, RB, kRowNT, IN, OUT><<<grid, kRowNT, shm, s>>>(a);
+  // FP32 up to n = 1024: the tables (8 KB) fit beside two row blocks per CU;
+  // n = 1024 (the benchmark size) runs the compile-time form
+  constexpr bool F32 = sizeof(T) == 4;
+  const size_t shm_t = shm + sizeof(cplx<T>) * (size_t)stage_table_len(31 - __builtin_clz(n));
+  // (row blocks at n = 1024: 8 rows in FP32, 4 in FP64)
+  if constexpr (IN != IN_PSF && RB == (F32 ? 8 : 4)) {
+    if (n == 1024) {
+      MUFFIN_ALLOW_BIG_LDS((row_pass<T, RB, kRowNT, IN, OUT, F32, 10>));
+      row_pass<T, RB, kRowNT, IN, OUT, F32, 10><<<grid, kRowNT, F32 ? shm_t : shm, s>>>(a);
+      MUFFIN_HIP_CHECK(hipGetLastError());
+      return 0;
+    }
+  }
+  if (F32 && n <= 1024) {
+    MUFFIN_ALLOW_BIG_LDS((row_pass<T, RB, kRowNT, IN, OUT, F32, 0>));
+    row_pass<T, RB, kRowNT, IN, OUT, F32, 0><<<grid, kRowNT, shm_t, s>>>(a);
+  } else {
+    MUFFIN_ALLOW_BIG_LDS((row_pass<T, RB, kRowNT, IN, OUT, false, 0>));
+    row_pass<T, RB, kRowNT, IN, OUT, false, 0><<<grid, kRowNT, shm, s>>>(a);
+  }
   MUFFIN_HIP_CHECK(hipGetLastError());
   return 0;
 }
@@ -743,12 +936,19 @@ static int launch_col(const FftPlan<T>& p, const cplx<T>* const* in, cplx<T>* co
   // FFT buffer + the block's transfer-function columns
   const size_t shm = sizeof(cplx<T>) * (size_t)a.B * (sw_stride<T>(2 * p.n) + 2 * p.n);
   dim3 grid(xcd_grid(a.nblocks), 1);
-  if (2 * p.n <= 2048) {
-    MUFFIN_ALLOW_BIG_LDS((col_pass<T, 256>));
-    col_pass<T, 256><<<grid, 256, shm, s>>>(a);
+  // FP32 up to 2n = 2048: tables (16 KB) in LDS, three blocks per CU;
+  // n = 1024 (the benchmark size) runs the compile-time form
+  constexpr bool F32 = sizeof(T) == 4;
+  const size_t shm_t = shm + sizeof(cplx<T>) * (size_t)stage_table_len(a.logn + 1);
+  if (p.n == 1024) {
+    MUFFIN_ALLOW_BIG_LDS((col_pass<T, 256, F32, 10>));
+    col_pass<T, 256, F32, 10><<<grid, 256, F32 ? shm_t : shm, s>>>(a);
+  } else if (2 * p.n <= 2048) {
+    MUFFIN_ALLOW_BIG_LDS((col_pass<T, 256, F32, 0>));
+    col_pass<T, 256, F32, 0><<<grid, 256, F32 ? shm_t : shm, s>>>(a);
   } else {
-    MUFFIN_ALLOW_BIG_LDS((col_pass<T, 512>));
-    col_pass<T, 512><<<grid, 512, shm, s>>>(a);
+    MUFFIN_ALLOW_BIG_LDS((col_pass<T, 512, false, 0>));
+    col_pass<T, 512, false, 0><<<grid, 512, shm, s>>>(a);
   }
   MUFFIN_HIP_CHECK(hipGetLastError());
   return 0;
