@@ -30,8 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # per voxel (all state sets of the launch together): (working-precision
 # values, mask bytes).  Each input and output array is counted once.
 #   synthesis_l1: per set the 6 level-1 detail coefficients of the 8 bases
-#     (8 x 3/4) + the 2 coarse values (8 x 1/4) in, S out; the two d/dmu sets
-#     also read the primal's 6 detail coefficients.  6 sets: 4*9 + 2*15.
+#     (8 x 3/4) + the 2 coarse values (8 x 1/4) in, S out.  6 sets: 6*9.
 #   analysis_l1_primal: per set x~, x in; 6 detail coefficients read and
 #     written; 2 low-pass values out; 6 mask bytes out.  2 sets.
 #   analysis_l1_deriv: as above with the mask read; the d/dmu sets read the
@@ -42,7 +41,7 @@ HBM_PEAK_GBS = 8000.0
 #   primal_step: per trajectory x, G, H^T y, S, T in, x~ out; each
 #     derivative x', G', S', T' in, x~' out.  2 trajectories: 2*(6+5+5).
 STAGE_TRAFFIC = {
-    "synthesis_l1": (66, 0),
+    "synthesis_l1": (54, 0),
     "analysis_l1_primal": (32, 12),
     "analysis_l1_deriv": (68, 24),
     "dct_primal": (10, 2),

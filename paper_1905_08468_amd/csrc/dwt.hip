@@ -571,14 +571,11 @@ __device__ __forceinline__ void store4(T* dst, const T (&acc)[2][2], T sc, bool 
 // DEEP = false: level 1 (the bases' syntheses summed into S); true: the
 // coarser levels (one output per basis).
 // PN: number of bases when known at compile time, or 0 (see dwt_an).
-template <typename T, int TC, int NT, bool DEEP, int PN>
-__global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_sy(SyArgs<T> a) {
+// UB: the set combines two dual arrays (a1 U_a + a2 U_b, the d/dmu sets).
+template <typename T, int TC, int NT, bool DEEP, int PN, bool UB>
+__device__ __forceinline__ void sy_block(const SyArgs<T>& a, int lb, T* s_q, T* s_r) {
   constexpr int W = TC + kSHal;
   constexpr int NQ = (4 * W * W + NT - 1) / NT;  // tile values per thread
-  __shared__ T s_q[4 * W * W];
-  __shared__ T s_r[2 * TC * 2 * W];
-  const int lb = xcd_remap_d(blockIdx.x, a.nblocks);
-  if (lb >= a.nblocks) return;
   const int tiles2 = a.tiles * a.tiles;
   const int band = lb / tiles2;
   const int tile = lb - band * tiles2;
@@ -610,7 +607,12 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_sy(SyArgs<T> a) {
   // wrap), computed once: the low-low quadrant reads the coarser level's
   // output (offset in a half x half plane, flagged by a negative value) when
   // there is one, the other quadrants read U.
-  int off[NQ];
+  // Byte offsets of this thread's tile values inside their source plane
+  // (periodic wrap; also valid for the idle tail t >= 4 W^2).  Values of the
+  // low-low quadrant (t < W^2) come from the coarser level's output when
+  // there is one, the others from U.
+  constexpr int Q0 = W * W;
+  uint32_t off[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const int t = threadIdx.x + i * NT;
@@ -618,19 +620,25 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_sy(SyArgs<T> a) {
     const int r = rem / W, c = rem - r * W;
     const int kr = (kr0 - kSHal + r) & hm, kc = (kc0 - kSHal + c) & hm;
     if (quad == 0 && has_ll) {
-      off[i] = -1 - (kr * half + kc);
+      off[i] = (uint32_t)((kr * half + kc) * (int)sizeof(T));
     } else {
       const int roff = (quad & 1) ? half : 0, coff = (quad & 2) ? half : 0;
-      off[i] = (roff + kr) * n + (coff + kc);
+      off[i] = (uint32_t)(((roff + kr) * n + (coff + kc)) * (int)sizeof(T));
     }
   }
   const T ta1 = T(a1), ta2 = T(a2);
-  const bool has_ub = a.Ub[set] != nullptr;
+  constexpr bool has_ub = UB;
+  auto ld = [](const T* base, uint32_t boff) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
+  };
   // Raw tile values of one basis: ra from U (or the coarser level's output
   // for the low-low quadrant), rb from the second dual array when the set
-  // combines two.  The loads are unconditional (no branch between a load and
-  // its use), so all of them stay in flight while the previous basis is
-  // filtered; the combination is applied when the tile is written to LDS.
+  // combines two.  The source of slot i is known from i except for the one
+  // slot that straddles the low-low quadrant's end, so the loads take a
+  // uniform base and a 32-bit offset; they are unconditional (no branch
+  // between a load and its use), so all of them stay in flight while the
+  // previous basis is filtered, and the combination is applied when the tile
+  // is written to LDS.
   T ra[NQ], rb[NQ];
   auto fetch = [&](int pidx) {
     const T* Ua = a.Ua[set] + ((size_t)band * a.P + pidx) * plane;
@@ -638,11 +646,19 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_sy(SyArgs<T> a) {
     const T* ll = has_ll ? a.llin[set] + ((size_t)band * a.P + pidx) * (size_t)half * half : Ua;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
-      const int t = threadIdx.x + i * NT;
-      if (t < 4 * W * W) {
-        const int o = off[i];
-        ra[i] = o < 0 ? ll[-1 - o] : Ua[o];
-        if (has_ub) rb[i] = Ub[o < 0 ? 0 : o];
+      const bool q0 = has_ll && (int)threadIdx.x + i * NT < Q0;
+      if constexpr (UB) {
+        // two arrays: per-lane source and address (measured faster here
+        // than two uniform-base loads per slot); the low-low values of
+        // the coarsest level are U values and are combined too
+        ra[i] = ld(q0 ? ll : Ua, off[i]);
+        rb[i] = ld(Ub, q0 ? 0u : off[i]);
+      } else if ((i + 1) * NT <= Q0) {
+        ra[i] = ld(ll, off[i]);  // (ll = Ua at the coarsest level)
+      } else if (i * NT >= Q0) {
+        ra[i] = ld(Ua, off[i]);
+      } else {
+        ra[i] = ld(q0 ? ll : Ua, off[i]);
       }
     }
   };
@@ -651,8 +667,9 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_sy(SyArgs<T> a) {
     for (int i = 0; i < NQ; ++i) {
       const int t = threadIdx.x + i * NT;
       if (t < 4 * W * W) {
+        const bool q0 = has_ll && t < Q0;
         T v = ra[i];
-        if (off[i] >= 0) {
+        if (!q0) {
           v = ta1 * v;
           if (has_ub) v = fma(ta2, rb[i], v);
         }
@@ -690,6 +707,18 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_sy(SyArgs<T> a) {
     T* dst = a.S[set] + (size_t)band * plane + (size_t)row * n + col;
     store4(dst, acc, T(beta / sqrt((double)a.P)), col + 3 < Ms);
   }
+}
+
+// One launch per kind of set: UB (the sets combining two dual arrays) or not,
+// so each kernel holds one compact instantiation.
+template <typename T, int TC, int NT, bool DEEP, int PN, bool UB>
+__global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_sy(SyArgs<T> a) {
+  constexpr int W = TC + kSHal;
+  __shared__ T s_q[4 * W * W];
+  __shared__ T s_r[2 * TC * 2 * W];
+  const int lb = xcd_remap_d(blockIdx.x, a.nblocks);
+  if (lb >= a.nblocks) return;
+  sy_block<T, TC, NT, DEEP, PN, UB>(a, lb, s_q, s_r);
 }
 
 // ---------------------------------------------------------------------------
@@ -755,41 +784,50 @@ int dwt_synthesis(const DwtPlan<T>& p, const SynthesisIO<T>& io, const DevParams
   if (lev_lo <= 0) lev_lo = 1;
   if (lev_hi <= 0 || lev_hi > p.J) lev_hi = p.J;
   for (int lev = lev_hi; lev >= lev_lo; --lev) {
-    SyArgs<T> a{};
-    for (int i = 0; i < io.nsets; ++i) {
-      a.Ua[i] = io.Ua[i];
-      a.Ub[i] = io.Ub[i];
-      a.a1_sel[i] = io.a1_sel[i];
-      a.a2_sel[i] = io.a2_sel[i];
-      // output of level j (j >= 2, side n >> (j-1)): tmp0 for even j, tmp1 for odd j
-      a.llin[i] = lev < p.J ? ((lev + 1) % 2 == 0 ? io.tmp0[i] : io.tmp1[i]) : nullptr;
-      a.llout[i] = lev >= 2 ? (lev % 2 == 0 ? io.tmp0[i] : io.tmp1[i]) : nullptr;
-      a.S[i] = io.S[i];
+    // two launches: the sets without a second dual array, then those with one
+    for (int ub = 0; ub < 2; ++ub) {
+      SyArgs<T> a{};
+      int ns = 0;
+      for (int i = 0; i < io.nsets; ++i) {
+        if ((io.Ub[i] != nullptr) != (ub == 1)) continue;
+        a.Ua[ns] = io.Ua[i];
+        a.Ub[ns] = io.Ub[i];
+        a.a1_sel[ns] = io.a1_sel[i];
+        a.a2_sel[ns] = io.a2_sel[i];
+        // output of level j (j >= 2, side n >> (j-1)): tmp0 for even j, tmp1 for odd j
+        a.llin[ns] = lev < p.J ? ((lev + 1) % 2 == 0 ? io.tmp0[i] : io.tmp1[i]) : nullptr;
+        a.llout[ns] = lev >= 2 ? (lev % 2 == 0 ? io.tmp0[i] : io.tmp1[i]) : nullptr;
+        a.S[ns] = io.S[i];
+        ++ns;
+      }
+      if (ns == 0) continue;
+      a.beta = io.beta;
+      a.dp = dp;
+      a.n = p.n;
+      a.L = p.L;
+      a.P = p.P;
+      a.level = lev;
+      a.J = p.J;
+      a.Ms = p.n >> (lev - 1);
+      a.pure = io.pure;
+      const int half = a.Ms >> 1;
+      a.tiles = (half + kTO - 1) / kTO;
+      a.nblocks = a.tiles * a.tiles * p.L;
+      dim3 grid(xcd_grid_h(a.nblocks), ns);
+      // (the basis count stays a run-time value here: compiled for P = 8 the
+      // fully unrolled kernel needs 137 VGPRs and runs at half the occupancy)
+      if (lev == 1) {
+        if (ub) dwt_sy<T, kTO, kNT, false, 0, true><<<grid, kNT, 0, s>>>(a);
+        else dwt_sy<T, kTO, kNT, false, 0, false><<<grid, kNT, 0, s>>>(a);
+      } else {
+        if (ub) dwt_sy<T, kTO, kNT, true, 0, true><<<grid, kNT, 0, s>>>(a);
+        else dwt_sy<T, kTO, kNT, true, 0, false><<<grid, kNT, 0, s>>>(a);
+      }
+      MUFFIN_HIP_CHECK(hipGetLastError());
     }
-    a.beta = io.beta;
-    a.dp = dp;
-    a.n = p.n;
-    a.L = p.L;
-    a.P = p.P;
-    a.level = lev;
-    a.J = p.J;
-    a.Ms = p.n >> (lev - 1);
-    a.pure = io.pure;
-    const int half = a.Ms >> 1;
-    a.tiles = (half + kTO - 1) / kTO;
-    a.nblocks = a.tiles * a.tiles * p.L;
-    dim3 grid(xcd_grid_h(a.nblocks), io.nsets);
-    // (the basis count stays a run-time value here: compiled for P = 8 the
-    // fully unrolled kernel needs 137 VGPRs and runs at half the occupancy)
-    if (lev == 1)
-      dwt_sy<T, kTO, kNT, false, 0><<<grid, kNT, 0, s>>>(a);
-    else
-      dwt_sy<T, kTO, kNT, true, 0><<<grid, kNT, 0, s>>>(a);
-    MUFFIN_HIP_CHECK(hipGetLastError());
   }
   return 0;
 }
-
 template int dwt_analysis<double>(const DwtPlan<double>&, const AnalysisIO<double>&,
                                   const DevParams*, hipStream_t, int, int);
 template int dwt_analysis<float>(const DwtPlan<float>&, const AnalysisIO<float>&,

@@ -36,6 +36,7 @@ __global__ void __launch_bounds__(kEwNT) primal_kernel(PrimalIO<T> io, size_t co
                                                        const DevParams* dp) {
   const int tr = blockIdx.y;
   const T tau = T(dp->tau);
+  const T mu = T(dp->mu);
   const T* __restrict__ x0 = io.x[tr][0];
   const T* __restrict__ g0 = io.g[tr][0];
   const T* __restrict__ hy = io.hty[tr];
@@ -56,13 +57,19 @@ __global__ void __launch_bounds__(kEwNT) primal_kernel(PrimalIO<T> io, size_t co
         td[d] = io.t[tr][d + 1][i];
       }
     }
-    const T m = x0[i] - tau * ((g0[i] - hy[i]) + s0[i] + t0[i]);
+    // s arrays hold beta_l / sqrt(P) W_s^T u of their own set; the spatial
+    // term of the primal update is mu s, and its mu-derivative
+    // s + mu s' (the primal's s is in registers already)
+    const T sp = s0[i];
+    const T m = x0[i] - tau * ((g0[i] - hy[i]) + mu * sp + t0[i]);
     const bool pos = m > T(0);
     o0[i] = pos ? m : T(0);
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
       if (d < nd) {
-        const T md = xd[d] - tau * (gd[d] + sd[d] + td[d]);
+        T sterm = mu * sd[d];
+        if (d == 0) sterm += sp;  // d/dmu set
+        const T md = xd[d] - tau * (gd[d] + sterm + td[d]);
         io.xt[tr][d + 1][i] = pos ? md : T(0);
       }
     }

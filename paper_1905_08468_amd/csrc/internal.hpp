@@ -196,7 +196,7 @@ struct PrimalIO {
   const T* x[2][3];
   const T* g[2][3];      // H^T H x
   const T* hty[2];       // H^T y of the trajectory (primal only)
-  const T* s[2][3];
+  const T* s[2][3];      // beta_l / sqrt(P) W_s^T u of each set (no mu)
   const T* t[2][3];
   T* xt[2][3];
   int ntraj, nderiv;

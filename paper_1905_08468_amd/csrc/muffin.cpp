@@ -504,20 +504,17 @@ struct Impl final : ImplBase {
       SynthesisIO<T> io{};
       io.nsets = nsets;
       io.beta = beta;
+      // Every set synthesises its own dual variable, S = beta / sqrt(P)
+      // W_s^T U (linear, so the mu-derivative's W_s^T (mu U' + U) is
+      // mu S' + S of the primal set: the primal step combines them)
       for (int s = 0; s < nsets; ++s) {
         io.Ua[s] = U[s];
-        io.a1_sel[s] = SEL_MU;
+        io.a1_sel[s] = SEL_ONE;
         io.Ub[s] = nullptr;
         io.a2_sel[s] = SEL_ZERO;
         io.S[s] = S[s];
         io.tmp0[s] = tmp0(s);
         io.tmp1[s] = tmp1(s);
-      }
-      if (sure) {
-        io.Ub[2] = U[0];
-        io.a2_sel[2] = SEL_ONE;
-        io.Ub[4] = U[1];
-        io.a2_sel[4] = SEL_ONE;
       }
       if (J >= 2) {
         tm.begin(ST_SYN_DEEP, st);
