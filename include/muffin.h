@@ -82,6 +82,16 @@ typedef struct {
   int32_t deriv_reset;  /* 1: derivative states restart at each theta update */
   int32_t pi_iters;     /* max power iterations for beta_H (if tau <= 0) */
   double pi_tol;        /* relative change stopping the power iteration */
+  double stop_rel;      /* > 0: muffin_run stops once the relative change of
+                           the Y trajectory over one iteration,
+                           max(|X^k - X^(k-1)| / |X^k|,
+                               sqrt(|dU|^2 + |dV|^2) / sqrt(|U^k|^2 + |V^k|^2)),
+                           is <= stop_rel (checked every check_every
+                           iterations; FP64 sums).  The paper fixes no
+                           stopping rule; this is the relative primal-dual
+                           residual of the serving form.  0: run exactly
+                           the requested iterations. */
+  int32_t check_every;  /* iterations between checks of stop_rel, >= 1 */
 } muffin_config;
 
 typedef struct {
@@ -93,11 +103,14 @@ typedef struct {
   double sugar_mu;        /* SUGAR-FDMC at the last update (eq. `SUGAR`) */
   double sugar_gamma;
   double res2;            /* ||Y - H X||^2 at the last update */
+  double last_rel_change; /* last checked relative change (stop_rel), or -1 */
+  int32_t stopped;        /* 1: the last muffin_run ended on stop_rel */
 } muffin_report;
 
 /* Fills *cfg with the paper's defaults for an n x n x L cube: P = 8 bases,
  * J = 3 levels (fewer when n is small), sigma = 10, Delta = 10, OPNORM rule,
- * rho = 0.99, eps_w = 1e-6, plain MUFFIN (sure = 0), mu = gamma = 1. */
+ * rho = 0.99, eps_w = 1e-6, plain MUFFIN (sure = 0), mu = gamma = 1, no
+ * stopping rule (stop_rel = 0, check_every = 10). */
 int muffin_default_config(muffin_config* cfg, int32_t n, int32_t L);
 
 /* Device bytes the handle will hold for *cfg (admission control).  Returns 0
@@ -124,8 +137,32 @@ int muffin_set_problem(muffin_handle* h, const void* dirty, const void* psf,
 
 /* Runs `iters` iterations (Algorithm 2, or Algorithm 5 when sure), resuming
  * from the current state.  If report != NULL the stream is synchronised and
- * *report filled; otherwise the call only enqueues work. */
+ * *report filled; otherwise the call only enqueues work (with stop_rel > 0
+ * it synchronises at every check and may stop early). */
 int muffin_run(muffin_handle* h, int32_t iters, muffin_report* report);
+
+/* Initial estimate X^(0) = x0 (device cube [L][n][n]) for both trajectories
+ * instead of 0 (Algorithm 5's initialisation; dual and derivative states
+ * stay zero).  Call after muffin_set_problem. */
+int muffin_set_initial(muffin_handle* h, const void* x0);
+
+/* Checkpoint of the iteration state (X, U, V, T of every state set, the
+ * device scalars theta, tau, sums, the iteration and update counters and the
+ * theta history) in a host buffer of muffin_state_bytes(h) bytes.  Loading
+ * requires a handle of the same configuration with the same problem set;
+ * mismatches return E_SHAPE, a foreign buffer E_INVAL.  Both synchronise the
+ * stream.  A run resumed from a checkpoint continues exactly as the
+ * uninterrupted run. */
+size_t muffin_state_bytes(muffin_handle* h);
+int muffin_state_save(muffin_handle* h, void* host_buf, size_t bytes);
+int muffin_state_load(muffin_handle* h, const void* host_buf, size_t bytes);
+
+/* One call: create, set_problem (weights NULL -> rule of Section 2.1),
+ * optional x0, run `iters` iterations (or to cfg->stop_rel), copy the sky to
+ * sky_out (device [L][n][n]), destroy.  Synchronises `stream`. */
+int muffin_solve(const muffin_config* cfg, const void* dirty, const void* psf,
+                 const double* alpha, const double* beta, const void* delta, const void* x0,
+                 int32_t iters, void* sky_out, muffin_report* report, void* stream);
 
 /* Copies the current sky estimate X (Y trajectory) to x_out [L][n][n]. */
 int muffin_get_sky(muffin_handle* h, void* x_out);

@@ -218,6 +218,68 @@ int axpy_copy(T* out, const T* a, const T* b, double beta, size_t count, hipStre
 }
 
 template <typename T>
+__global__ void copy_kernel(T* out, const T* in, size_t count) {
+  for (size_t i = blockIdx.x * (size_t)kEwNT + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * kEwNT)
+    out[i] = in[i];
+}
+
+template <typename T>
+int copy_dev(T* out, const T* in, size_t count, hipStream_t s) {
+  if (count == 0) return 0;
+  const int bx = (int)std::min<size_t>((count + kEwNT - 1) / kEwNT, 8192);
+  copy_kernel<T><<<bx, kEwNT, 0, s>>>(out, in, count);
+  MUFFIN_HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+// Per block: sum (a - b)^2 and sum a^2 in FP64 (fixed order: deterministic).
+template <typename T>
+__global__ void __launch_bounds__(kEwNT) diffsq_kernel(const T* a, const T* b, size_t count,
+                                                       double* partials) {
+  __shared__ double sh[kEwNT / 64];
+  double d2 = 0.0, a2 = 0.0;
+  for (size_t i = blockIdx.x * (size_t)kEwNT + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * kEwNT) {
+    const double av = double(a[i]), dv = av - double(b[i]);
+    d2 += dv * dv;
+    a2 += av * av;
+  }
+  const double sd = block_sum_all<kEwNT>(d2, sh);
+  const double sa = block_sum_all<kEwNT>(a2, sh);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = sd;
+    partials[2 * blockIdx.x + 1] = sa;
+  }
+}
+
+__global__ void __launch_bounds__(kEwNT) reduce2_kernel(const double* partials, int count,
+                                                        double* out) {
+  __shared__ double sh[kEwNT / 64];
+  double d = 0.0, a = 0.0;
+  for (int i = threadIdx.x; i < count; i += kEwNT) {
+    d += partials[2 * i];
+    a += partials[2 * i + 1];
+  }
+  const double sd = block_sum_all<kEwNT>(d, sh);
+  const double sa = block_sum_all<kEwNT>(a, sh);
+  if (threadIdx.x == 0) {
+    out[0] = sd;
+    out[1] = sa;
+  }
+}
+
+template <typename T>
+int diff_sq(const T* a, const T* b, size_t count, double* partials, int nblocks, double* out,
+            hipStream_t s) {
+  diffsq_kernel<T><<<nblocks, kEwNT, 0, s>>>(a, b, count, partials);
+  MUFFIN_HIP_CHECK(hipGetLastError());
+  reduce2_kernel<<<1, kEwNT, 0, s>>>(partials, nblocks, out);
+  MUFFIN_HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+template <typename T>
 __global__ void nonfinite_kernel(const T* p, size_t count, int* flag) {
   int bad = 0;
   for (size_t i = blockIdx.x * (size_t)kEwNT + threadIdx.x; i < count;
@@ -398,6 +460,12 @@ template int dot_partials<float>(const float*, const float*, const float*, size_
 template int fill_zero<double>(double*, size_t, hipStream_t);
 template int fill_zero<float>(float*, size_t, hipStream_t);
 template int fill_zero<uint8_t>(uint8_t*, size_t, hipStream_t);
+template int copy_dev<double>(double*, const double*, size_t, hipStream_t);
+template int copy_dev<float>(float*, const float*, size_t, hipStream_t);
+template int diff_sq<double>(const double*, const double*, size_t, double*, int, double*,
+                             hipStream_t);
+template int diff_sq<float>(const float*, const float*, size_t, double*, int, double*,
+                            hipStream_t);
 template int axpy_copy<double>(double*, const double*, const double*, double, size_t, hipStream_t);
 template int axpy_copy<float>(float*, const float*, const float*, double, size_t, hipStream_t);
 template int count_nonfinite<double>(const double*, size_t, int*, hipStream_t);

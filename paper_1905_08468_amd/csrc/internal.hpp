@@ -217,6 +217,13 @@ int fill_zero(T* p, size_t count, hipStream_t s);
 template <typename T>
 int axpy_copy(T* out, const T* a, const T* b, double beta, size_t count, hipStream_t s);
 template <typename T>
+int copy_dev(T* out, const T* in, size_t count, hipStream_t s);
+// out[0] = sum (a - b)^2, out[1] = sum a^2 (FP64, deterministic); partials
+// holds 2 nblocks doubles.
+template <typename T>
+int diff_sq(const T* a, const T* b, size_t count, double* partials, int nblocks, double* out,
+            hipStream_t s);
+template <typename T>
 int count_nonfinite(const T* p, size_t count, int* flag, hipStream_t s);
 template <typename T, typename U>
 int convert(U* out, const T* in, size_t count, hipStream_t s);

@@ -131,6 +131,8 @@ int validate(const muffin_config* c) {
     if (!(c->eta_mu >= 0) || !(c->eta_gamma >= 0)) return MUFFIN_E_INVAL;
   }
   if (c->tau <= 0 && c->pi_iters < 1) return MUFFIN_E_INVAL;
+  if (!(c->stop_rel >= 0)) return MUFFIN_E_INVAL;
+  if (c->stop_rel > 0 && c->check_every < 1) return MUFFIN_E_INVAL;
   return MUFFIN_OK;
 }
 
@@ -168,6 +170,10 @@ struct ImplBase {
   virtual int history(double* rows, int max_rows) = 0;
   virtual int weights(double* alpha, double* beta) = 0;
   virtual int op(int kind, const void* in, void* out) = 0;
+  virtual int set_initial(const void* x0) = 0;
+  virtual size_t state_bytes() = 0;
+  virtual int state_save(void* buf, size_t bytes) = 0;
+  virtual int state_load(const void* buf, size_t bytes) = 0;
   virtual Timer& timer() = 0;
   virtual hipStream_t stream() = 0;
 };
@@ -184,6 +190,7 @@ size_t workspace_bytes_of(const muffin_config* c) {
   shared += L * (n + 1) * 2 * n * 2 * es;                        // transfer functions
   shared += c->sure ? 2 * (P + 1) * LN : 0;                      // masks (bytes)
   shared += (N + L) * 8 + 4096 * 8 + 64 * 1024;                  // weights, partials, params
+  if (c->stop_rel > 0) shared += (P + 1) * LN * es;              // U, V snapshots (stop rule)
   return nsets * per_set + shared;
 }
 
@@ -206,6 +213,12 @@ struct Impl final : ImplBase {
   T *Y = nullptr, *Ybar = nullptr, *HTy = nullptr, *HTybar = nullptr, *HTd = nullptr;
   double *alpha = nullptr, *beta = nullptr, *partials = nullptr, *hist = nullptr;
   int* flag = nullptr;
+  // stopping rule: U, V of the Y trajectory before a checked iteration, and
+  // the six FP64 sums of the relative change
+  T *Usnap = nullptr, *Vsnap = nullptr;
+  double* relsum = nullptr;
+  double last_rel = -1.0;
+  bool stopped = false;
   int max_hist = 0;
   bool have_problem = false;
   int k_done = 0;
@@ -266,6 +279,11 @@ struct Impl final : ImplBase {
     hist = dev.alloc<double>((size_t)max_hist * kHistCols);
     dp = dev.alloc<DevParams>(1);
     flag = dev.alloc<int>(1);
+    if (cfg.stop_rel > 0) {
+      Usnap = dev.alloc<T>(LN * P);
+      Vsnap = dev.alloc<T>(LN);
+      relsum = dev.alloc<double>(8);
+    }
     if (dev.failed) {
       dev.release();
       return MUFFIN_E_NOMEM;
@@ -477,6 +495,8 @@ struct Impl final : ImplBase {
     }
     MUFFIN_HIP_CHECK(hipStreamSynchronize(st));
     k_done = 0;
+    last_rel = -1.0;
+    stopped = false;
     n_upd = 0;
     have_problem = true;
     return 0;
@@ -693,13 +713,133 @@ struct Impl final : ImplBase {
     return 0;
   }
 
+  // Relative change of the Y trajectory over the iteration just run (the
+  // stopping rule): max(|X^k - X^(k-1)| / |X^k|,
+  // sqrt(|dU|^2 + |dV|^2) / sqrt(|U^k|^2 + |V^k|^2)), FP64 sums.
+  int rel_change(double* out) {
+    const int nb = dot_blocks();
+    RC(diff_sq<T>(X[0], Xt[0], LN, partials, nb, relsum, st));
+    RC(diff_sq<T>(U[0], Usnap, LN * P, partials, nb, relsum + 2, st));
+    RC(diff_sq<T>(V[0], Vsnap, LN, partials, nb, relsum + 4, st));
+    double h[6];
+    MUFFIN_HIP_CHECK(hipMemcpyAsync(h, relsum, sizeof(h), hipMemcpyDeviceToHost, st));
+    MUFFIN_HIP_CHECK(hipStreamSynchronize(st));
+    auto ratio = [](double num, double den) {
+      if (den > 0) return num / den;
+      return num > 0 ? HUGE_VAL : 0.0;
+    };
+    const double rx = ratio(h[0], h[1]);
+    const double rd = ratio(h[2] + h[4], h[3] + h[5]);
+    *out = std::sqrt(std::max(rx, rd));
+    return 0;
+  }
+
   int run(int iters) override {
     if (!have_problem) return MUFFIN_E_STATE;
     if (iters < 0) return MUFFIN_E_INVAL;
+    stopped = false;
     for (int i = 0; i < iters; ++i) {
+      const bool check = cfg.stop_rel > 0 && (k_done + 1) % cfg.check_every == 0;
+      if (check) {
+        RC(copy_dev<T>(Usnap, U[0], LN * P, st));
+        RC(copy_dev<T>(Vsnap, V[0], LN, st));
+      }
       RC(iterate());
       if (tm.on && tm.used > 4096) RC(tm.collect(st));
+      if (check) {
+        RC(rel_change(&last_rel));
+        if (last_rel <= cfg.stop_rel) {
+          stopped = true;
+          break;
+        }
+      }
     }
+    return 0;
+  }
+
+  int set_initial(const void* x0) override {
+    if (!have_problem) return MUFFIN_E_STATE;
+    if (!x0) return MUFFIN_E_INVAL;
+    // both trajectories start from x0; derivative states stay zero
+    const int ntraj = cfg.sure ? 2 : 1;
+    for (int t = 0; t < ntraj; ++t)
+      MUFFIN_HIP_CHECK(hipMemcpyAsync(X[t], x0, sizeof(T) * LN, hipMemcpyDeviceToDevice, st));
+    return 0;
+  }
+
+  // ---- checkpoint: header, device scalars, per set X, U, V, T, history ----
+  struct StateHeader {
+    char magic[8];
+    int32_t version, n, L, P, J, mode, sure, nsets, elem, k_done, n_upd, max_hist;
+    DevParams params;
+  };
+  size_t state_bytes() override {
+    return sizeof(StateHeader) + (size_t)nsets * (3 + P) * LN * sizeof(T) +
+           (size_t)max_hist * kHistCols * sizeof(double);
+  }
+  void state_regions(std::vector<std::pair<void*, size_t>>& r) {
+    for (int s = 0; s < nsets; ++s) {
+      r.push_back({X[s], LN * sizeof(T)});
+      r.push_back({U[s], LN * P * sizeof(T)});
+      r.push_back({V[s], LN * sizeof(T)});
+      r.push_back({Tt[s], LN * sizeof(T)});
+    }
+    r.push_back({hist, (size_t)max_hist * kHistCols * sizeof(double)});
+  }
+  int state_save(void* buf, size_t bytes) override {
+    if (!have_problem) return MUFFIN_E_STATE;
+    if (!buf || bytes < state_bytes()) return MUFFIN_E_INVAL;
+    StateHeader hd{};
+    std::memcpy(hd.magic, "MUFFINST", 8);
+    hd.version = 1;
+    hd.n = n;
+    hd.L = L;
+    hd.P = P;
+    hd.J = J;
+    hd.mode = cfg.mode;
+    hd.sure = cfg.sure;
+    hd.nsets = nsets;
+    hd.elem = (int)sizeof(T);
+    hd.k_done = k_done;
+    hd.n_upd = n_upd;
+    hd.max_hist = max_hist;
+    MUFFIN_HIP_CHECK(hipMemcpyAsync(&hd.params, dp, sizeof(DevParams), hipMemcpyDeviceToHost, st));
+    MUFFIN_HIP_CHECK(hipStreamSynchronize(st));
+    char* o = static_cast<char*>(buf);
+    std::memcpy(o, &hd, sizeof(hd));
+    o += sizeof(hd);
+    std::vector<std::pair<void*, size_t>> r;
+    state_regions(r);
+    for (auto& e : r) {
+      MUFFIN_HIP_CHECK(hipMemcpy(o, e.first, e.second, hipMemcpyDeviceToHost));
+      o += e.second;
+    }
+    return 0;
+  }
+  int state_load(const void* buf, size_t bytes) override {
+    if (!have_problem) return MUFFIN_E_STATE;
+    if (!buf || bytes < sizeof(StateHeader)) return MUFFIN_E_INVAL;
+    StateHeader hd;
+    std::memcpy(&hd, buf, sizeof(hd));
+    if (std::memcmp(hd.magic, "MUFFINST", 8) != 0 || hd.version != 1) return MUFFIN_E_INVAL;
+    if (hd.n != n || hd.L != L || hd.P != P || hd.J != J || hd.mode != cfg.mode ||
+        hd.sure != cfg.sure || hd.nsets != nsets || hd.elem != (int)sizeof(T) ||
+        hd.max_hist != max_hist)
+      return MUFFIN_E_SHAPE;
+    if (bytes < state_bytes()) return MUFFIN_E_INVAL;
+    MUFFIN_HIP_CHECK(hipStreamSynchronize(st));
+    const char* o = static_cast<const char*>(buf) + sizeof(hd);
+    std::vector<std::pair<void*, size_t>> r;
+    state_regions(r);
+    for (auto& e : r) {
+      MUFFIN_HIP_CHECK(hipMemcpy(e.first, o, e.second, hipMemcpyHostToDevice));
+      o += e.second;
+    }
+    MUFFIN_HIP_CHECK(hipMemcpy(dp, &hd.params, sizeof(DevParams), hipMemcpyHostToDevice));
+    k_done = hd.k_done;
+    n_upd = hd.n_upd;
+    last_rel = -1.0;
+    stopped = false;
     return 0;
   }
 
@@ -710,6 +850,8 @@ struct Impl final : ImplBase {
     std::memset(r, 0, sizeof(*r));
     r->iters_done = k_done;
     r->theta_updates = h.n_updates;
+    r->last_rel_change = last_rel;
+    r->stopped = stopped ? 1 : 0;
     r->mu = h.mu;
     r->gamma = h.gamma;
     r->tau = h.tau;
@@ -860,6 +1002,8 @@ int muffin_default_config(muffin_config* c, int32_t n, int32_t L) {
   c->deriv_reset = 1;
   c->pi_iters = 200;
   c->pi_tol = 1e-10;
+  c->stop_rel = 0.0;
+  c->check_every = 10;
   return MUFFIN_OK;
 }
 
@@ -930,6 +1074,42 @@ int muffin_get_weights(muffin_handle* h, double* alpha, double* beta) {
 int muffin_get_report(muffin_handle* h, muffin_report* report) {
   if (!h || !report) return MUFFIN_E_INVAL;
   return h->impl->report(report);
+}
+
+int muffin_set_initial(muffin_handle* h, const void* x0) {
+  if (!h) return MUFFIN_E_INVAL;
+  return h->impl->set_initial(x0);
+}
+
+size_t muffin_state_bytes(muffin_handle* h) {
+  if (!h) return 0;
+  return h->impl->state_bytes();
+}
+
+int muffin_state_save(muffin_handle* h, void* host_buf, size_t bytes) {
+  if (!h) return MUFFIN_E_INVAL;
+  return h->impl->state_save(host_buf, bytes);
+}
+
+int muffin_state_load(muffin_handle* h, const void* host_buf, size_t bytes) {
+  if (!h) return MUFFIN_E_INVAL;
+  return h->impl->state_load(host_buf, bytes);
+}
+
+int muffin_solve(const muffin_config* cfg, const void* dirty, const void* psf,
+                 const double* alpha, const double* beta, const void* delta, const void* x0,
+                 int32_t iters, void* sky_out, muffin_report* report, void* stream) {
+  if (!sky_out) return MUFFIN_E_INVAL;
+  muffin_handle* h = nullptr;
+  int rc = muffin_create(&h, cfg, stream);
+  if (rc) return rc;
+  rc = muffin_set_problem(h, dirty, psf, alpha, beta, delta);
+  if (!rc && x0) rc = muffin_set_initial(h, x0);
+  if (!rc) rc = muffin_run(h, iters, report);
+  if (!rc) rc = muffin_get_sky(h, sky_out);
+  if (!rc && hipStreamSynchronize(h->stream) != hipSuccess) rc = MUFFIN_E_HIP;
+  muffin_destroy(h);
+  return rc;
 }
 
 int muffin_destroy(muffin_handle* h) {

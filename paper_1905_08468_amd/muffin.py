@@ -39,6 +39,7 @@ class Config(C.Structure):
         ("eta_mu", C.c_double), ("eta_gamma", C.c_double),
         ("eps_fd", C.c_double), ("sigma_w", C.c_double),
         ("deriv_reset", C.c_int32), ("pi_iters", C.c_int32), ("pi_tol", C.c_double),
+        ("stop_rel", C.c_double), ("check_every", C.c_int32),
     ]
 
 
@@ -48,6 +49,7 @@ class Report(C.Structure):
         ("mu", C.c_double), ("gamma", C.c_double), ("tau", C.c_double),
         ("beta_H", C.c_double), ("psure", C.c_double), ("sugar_mu", C.c_double),
         ("sugar_gamma", C.c_double), ("res2", C.c_double),
+        ("last_rel_change", C.c_double), ("stopped", C.c_int32),
     ]
 
     def as_dict(self):
@@ -61,6 +63,8 @@ EXPORTS = [
     "muffin_strerror", "muffin_op_H", "muffin_op_HT", "muffin_op_HTH", "muffin_op_Ws",
     "muffin_op_WsT", "muffin_op_dct", "muffin_op_idct",
     "muffin_set_timing", "muffin_get_timing", "muffin_stage_name",
+    "muffin_set_initial", "muffin_state_bytes", "muffin_state_save", "muffin_state_load",
+    "muffin_solve",
 ]
 
 
@@ -88,6 +92,11 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "muffin_set_timing": ([vp, i32], C.c_int),
         "muffin_get_timing": ([vp, dp, C.POINTER(C.c_int64), i32], C.c_int),
         "muffin_stage_name": ([i32], C.c_char_p),
+        "muffin_set_initial": ([vp, vp], C.c_int),
+        "muffin_state_bytes": ([vp], C.c_size_t),
+        "muffin_state_save": ([vp, vp, C.c_size_t], C.c_int),
+        "muffin_state_load": ([vp, vp, C.c_size_t], C.c_int),
+        "muffin_solve": ([cfgp, vp, vp, dp, dp, vp, vp, i32, vp, C.POINTER(Report), vp], C.c_int),
     }
     for name in ["muffin_op_H", "muffin_op_HT", "muffin_op_HTH", "muffin_op_Ws",
                  "muffin_op_WsT", "muffin_op_dct", "muffin_op_idct"]:
@@ -181,6 +190,26 @@ class Muffin:
             raise MuffinError(rc, "muffin_run")
         return rep.as_dict() if report else None
 
+    def set_initial(self, x0):
+        self._check(x0, self.cube, "x0")
+        rc = _lib.muffin_set_initial(self.h, _ptr(x0))
+        if rc:
+            raise MuffinError(rc, "muffin_set_initial")
+
+    def state_save(self) -> np.ndarray:
+        nb = int(_lib.muffin_state_bytes(self.h))
+        buf = np.empty(nb, dtype=np.uint8)
+        rc = _lib.muffin_state_save(self.h, buf.ctypes.data_as(C.c_void_p), nb)
+        if rc:
+            raise MuffinError(rc, "muffin_state_save")
+        return buf
+
+    def state_load(self, buf: np.ndarray):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        rc = _lib.muffin_state_load(self.h, buf.ctypes.data_as(C.c_void_p), buf.size)
+        if rc:
+            raise MuffinError(rc, "muffin_state_load")
+
     def report(self):
         rep = Report()
         rc = _lib.muffin_get_report(self.h, C.byref(rep))
@@ -269,3 +298,21 @@ class Muffin:
             self.close()
         except Exception:
             pass
+
+
+def solve(cfg: Config, dirty, psf, iters: int, alpha=None, beta=None, delta=None, x0=None,
+          stream=None):
+    """One-call solve (muffin_solve): returns (sky tensor, report dict)."""
+    import torch
+    dt = torch.float64 if cfg.mode == F64 else torch.float32
+    out = torch.empty((cfg.L, cfg.n, cfg.n), dtype=dt, device=dirty.device)
+    a = _dptr(alpha)
+    b = _dptr(beta)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rep = Report()
+    rc = _lib.muffin_solve(C.byref(cfg), _ptr(dirty), _ptr(psf), a[1] if a else None,
+                           b[1] if b else None, _ptr(delta), _ptr(x0), int(iters), _ptr(out),
+                           C.byref(rep), C.c_void_p(s.cuda_stream))
+    if rc:
+        raise MuffinError(rc, "muffin_solve")
+    return out, rep.as_dict()
