@@ -46,7 +46,8 @@ enum {
   MUFFIN_E_NOMEM = -3,     /* device allocation failed; nothing allocated */
   MUFFIN_E_NONFINITE = -4, /* NaN or Inf in an input cube */
   MUFFIN_E_HIP = -5,       /* HIP runtime error */
-  MUFFIN_E_STATE = -6      /* call out of order (e.g. run before set_problem) */
+  MUFFIN_E_STATE = -6,     /* call out of order (e.g. run before set_problem) */
+  MUFFIN_E_BUSY = -7       /* serving queue full */
 };
 
 /* Arithmetic forms.  F64: everything in double.  F32: FFT, wavelet,
@@ -196,6 +197,67 @@ const char* muffin_stage_name(int32_t stage);
 
 int muffin_destroy(muffin_handle* h);
 const char* muffin_strerror(int code);
+
+/* ---- serving: continuous batching of independent solves ----
+ * A server owns a worker thread and a pool of handles on the device that is
+ * current at creation.  Submitted solves wait in a FIFO queue; the worker
+ * admits the head request as soon as a slot (max_active) and its workspace
+ * (muffin_workspace_bytes, within hbm_budget) are free, reusing an idle
+ * handle of the same configuration or creating one (idle handles of other
+ * configurations are released when memory is needed).  Admitted solves keep
+ * their state resident and iterate in chunks on streams of their own, so
+ * their kernels overlap on the device; a solve ends when cfg->stop_rel is
+ * met (checked every cfg->check_every iterations) or after max_iters.
+ * Results do not depend on what else runs: each solve executes exactly the
+ * kernels of a lone muffin_run.
+ *
+ * Inputs are device pointers (working type of cfg->mode) that the caller
+ * keeps valid until the request has been admitted (status RUNNING or later);
+ * alpha/beta (host, may be NULL) are copied at submission.  sky_out
+ * (device [L][n][n]) is written when the request completes.  Latency is
+ * measured from submission to completion on the host's steady clock. */
+typedef struct muffin_server muffin_server;
+
+typedef struct {
+  size_t hbm_budget;   /* bytes for the pooled handles; 0: 85% of the free memory */
+  int32_t max_active;  /* solves iterating at once, 1..64 */
+  int32_t max_queue;   /* waiting requests before submit returns E_BUSY */
+  int32_t chunk;       /* iterations per scheduling round of a solve without stop rule */
+} muffin_server_config;
+
+typedef struct {
+  int32_t queued, active, completed, failed, cancelled;
+  int32_t pooled_handles;
+  size_t bytes_in_use, bytes_budget;
+} muffin_server_stats;
+
+enum {
+  MUFFIN_REQ_QUEUED = 0,
+  MUFFIN_REQ_RUNNING = 1,
+  MUFFIN_REQ_DONE = 2,
+  MUFFIN_REQ_CANCELLED = 3  /* a failed request reports its (negative) error code */
+};
+
+/* Defaults: hbm_budget 0, max_active 8, max_queue 4096, chunk 10. */
+int muffin_server_default_config(muffin_server_config* sc);
+int muffin_server_create(muffin_server** s, const muffin_server_config* sc);
+/* Validates cfg (E_INVAL / E_SHAPE), refuses a solve whose workspace exceeds
+ * the budget (E_NOMEM) or a full queue (E_BUSY); *ticket identifies it. */
+int muffin_server_submit(muffin_server* s, const muffin_config* cfg, const void* dirty,
+                         const void* psf, const double* alpha, const double* beta,
+                         const void* delta, int32_t max_iters, void* sky_out, int64_t* ticket);
+/* Non-blocking status; report and latency are filled once the request is done. */
+int muffin_server_poll(muffin_server* s, int64_t ticket, int32_t* status, muffin_report* report,
+                       double* latency_ms);
+/* Blocks until the request leaves the queue/running states or timeout_ms
+ * (< 0: no limit) passes; then as muffin_server_poll. */
+int muffin_server_wait(muffin_server* s, int64_t ticket, double timeout_ms, int32_t* status,
+                       muffin_report* report, double* latency_ms);
+/* Cancels a queued request, or a running one at its next chunk boundary. */
+int muffin_server_cancel(muffin_server* s, int64_t ticket);
+int muffin_server_get_stats(muffin_server* s, muffin_server_stats* out);
+/* Cancels what is queued or running, joins the worker, frees the pool. */
+int muffin_server_destroy(muffin_server* s);
 
 /* ---- operator entry points (same kernels as the iteration) ----
  * in/out are device cubes of the handle's working type.

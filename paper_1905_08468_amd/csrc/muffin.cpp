@@ -171,6 +171,8 @@ struct ImplBase {
   virtual int weights(double* alpha, double* beta) = 0;
   virtual int op(int kind, const void* in, void* out) = 0;
   virtual int set_initial(const void* x0) = 0;
+  virtual int run_chunk(int iters, bool check) = 0;
+  virtual int chunk_poll(int* done, double* rel) = 0;
   virtual size_t state_bytes() = 0;
   virtual int state_save(void* buf, size_t bytes) = 0;
   virtual int state_load(const void* buf, size_t bytes) = 0;
@@ -219,6 +221,10 @@ struct Impl final : ImplBase {
   double* relsum = nullptr;
   double last_rel = -1.0;
   bool stopped = false;
+  // asynchronous chunks (serving): completion event, pinned copy of the sums
+  hipEvent_t chunk_ev = nullptr;
+  double* relhost = nullptr;
+  bool chunk_check = false;
   int max_hist = 0;
   bool have_problem = false;
   int k_done = 0;
@@ -239,6 +245,8 @@ struct Impl final : ImplBase {
     nsets = c.sure ? 6 : 1;
   }
   ~Impl() override {
+    if (chunk_ev) (void)hipEventDestroy(chunk_ev);
+    if (relhost) (void)hipHostFree(relhost);
     fft_free_plan(fft);
     dct_free_plan(dct);
     dev.release();
@@ -757,6 +765,60 @@ struct Impl final : ImplBase {
     return 0;
   }
 
+  // Enqueues `iters` iterations without waiting; with check (stop_rel > 0)
+  // the last one is followed by the stopping-rule sums, copied to pinned
+  // host memory.  chunk_poll reports completion and the relative change.
+  int run_chunk(int iters, bool check) override {
+    if (!have_problem) return MUFFIN_E_STATE;
+    if (iters < 1) return MUFFIN_E_INVAL;
+    // (checked iterations are the multiples of check_every, as in run())
+    check = check && cfg.stop_rel > 0 && (k_done + iters) % cfg.check_every == 0;
+    if (!chunk_ev) {
+      MUFFIN_HIP_CHECK(hipEventCreateWithFlags(&chunk_ev, hipEventDisableTiming));
+      MUFFIN_HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&relhost), 8 * sizeof(double),
+                                     hipHostMallocDefault));
+    }
+    for (int i = 0; i < iters; ++i) {
+      const bool last = i == iters - 1;
+      if (check && last) {
+        RC(copy_dev<T>(Usnap, U[0], LN * P, st));
+        RC(copy_dev<T>(Vsnap, V[0], LN, st));
+      }
+      RC(iterate());
+    }
+    if (check) {
+      const int nb = dot_blocks();
+      RC(diff_sq<T>(X[0], Xt[0], LN, partials, nb, relsum, st));
+      RC(diff_sq<T>(U[0], Usnap, LN * P, partials, nb, relsum + 2, st));
+      RC(diff_sq<T>(V[0], Vsnap, LN, partials, nb, relsum + 4, st));
+      MUFFIN_HIP_CHECK(hipMemcpyAsync(relhost, relsum, 6 * sizeof(double),
+                                      hipMemcpyDeviceToHost, st));
+    }
+    MUFFIN_HIP_CHECK(hipEventRecord(chunk_ev, st));
+    chunk_check = check;
+    return 0;
+  }
+
+  int chunk_poll(int* done, double* rel) override {
+    *done = 0;
+    if (!chunk_ev) return MUFFIN_E_STATE;
+    const hipError_t e = hipEventQuery(chunk_ev);
+    if (e == hipErrorNotReady) return 0;
+    MUFFIN_HIP_CHECK(e);
+    *done = 1;
+    if (chunk_check) {
+      const double* h = relhost;
+      auto ratio = [](double num, double den) {
+        if (den > 0) return num / den;
+        return num > 0 ? HUGE_VAL : 0.0;
+      };
+      last_rel = std::sqrt(std::max(ratio(h[0], h[1]), ratio(h[2] + h[4], h[3] + h[5])));
+      stopped = last_rel <= cfg.stop_rel;
+    }
+    *rel = last_rel;
+    return 0;
+  }
+
   int set_initial(const void* x0) override {
     if (!have_problem) return MUFFIN_E_STATE;
     if (!x0) return MUFFIN_E_INVAL;
@@ -974,6 +1036,16 @@ struct muffin_handle {
   std::unique_ptr<ImplBase> impl;
 };
 
+namespace muffin {
+int handle_run_chunk(muffin_handle* h, int iters, bool check) {
+  return h->impl->run_chunk(iters, check);
+}
+int handle_chunk_poll(muffin_handle* h, int* done, double* rel) {
+  return h->impl->chunk_poll(done, rel);
+}
+size_t handle_workspace_bytes(const muffin_config* c) { return workspace_bytes_of(c); }
+}  // namespace muffin
+
 extern "C" {
 
 int muffin_default_config(muffin_config* c, int32_t n, int32_t L) {
@@ -1152,6 +1224,7 @@ const char* muffin_strerror(int code) {
     case MUFFIN_E_NONFINITE: return "non-finite value in an input cube";
     case MUFFIN_E_HIP: return "HIP runtime error";
     case MUFFIN_E_STATE: return "call out of order";
+    case MUFFIN_E_BUSY: return "serving queue full";
     default: return "unknown error";
   }
 }

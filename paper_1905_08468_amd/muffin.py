@@ -20,7 +20,8 @@ F64, F32, F32_BF16DCT = 0, 1, 2
 TAU_OPNORM, TAU_PAPER_SUM = 0, 1
 
 ERRORS = {0: "ok", -1: "E_INVAL", -2: "E_SHAPE", -3: "E_NOMEM", -4: "E_NONFINITE",
-          -5: "E_HIP", -6: "E_STATE"}
+          -5: "E_HIP", -6: "E_STATE", -7: "E_BUSY"}
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED = 0, 1, 2, 3
 
 
 class MuffinError(RuntimeError):
@@ -56,6 +57,20 @@ class Report(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int32),
+                ("max_queue", C.c_int32), ("chunk", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("queued", C.c_int32), ("active", C.c_int32), ("completed", C.c_int32),
+                ("failed", C.c_int32), ("cancelled", C.c_int32), ("pooled_handles", C.c_int32),
+                ("bytes_in_use", C.c_size_t), ("bytes_budget", C.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 EXPORTS = [
     "muffin_default_config", "muffin_workspace_bytes", "muffin_create", "muffin_set_problem",
     "muffin_run", "muffin_get_sky", "muffin_get_state", "muffin_set_state",
@@ -65,6 +80,9 @@ EXPORTS = [
     "muffin_set_timing", "muffin_get_timing", "muffin_stage_name",
     "muffin_set_initial", "muffin_state_bytes", "muffin_state_save", "muffin_state_load",
     "muffin_solve",
+    "muffin_server_default_config", "muffin_server_create", "muffin_server_submit",
+    "muffin_server_poll", "muffin_server_wait", "muffin_server_cancel",
+    "muffin_server_get_stats", "muffin_server_destroy",
 ]
 
 
@@ -97,6 +115,16 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "muffin_state_save": ([vp, vp, C.c_size_t], C.c_int),
         "muffin_state_load": ([vp, vp, C.c_size_t], C.c_int),
         "muffin_solve": ([cfgp, vp, vp, dp, dp, vp, vp, i32, vp, C.POINTER(Report), vp], C.c_int),
+        "muffin_server_default_config": ([C.POINTER(ServerConfig)], C.c_int),
+        "muffin_server_create": ([C.POINTER(vp), C.POINTER(ServerConfig)], C.c_int),
+        "muffin_server_submit": ([vp, cfgp, vp, vp, dp, dp, vp, i32, vp,
+                                  C.POINTER(C.c_int64)], C.c_int),
+        "muffin_server_poll": ([vp, C.c_int64, C.POINTER(i32), C.POINTER(Report), dp], C.c_int),
+        "muffin_server_wait": ([vp, C.c_int64, C.c_double, C.POINTER(i32), C.POINTER(Report),
+                                dp], C.c_int),
+        "muffin_server_cancel": ([vp, C.c_int64], C.c_int),
+        "muffin_server_get_stats": ([vp, C.POINTER(ServerStats)], C.c_int),
+        "muffin_server_destroy": ([vp], C.c_int),
     }
     for name in ["muffin_op_H", "muffin_op_HT", "muffin_op_HTH", "muffin_op_Ws",
                  "muffin_op_WsT", "muffin_op_dct", "muffin_op_idct"]:
@@ -316,3 +344,91 @@ def solve(cfg: Config, dirty, psf, iters: int, alpha=None, beta=None, delta=None
     if rc:
         raise MuffinError(rc, "muffin_solve")
     return out, rep.as_dict()
+
+
+class Server:
+    """Continuous-batching request loop (muffin_server_*) on the current device.
+
+    submit() keeps references to the request's tensors until it has ended,
+    so the caller may drop its own."""
+
+    def __init__(self, hbm_budget: int = 0, max_active: int = 8, max_queue: int = 4096,
+                 chunk: int = 10):
+        sc = ServerConfig()
+        _lib.muffin_server_default_config(C.byref(sc))
+        sc.hbm_budget, sc.max_active, sc.max_queue, sc.chunk = hbm_budget, max_active, \
+            max_queue, chunk
+        h = C.c_void_p()
+        rc = _lib.muffin_server_create(C.byref(h), C.byref(sc))
+        if rc:
+            raise MuffinError(rc, "muffin_server_create")
+        self.h = h
+        self._keep = {}
+
+    def submit(self, cfg: Config, dirty, psf, max_iters: int, alpha=None, beta=None,
+               delta=None, out=None):
+        import torch
+        dt = torch.float64 if cfg.mode == F64 else torch.float32
+        if out is None:
+            out = torch.empty((cfg.L, cfg.n, cfg.n), dtype=dt, device=dirty.device)
+        for t, shape in ((dirty, (cfg.L, cfg.n, cfg.n)), (psf, (cfg.L, 2 * cfg.n, 2 * cfg.n)),
+                         (out, (cfg.L, cfg.n, cfg.n))):
+            if tuple(t.shape) != shape or t.dtype != dt or not t.is_contiguous():
+                raise ValueError(f"expected contiguous {dt} {shape}, got {t.dtype} {tuple(t.shape)}")
+        a = _dptr(alpha)
+        b = _dptr(beta)
+        tk = C.c_int64()
+        # the C side reads the inputs when it admits the request
+        torch.cuda.current_stream().synchronize()
+        rc = _lib.muffin_server_submit(self.h, C.byref(cfg), _ptr(dirty), _ptr(psf),
+                                       a[1] if a else None, b[1] if b else None, _ptr(delta),
+                                       int(max_iters), _ptr(out), C.byref(tk))
+        if rc:
+            raise MuffinError(rc, "muffin_server_submit")
+        self._keep[tk.value] = (dirty, psf, delta, out)
+        return tk.value
+
+    def _result(self, ticket, st, rep, lat):
+        out = self._keep[ticket][3]
+        if st.value not in (REQ_QUEUED, REQ_RUNNING):
+            self._keep[ticket] = (None, None, None, out)
+        return {"status": st.value, "report": rep.as_dict(), "latency_ms": lat.value, "sky": out}
+
+    def poll(self, ticket: int):
+        st, rep, lat = C.c_int32(), Report(), C.c_double()
+        rc = _lib.muffin_server_poll(self.h, ticket, C.byref(st), C.byref(rep), C.byref(lat))
+        if rc:
+            raise MuffinError(rc, "muffin_server_poll")
+        return self._result(ticket, st, rep, lat)
+
+    def wait(self, ticket: int, timeout_ms: float = -1.0):
+        st, rep, lat = C.c_int32(), Report(), C.c_double()
+        rc = _lib.muffin_server_wait(self.h, ticket, float(timeout_ms), C.byref(st),
+                                     C.byref(rep), C.byref(lat))
+        if rc:
+            raise MuffinError(rc, "muffin_server_wait")
+        return self._result(ticket, st, rep, lat)
+
+    def cancel(self, ticket: int):
+        rc = _lib.muffin_server_cancel(self.h, ticket)
+        if rc:
+            raise MuffinError(rc, "muffin_server_cancel")
+
+    def stats(self):
+        s = ServerStats()
+        rc = _lib.muffin_server_get_stats(self.h, C.byref(s))
+        if rc:
+            raise MuffinError(rc, "muffin_server_get_stats")
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.muffin_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
