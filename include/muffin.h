@@ -259,6 +259,27 @@ int muffin_server_get_stats(muffin_server* s, muffin_server_stats* out);
 /* Cancels what is queued or running, joins the worker, frees the pool. */
 int muffin_server_destroy(muffin_server* s);
 
+/* ---- batching: many independent cubes as one captured graph ----
+ * `count` handles (any sizes, forms and configurations), each with its
+ * problem set and a non-null stream of its own, iterate together: one chunk
+ * of `chunk` iterations of every handle is captured into one HIP graph with
+ * a fork/join over the handles' streams (the cubes' kernels run
+ * concurrently) and each later chunk is one graph launch on `stream` (the
+ * root, distinct from the handles' streams).  chunk must be even and a
+ * multiple of every adaptive handle's Delta (0: the least such value); each
+ * handle must stand at a multiple of chunk iterations (e.g. just after
+ * muffin_set_problem) and have timing off.  Results are those of the same
+ * iterations run with muffin_run on each handle.
+ * muffin_batch_run(b, chunks) enqueues chunks x chunk iterations of every
+ * handle (the first call runs its first chunk directly and records the
+ * graph); synchronise `stream` to wait.  Stopping rules are not evaluated
+ * inside a batch. */
+typedef struct muffin_batch muffin_batch;
+int muffin_batch_create(muffin_batch** b, muffin_handle* const* handles, int32_t count,
+                        int32_t chunk, void* stream);
+int muffin_batch_run(muffin_batch* b, int32_t chunks);
+int muffin_batch_destroy(muffin_batch* b);
+
 /* ---- operator entry points (same kernels as the iteration) ----
  * in/out are device cubes of the handle's working type.
  *   op_H:   out = H_l in_l     (eq. `model`)

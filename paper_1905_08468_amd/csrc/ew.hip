@@ -141,8 +141,15 @@ __device__ void tau_from_rule(DevParams* dp) {
   dp->tau = dp->rho / (0.5 * dp->beta_H + dp->sigma * k);
 }
 
-__global__ void theta_kernel(DevParams* dp, double* hist_row, int k, long long LN, int apply) {
+// The history row and its iteration number follow from the device's update
+// counter (updates happen after every `period` iterations), so the kernel
+// can be replayed from a captured graph.
+__global__ void theta_kernel(DevParams* dp, double* hist, int max_hist, int period,
+                             long long LN, int apply) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int q = dp->n_updates;  // this update's index
+  double* hist_row = (hist && q < max_hist) ? hist + (size_t)q * kHistCols : nullptr;
+  const long long k = (long long)(q + 1) * period;
   const double c = 2.0 * dp->sigma_w * dp->sigma_w / dp->eps_fd;
   const double s_mu = 2.0 * dp->sums[SLOT_GX_MU] + c * dp->sums[SLOT_FD_MU];
   const double s_ga = 2.0 * dp->sums[SLOT_GX_GA] + c * dp->sums[SLOT_FD_GA];
@@ -168,9 +175,9 @@ __global__ void theta_kernel(DevParams* dp, double* hist_row, int k, long long L
   }
 }
 
-int theta_update(DevParams* dp, double* hist_row, int k, long long LN, int apply,
+int theta_update(DevParams* dp, double* hist, int max_hist, int period, long long LN, int apply,
                  hipStream_t s) {
-  theta_kernel<<<1, 64, 0, s>>>(dp, hist_row, k, LN, apply);
+  theta_kernel<<<1, 64, 0, s>>>(dp, hist, max_hist, period, LN, apply);
   MUFFIN_HIP_CHECK(hipGetLastError());
   return 0;
 }

@@ -234,8 +234,8 @@ int weights_from(const T* x0, int L, int N, double eps, double* alpha, double* b
                  double* partials, hipStream_t s);
 
 // K-THETA: SUGAR from the reduction slots, theta update, tau recompute,
-// history row.
-int theta_update(DevParams* dp, double* hist_row, int k, long long LN, int apply,
+// history row (hist[n_updates], iteration (n_updates + 1) * period).
+int theta_update(DevParams* dp, double* hist, int max_hist, int period, long long LN, int apply,
                  hipStream_t s);
 int tau_refresh(DevParams* dp, hipStream_t s);
 

@@ -24,6 +24,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <numeric>
 #include <vector>
 
 #include "../../include/muffin.h"
@@ -172,6 +173,10 @@ struct ImplBase {
   virtual int op(int kind, const void* in, void* out) = 0;
   virtual int set_initial(const void* x0) = 0;
   virtual int run_chunk(int iters, bool check) = 0;
+  virtual int iterate_n(int iters) = 0;  // enqueue only (no checks, no sync)
+  virtual void advance(int iters) = 0;   // host counters after graph replays
+  virtual int iters_done() const = 0;
+  virtual bool ready() const = 0;
   virtual int chunk_poll(int* done, double* rel) = 0;
   virtual size_t state_bytes() = 0;
   virtual int state_save(void* buf, size_t bytes) = 0;
@@ -708,8 +713,8 @@ struct Impl final : ImplBase {
     RC(reduce_to_slot(partials, nb, dp, SLOT_FD_GA, st));
     RC(dot_partials<T>(X[1], X[0], HTd, LN, partials, nb, st));
     RC(reduce_to_slot(partials, nb, dp, SLOT_FD_X, st));
-    double* row = q < max_hist ? hist + (size_t)q * kHistCols : nullptr;
-    RC(theta_update(dp, row, k_done, (long long)LN, 1, st));
+    (void)q;
+    RC(theta_update(dp, hist, max_hist, cfg.delta_period, (long long)LN, 1, st));
     if (cfg.deriv_reset) {
       for (int s = 2; s < 6; ++s) {
         RC(fill_zero(X[s], LN, st));
@@ -798,6 +803,18 @@ struct Impl final : ImplBase {
     chunk_check = check;
     return 0;
   }
+
+  int iterate_n(int iters) override {
+    if (!have_problem) return MUFFIN_E_STATE;
+    for (int i = 0; i < iters; ++i) RC(iterate());
+    return 0;
+  }
+  void advance(int iters) override {
+    k_done += iters;
+    if (cfg.sure) n_upd += iters / cfg.delta_period;
+  }
+  int iters_done() const override { return k_done; }
+  bool ready() const override { return have_problem && !tm.on; }
 
   int chunk_poll(int* done, double* rel) override {
     *done = 0;
@@ -1045,6 +1062,111 @@ int handle_chunk_poll(muffin_handle* h, int* done, double* rel) {
 }
 size_t handle_workspace_bytes(const muffin_config* c) { return workspace_bytes_of(c); }
 }  // namespace muffin
+
+// Many independent cubes as one graph: one chunk of iterations of every
+// handle, captured with a fork/join over the handles' streams (the cubes'
+// kernels run concurrently) and replayed per chunk.
+struct muffin_batch {
+  std::vector<muffin_handle*> hs;
+  int chunk = 0;
+  hipStream_t root = nullptr;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> joins;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool captured = false;
+
+  int capture() {
+    // one eager chunk first: every kernel attribute is set outside the
+    // capture, and the graph starts from the same pointer parity
+    for (auto* h : hs) RC(h->impl->iterate_n(chunk));
+    for (auto* h : hs) MUFFIN_HIP_CHECK(hipStreamSynchronize(h->stream));
+    MUFFIN_HIP_CHECK(hipStreamBeginCapture(root, hipStreamCaptureModeRelaxed));
+    int rc = 0;
+    if (hipEventRecord(fork, root) != hipSuccess) rc = MUFFIN_E_HIP;
+    for (size_t i = 0; !rc && i < hs.size(); ++i)
+      if (hipStreamWaitEvent(hs[i]->stream, fork, 0) != hipSuccess) rc = MUFFIN_E_HIP;
+    for (size_t i = 0; !rc && i < hs.size(); ++i) rc = hs[i]->impl->iterate_n(chunk);
+    for (size_t i = 0; !rc && i < hs.size(); ++i) {
+      if (hipEventRecord(joins[i], hs[i]->stream) != hipSuccess ||
+          hipStreamWaitEvent(root, joins[i], 0) != hipSuccess)
+        rc = MUFFIN_E_HIP;
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(root, &g);
+    if (rc || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc ? rc : MUFFIN_E_HIP;
+    }
+    graph = g;
+    MUFFIN_HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    captured = true;
+    return 0;
+  }
+};
+
+extern "C" {
+
+int muffin_batch_create(muffin_batch** b, muffin_handle* const* handles, int32_t count,
+                        int32_t chunk, void* stream) {
+  if (!b || !handles || count < 1 || !stream) return MUFFIN_E_INVAL;
+  *b = nullptr;
+  // the chunk: even (pointer swaps return to the captured state) and a
+  // multiple of every adaptive handle's Delta (theta updates at the same
+  // iterations as an uninterrupted run)
+  long long need = 2;
+  for (int i = 0; i < count; ++i) {
+    muffin_handle* h = handles[i];
+    if (!h || !h->stream || h->stream == static_cast<hipStream_t>(stream)) return MUFFIN_E_INVAL;
+    if (!h->impl->ready()) return MUFFIN_E_STATE;
+    if (h->cfg.sure) need = std::lcm(need, (long long)h->cfg.delta_period);
+  }
+  if (chunk <= 0) chunk = (int32_t)need;
+  if (chunk % need != 0) return MUFFIN_E_INVAL;
+  for (int i = 0; i < count; ++i)
+    if (handles[i]->impl->iters_done() % chunk != 0) return MUFFIN_E_STATE;
+  std::unique_ptr<muffin_batch> bb(new (std::nothrow) muffin_batch());
+  if (!bb) return MUFFIN_E_NOMEM;
+  bb->hs.assign(handles, handles + count);
+  bb->chunk = chunk;
+  bb->root = static_cast<hipStream_t>(stream);
+  if (hipEventCreateWithFlags(&bb->fork, hipEventDisableTiming) != hipSuccess) return MUFFIN_E_HIP;
+  bb->joins.resize(count, nullptr);
+  for (auto& e : bb->joins)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return MUFFIN_E_HIP;
+  *b = bb.release();
+  return MUFFIN_OK;
+}
+
+int muffin_batch_run(muffin_batch* b, int32_t chunks) {
+  if (!b || chunks < 0) return MUFFIN_E_INVAL;
+  if (chunks == 0) return MUFFIN_OK;
+  int done = 0;
+  if (!b->captured) {
+    RC(b->capture());  // one chunk run eagerly, the next only recorded
+    for (auto* h : b->hs) h->impl->advance(-b->chunk);  // (recording advanced them)
+    done = 1;
+  }
+  for (; done < chunks; ++done) {
+    MUFFIN_HIP_CHECK(hipGraphLaunch(b->exec, b->root));
+    for (auto* h : b->hs) h->impl->advance(b->chunk);
+  }
+  return MUFFIN_OK;
+}
+
+int muffin_batch_destroy(muffin_batch* b) {
+  if (!b) return MUFFIN_E_INVAL;
+  if (b->root) (void)hipStreamSynchronize(b->root);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (auto e : b->joins)
+    if (e) (void)hipEventDestroy(e);
+  delete b;
+  return MUFFIN_OK;
+}
+
+}  // extern "C"
 
 extern "C" {
 

@@ -83,6 +83,7 @@ EXPORTS = [
     "muffin_server_default_config", "muffin_server_create", "muffin_server_submit",
     "muffin_server_poll", "muffin_server_wait", "muffin_server_cancel",
     "muffin_server_get_stats", "muffin_server_destroy",
+    "muffin_batch_create", "muffin_batch_run", "muffin_batch_destroy",
 ]
 
 
@@ -125,6 +126,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "muffin_server_cancel": ([vp, C.c_int64], C.c_int),
         "muffin_server_get_stats": ([vp, C.POINTER(ServerStats)], C.c_int),
         "muffin_server_destroy": ([vp], C.c_int),
+        "muffin_batch_create": ([C.POINTER(vp), C.POINTER(vp), i32, i32, vp], C.c_int),
+        "muffin_batch_run": ([vp, i32], C.c_int),
+        "muffin_batch_destroy": ([vp], C.c_int),
     }
     for name in ["muffin_op_H", "muffin_op_HT", "muffin_op_HTH", "muffin_op_Ws",
                  "muffin_op_WsT", "muffin_op_dct", "muffin_op_idct"]:
@@ -245,11 +249,18 @@ class Muffin:
             raise MuffinError(rc, "muffin_get_report")
         return rep.as_dict()
 
+    def _settle(self):
+        # results were written on the handle's stream: when that is not the
+        # caller's current stream, wait for it before torch touches them
+        if self.stream != self.torch.cuda.current_stream():
+            self.stream.synchronize()
+
     def sky(self):
         out = self.torch.empty(self.cube, dtype=self.dtype, device=self.device)
         rc = _lib.muffin_get_sky(self.h, _ptr(out))
         if rc:
             raise MuffinError(rc, "muffin_get_sky")
+        self._settle()
         return out
 
     def _state_shape(self, which):
@@ -261,6 +272,7 @@ class Muffin:
         rc = _lib.muffin_get_state(self.h, which, set_, _ptr(out))
         if rc:
             raise MuffinError(rc, "muffin_get_state")
+        self._settle()
         return out
 
     def set_state(self, which: int, set_: int, t):
@@ -300,6 +312,7 @@ class Muffin:
         rc = fn(self.h, _ptr(x), _ptr(out))
         if rc:
             raise MuffinError(rc, f"muffin_op_{name}")
+        self._settle()
         return out
 
     def set_timing(self, on: bool = True):
@@ -426,6 +439,43 @@ class Server:
             _lib.muffin_server_destroy(self.h)
             self.h = None
             self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Handles iterated together as one captured graph per chunk
+    (muffin_batch_*).  Each handle needs a stream of its own; `stream` is the
+    root the graph is launched on."""
+
+    def __init__(self, handles, chunk: int = 0, stream=None):
+        import torch
+        self.handles = list(handles)
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        arr = (C.c_void_p * len(self.handles))(*[h.h for h in self.handles])
+        b = C.c_void_p()
+        rc = _lib.muffin_batch_create(C.byref(b), arr, len(self.handles), int(chunk),
+                                      C.c_void_p(self.stream.cuda_stream))
+        if rc:
+            raise MuffinError(rc, "muffin_batch_create")
+        self.h = b
+
+    def run(self, chunks: int):
+        rc = _lib.muffin_batch_run(self.h, int(chunks))
+        if rc:
+            raise MuffinError(rc, "muffin_batch_run")
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.muffin_batch_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:
