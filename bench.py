@@ -93,6 +93,12 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 1 GiB device copy (traffic-counter calibration)")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-cubes", type=int, default=48)
+    ap.add_argument("--batch-chunks", type=int, default=3)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
     return ap.parse_args()
 
 
@@ -118,6 +124,121 @@ def cpu_baseline(prob, n_bands_sample=1, Delta=10):
                       "numpy FFT and wavelet loops single-threaded",
             "cpu": platform.processor() or platform.machine(),
             "host_threads": os.cpu_count()}
+
+
+def _class_inputs(synth, torch, n, L, seed, dtype):
+    import numpy as np
+    p = synth.make_problem(n, L, seed=seed, device="cuda:0", **synth.scaled_counts(n))
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", dtype)
+    return p, d(p.dirty), d(p.psf), d(p.delta)
+
+
+def batch_form(mm, torch, synth, n_cubes, chunks, seed=7):
+    """Batching form: independent cubes with sizes drawn (seeded) from
+    {128, 256, 512}^2 px x {16, 32, 64, 128} bands, FP32, ADA-PT (Delta = 10),
+    iterated together as one captured graph per chunk of 10 iterations; the
+    same cubes are then run one after the other for comparison."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    sizes = [(int(rng.choice([128, 256, 512])), int(rng.choice([16, 32, 64, 128])))
+             for _ in range(n_cubes)]
+    inputs = {}
+    for n, L in sorted(set(sizes)):
+        inputs[(n, L)] = _class_inputs(synth, torch, n, L, 1000 + n + L, torch.float32)
+    torch.cuda.synchronize()
+    hs = []
+    t0 = time.perf_counter()
+    for n, L in sizes:
+        p, d, ps, dl = inputs[(n, L)]
+        cfg = mm.default_config(n, L, mode=mm.F32, sure=1, delta_period=10,
+                                eps_fd=0.01 * p.sigma_w, sigma_w=p.sigma_w, eta_mu=1e-6,
+                                eta_gamma=1e-6, pi_iters=30, pi_tol=1e-4)
+        h = mm.Muffin(cfg, stream=torch.cuda.Stream())
+        h.set_problem(d, ps, None, None, dl)
+        hs.append(h)
+    setup_s = time.perf_counter() - t0
+    vox = sum(n * n * L for n, L in sizes)
+    b = mm.Batch(hs, chunk=10)
+    b.run(1)                                   # eager chunk + graph capture
+    b.synchronize()
+    t0 = time.perf_counter()
+    b.run(chunks)
+    b.synchronize()
+    tb = time.perf_counter() - t0
+    iters = 10 * chunks
+    t0 = time.perf_counter()
+    for h in hs:
+        h.run(10, report=False)
+        h.stream.synchronize()
+    ts = (time.perf_counter() - t0) * chunks   # one chunk each, scaled
+    b.close()
+    for h in hs:
+        h.close()
+    del inputs
+    torch.cuda.empty_cache()
+    return {"form": "ADA-PT, FP32, independent cubes as one captured graph per 10 iterations",
+            "cubes": n_cubes, "sizes": "n in {128,256,512}, L in {16,32,64,128} (seeded draw)",
+            "voxels": vox, "iterations_timed": iters,
+            "cube_iters_per_s": round(n_cubes * iters / tb, 2),
+            "voxel_updates_per_s": round(vox * iters / tb, 1),
+            "ms_per_chunk": round(1e3 * tb / chunks, 2),
+            "one_after_another_cube_iters_per_s": round(n_cubes * iters / ts, 2),
+            "speedup_vs_one_after_another": round(ts / tb, 3), "setup_s": round(setup_s, 2)}
+
+
+def serve_form(mm, torch, synth, n_req, rate, seed=11):
+    """Serving form: Poisson arrivals (rate req/s) of plain deconvolution
+    solves, sizes uniform over {64,...,512}^2 px x {8,...,64} bands, FP32 with
+    the bf16 DCT, each to a relative change of 1e-4 (at most 2000
+    iterations), through the continuous-batching server (8 slots)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    ns, Ls = [64, 128, 256, 512], [8, 16, 32, 64]
+    classes = [(n, L) for n in ns for L in Ls]
+    inputs = {c: _class_inputs(synth, torch, c[0], c[1], 2000 + c[0] + c[1], torch.float32)
+              for c in classes}
+    torch.cuda.synchronize()
+    cfgs = {c: mm.default_config(c[0], c[1], mode=mm.F32_BF16DCT, stop_rel=1e-4,
+                                 check_every=10, pi_iters=30, pi_tol=1e-4) for c in classes}
+    srv = mm.Server(max_active=8)
+    # warm-up: one short solve per size class (handles pooled, kernels loaded)
+    warm = [srv.submit(cfgs[c], inputs[c][1], inputs[c][2], 10) for c in classes]
+    for t in warm:
+        srv.wait(t)
+    picks = [classes[i] for i in rng.integers(0, len(classes), size=n_req)]
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    tickets = []
+    t0 = time.perf_counter()
+    for c, ta in zip(picks, arrivals):
+        dt = t0 + ta - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append((c, srv.submit(cfgs[c], inputs[c][1], inputs[c][2], 2000)))
+    lat, its, vox_it, stopped = [], [], 0.0, 0
+    for c, t in tickets:
+        r = srv.wait(t)
+        if r["status"] != mm.REQ_DONE:
+            raise RuntimeError(f"request {t} ended with status {r['status']}")
+        lat.append(r["latency_ms"])
+        k = r["report"]["iters_done"]
+        its.append(k)
+        stopped += r["report"]["stopped"]
+        vox_it += c[0] * c[0] * c[1] * k
+    span = time.perf_counter() - t0
+    srv.close()
+    del inputs
+    torch.cuda.empty_cache()
+    lat = np.array(lat)
+    return {"form": "plain MUFFIN, FP32 + bf16 DCT, to relative change 1e-4 or 2000 iterations",
+            "requests": n_req, "rate_req_per_s": rate, "slots": 8,
+            "sizes": "n in {64,128,256,512}, L in {8,16,32,64}, uniform",
+            "p50_ms": round(float(np.percentile(lat, 50)), 2),
+            "p99_ms": round(float(np.percentile(lat, 99)), 2),
+            "mean_ms": round(float(lat.mean()), 2),
+            "throughput_req_per_s": round(n_req / span, 3),
+            "voxel_updates_per_s": round(vox_it / span, 1),
+            "iterations_mean": round(float(np.mean(its)), 1), "stopped_by_rule": stopped,
+            "span_s": round(span, 2)}
 
 
 def run_form(mm, torch, prob, mode, sure, steps, warmup, Delta=10):
@@ -233,6 +354,23 @@ def main():
         torch.cuda.synchronize()
         del src
         log("[bench] calibration: 3 x (1 GiB f32 read -> 512 MiB f16 written)")
+    torch.cuda.empty_cache()
+    batch = None
+    if not args.no_batch:
+        try:
+            batch = batch_form(mm, torch, synth, args.batch_cubes, args.batch_chunks)
+            log(f"[bench] batch: {batch['cube_iters_per_s']} cube-it/s, "
+                f"x{batch['speedup_vs_one_after_another']} vs one after another")
+        except Exception as e:  # report, do not hide
+            batch = {"error": str(e)}
+    serve = None
+    if not args.no_serve:
+        try:
+            serve = serve_form(mm, torch, synth, args.serve_requests, args.serve_rate)
+            log(f"[bench] serve: p50 {serve['p50_ms']} ms, p99 {serve['p99_ms']} ms, "
+                f"{serve['throughput_req_per_s']} req/s")
+        except Exception as e:  # report, do not hide
+            serve = {"error": str(e)}
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(prob)
@@ -263,6 +401,8 @@ def main():
         "roofline": roofline,
         "stages_ms_per_step": stages,
         "fp64_plain": fp64,
+        "batch": batch,
+        "serve": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -261,11 +261,11 @@ int muffin_server_destroy(muffin_server* s);
 
 /* ---- batching: many independent cubes as one captured graph ----
  * `count` handles (any sizes, forms and configurations), each with its
- * problem set and a non-null stream of its own, iterate together: one chunk
- * of `chunk` iterations of every handle is captured into one HIP graph with
- * a fork/join over the handles' streams (the cubes' kernels run
- * concurrently) and each later chunk is one graph launch on `stream` (the
- * root, distinct from the handles' streams).  chunk must be even and a
+ * problem set and a non-null stream, iterate together: one chunk of `chunk`
+ * iterations of every handle is captured into one HIP graph with a
+ * fork/join over the handles' streams (handles on different streams run
+ * concurrently, handles sharing a stream one after the other) and each
+ * later chunk is one graph launch on `stream` (the root).  chunk must be even and a
  * multiple of every adaptive handle's Delta (0: the least such value); each
  * handle must stand at a multiple of chunk iterations (e.g. just after
  * muffin_set_problem) and have timing off.  Results are those of the same

@@ -1117,7 +1117,9 @@ int muffin_batch_create(muffin_batch** b, muffin_handle* const* handles, int32_t
   long long need = 2;
   for (int i = 0; i < count; ++i) {
     muffin_handle* h = handles[i];
-    if (!h || !h->stream || h->stream == static_cast<hipStream_t>(stream)) return MUFFIN_E_INVAL;
+    // (handles may share streams, also with the root: their work then
+    // serialises on that stream inside the graph)
+    if (!h || !h->stream) return MUFFIN_E_INVAL;
     if (!h->impl->ready()) return MUFFIN_E_STATE;
     if (h->cfg.sure) need = std::lcm(need, (long long)h->cfg.delta_period);
   }
