@@ -25,6 +25,7 @@ if ROOT not in sys.path:
 
 METRIC = "primal-dual iters/s at 1024²×256 bands (FP32 vs FP64); served p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK, MFMA_F32_PEAK, MFMA_F64_PEAK = 2500.0, 157.3, 78.6   # TFLOP/s, dense
 
 # Algorithmic traffic of the single-launch stages of one ADA-PT iteration,
 # per voxel (all state sets of the launch together): (working-precision
@@ -93,6 +94,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 1 GiB device copy (traffic-counter calibration)")
+    ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-cubes", type=int, default=48)
     ap.add_argument("--batch-chunks", type=int, default=3)
@@ -241,6 +243,59 @@ def serve_form(mm, torch, synth, n_req, rate, seed=11):
             "span_s": round(span, 2)}
 
 
+def _errors(torch, x, ref):
+    d = (x.double() - ref).abs()
+    return {"max_abs": float(d.max()), "rel_l2": float(torch.linalg.vector_norm(d) /
+                                                     torch.linalg.vector_norm(ref))}
+
+
+def accuracy_form(mm, torch, synth, prob_c2, iters_plain=20, iters_adapt=40):
+    """Errors of the reduced-precision forms against the FP64 GPU path (the
+    path the parity tests pin to the FP64 oracle) from the same inputs and a
+    fixed step tau: plain MUFFIN at 1024^2 x 256 after `iters_plain`
+    iterations, ADA-PT at 256^2 x 64 after `iters_adapt` iterations (theta
+    updated every 10)."""
+    forms = [("f32", mm.F32), ("bf16", mm.F32_BF16DCT)]
+
+    def solve(prob, mode, sure, iters, tau):
+        dt = torch.float64 if mode == mm.F64 else torch.float32
+        cfg = mm.default_config(prob.n, prob.L, mode=mode, sure=1 if sure else 0,
+                                delta_period=10, eps_fd=0.01 * prob.sigma_w,
+                                sigma_w=prob.sigma_w, eta_mu=1e-6, eta_gamma=1e-6,
+                                tau=tau, pi_iters=50, pi_tol=1e-6)
+        h = mm.Muffin(cfg)
+        dev = lambda a: torch.from_numpy(a).to("cuda:0", dt)
+        h.set_problem(dev(prob.dirty), dev(prob.psf), None, None,
+                      dev(prob.delta) if sure else None)
+        rep = h.run(iters)
+        x = h.sky().double()
+        h.close()
+        torch.cuda.empty_cache()
+        return x, rep
+
+    out = {}
+    _, rep0 = solve(prob_c2, mm.F64, False, 0, 0.0)   # tau of the FP64 set-up
+    tau = rep0["tau"]
+    x64, _ = solve(prob_c2, mm.F64, False, iters_plain, tau)
+    out[f"plain_1024x256_{iters_plain}_iters"] = {
+        k: _errors(torch, solve(prob_c2, m, False, iters_plain, tau)[0], x64) for k, m in forms}
+    del x64
+    torch.cuda.empty_cache()
+    p1 = synth.make_config("c1", seed=0, device="cuda:0")
+    _, r0 = solve(p1, mm.F64, True, 0, 0.0)
+    x64, r64 = solve(p1, mm.F64, True, iters_adapt, r0["tau"])
+    ad = {}
+    for k, m in forms:
+        x, r = solve(p1, m, True, iters_adapt, r0["tau"])
+        e = _errors(torch, x, x64)
+        e["mu_rel"] = abs(r["mu"] - r64["mu"]) / abs(r64["mu"])
+        e["gamma_rel"] = abs(r["gamma"] - r64["gamma"]) / abs(r64["gamma"])
+        ad[k] = e
+    out[f"adapt_256x64_{iters_adapt}_iters"] = ad
+    out["reference"] = "FP64 GPU path, same inputs, same fixed tau"
+    return out
+
+
 def run_form(mm, torch, prob, mode, sure, steps, warmup, Delta=10):
     n, L = prob.n, prob.L
     dt = torch.float64 if mode == mm.F64 else torch.float32
@@ -316,6 +371,17 @@ def main():
             avg = ms / calls
             entry["algorithmic_GB"] = round(nbytes / 1e9, 2)
             entry["GBps"] = round(nbytes / (avg * 1e-3) / 1e9, 1)
+        if k in ("dct_primal", "dct_deriv"):
+            # two (L x L)(L x N) products per set; the bf16 form issues three
+            # MFMA products (hi hi, lo hi, hi lo) per product
+            sets = 2 if k == "dct_primal" else 4
+            lp = -(-L // 32) * 32
+            mult, peak = (3, MFMA_BF16_PEAK) if mode == mm.F32_BF16DCT else \
+                ((1, MFMA_F64_PEAK) if mode == mm.F64 else (1, MFMA_F32_PEAK))
+            fl = sets * 2 * 2.0 * lp * lp * n * n * mult
+            tf = fl / (ms / calls * 1e-3) / 1e12
+            entry["mfma_TFLOPs"] = round(tf, 1)
+            entry["mfma_util"] = round(tf / peak, 4)
         stages[k] = entry
     dom = max((k for k in stages if k in STAGE_TRAFFIC), key=lambda k: tm[k][0])
     vals, mbytes = STAGE_TRAFFIC[dom]
@@ -355,6 +421,13 @@ def main():
         del src
         log("[bench] calibration: 3 x (1 GiB f32 read -> 512 MiB f16 written)")
     torch.cuda.empty_cache()
+    accuracy = None
+    if not args.no_accuracy and args.workload == "c2":
+        try:
+            accuracy = accuracy_form(mm, torch, synth, prob)
+            log(f"[bench] accuracy: {json.dumps(accuracy)}")
+        except Exception as e:  # report, do not hide
+            accuracy = {"error": str(e)}
     batch = None
     if not args.no_batch:
         try:
@@ -401,6 +474,7 @@ def main():
         "roofline": roofline,
         "stages_ms_per_step": stages,
         "fp64_plain": fp64,
+        "accuracy": accuracy,
         "batch": batch,
         "serve": serve,
         "cpu_baseline": cpu,
