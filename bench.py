@@ -98,6 +98,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-cubes", type=int, default=48)
     ap.add_argument("--batch-chunks", type=int, default=3)
+    ap.add_argument("--no-multistart", action="store_true")
+    ap.add_argument("--ms-iters", type=int, default=200)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-rate", type=float, default=20.0)
@@ -186,6 +188,64 @@ def batch_form(mm, torch, synth, n_cubes, chunks, seed=7):
             "ms_per_chunk": round(1e3 * tb / chunks, 2),
             "one_after_another_cube_iters_per_s": round(n_cubes * iters / ts, 2),
             "speedup_vs_one_after_another": round(ts / tb, 3), "setup_s": round(setup_s, 2)}
+
+
+def multistart_form(mm, torch, synth, iters, seed=0, eta_mu=1e-3, eta_gamma=2e-4):
+    """Multi-start ADA-PT: the 256^2 px x 64 band cube (PSF 512^2) from the
+    four initial couples (mu, gamma) of Section 4.2, FP32, Delta = 10, as one
+    batch (one graph launch per 10 iterations of all four starts); then the
+    same four starts one after the other.  theta, SNR and WMSE of each start
+    after the timed iterations."""
+    p = synth.make_config("c1", seed=seed, device="cuda:0")
+    d = lambda a: torch.from_numpy(a).to("cuda:0", torch.float32)
+    dirty, psf, delta, truth = d(p.dirty), d(p.psf), d(p.delta), d(p.sky)
+    cfg = mm.default_config(p.n, p.L, mode=mm.F32, sure=1, delta_period=10,
+                            eps_fd=0.01 * p.sigma_w, sigma_w=p.sigma_w, eta_mu=eta_mu,
+                            eta_gamma=eta_gamma, pi_iters=100)
+    chunks = max(1, iters // 10)
+    ms = mm.MultiStart(cfg)
+    ms.set_problem(dirty, psf, delta=delta)
+    ms.run(1)                                  # eager chunk + graph capture
+    ms.synchronize()
+    t0 = time.perf_counter()
+    ms.run(chunks)
+    ms.synchronize()
+    tb = time.perf_counter() - t0
+    snr, wmse = ms.quality(truth)
+    starts = []
+    for i, (m0, g0) in enumerate(ms.starts):
+        r = ms.start(i).report()
+        starts.append({"theta0": [m0, g0], "mu": round(r["mu"], 6), "gamma": round(r["gamma"], 6),
+                       "sugar_mu": float(f"{r['sugar_mu']:.4g}"),
+                       "sugar_gamma": float(f"{r['sugar_gamma']:.4g}"),
+                       "snr_db": round(float(snr[i]), 3), "wmse": float(f"{wmse[i]:.4g}")})
+    ms.close()
+    # the same starts one after the other, eager, for the same iterations
+    ts = 0.0
+    for m0, g0 in mm.MultiStart.PAPER_STARTS:
+        c = mm.default_config(p.n, p.L, mode=mm.F32, sure=1, delta_period=10,
+                              eps_fd=0.01 * p.sigma_w, sigma_w=p.sigma_w, eta_mu=eta_mu,
+                              eta_gamma=eta_gamma, pi_iters=100, mu=m0, gamma=g0)
+        h = mm.Muffin(c)
+        h.set_problem(dirty, psf, None, None, delta)
+        h.run(10, report=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.run(10 * chunks, report=False)
+        torch.cuda.synchronize()
+        ts += time.perf_counter() - t0
+        h.close()
+    del dirty, psf, delta, truth
+    torch.cuda.empty_cache()
+    k = 10 * (chunks + 1)
+    return {"form": "ADA-PT, FP32, 256x256 px x 64 bands from the four (mu, gamma) of "
+                    "Section 4.2, one captured graph per 10 iterations of all starts",
+            "eta": [eta_mu, eta_gamma], "iterations_timed": 10 * chunks,
+            "start_iters_per_s": round(4 * 10 * chunks / tb, 2),
+            "ms_per_iteration_all_starts": round(1e3 * tb / (10 * chunks), 3),
+            "one_after_another_start_iters_per_s": round(4 * 10 * chunks / ts, 2),
+            "speedup_vs_one_after_another": round(ts / tb, 3),
+            "after_iterations": k, "starts": starts}
 
 
 def serve_form(mm, torch, synth, n_req, rate, seed=11):
@@ -436,6 +496,14 @@ def main():
                 f"x{batch['speedup_vs_one_after_another']} vs one after another")
         except Exception as e:  # report, do not hide
             batch = {"error": str(e)}
+    multistart = None
+    if not args.no_multistart:
+        try:
+            multistart = multistart_form(mm, torch, synth, args.ms_iters)
+            log(f"[bench] multi-start: {multistart['start_iters_per_s']} start-it/s, "
+                f"x{multistart['speedup_vs_one_after_another']} vs one after another")
+        except Exception as e:  # report, do not hide
+            multistart = {"error": str(e)}
     serve = None
     if not args.no_serve:
         try:
@@ -476,6 +544,7 @@ def main():
         "fp64_plain": fp64,
         "accuracy": accuracy,
         "batch": batch,
+        "multistart": multistart,
         "serve": serve,
         "cpu_baseline": cpu,
     }

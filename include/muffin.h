@@ -280,6 +280,50 @@ int muffin_batch_create(muffin_batch** b, muffin_handle* const* handles, int32_t
 int muffin_batch_run(muffin_batch* b, int32_t chunks);
 int muffin_batch_destroy(muffin_batch* b);
 
+/* ---- multi-start ADA-PT: one cube from several initial theta ----
+ * Section 4.2 runs ADA-PT on one cube from four initial couples
+ * theta^(0) = (mu, gamma) and follows theta, SUGAR, SNR and WMSE per
+ * iteration.  A multi-start object holds one handle per start (cfg with
+ * mu = mu0[i], gamma = gamma0[i]; cfg->sure may be 0 for a plain sweep of
+ * fixed theta), each on a stream of its own, and iterates them as one batch
+ * (one graph launch per chunk of every start, as muffin_batch_*).
+ *   create:      starts in 1..64; mu0, gamma0 host double[starts], >= 0.
+ *                stream: the root stream (NULL: one of its own).
+ *   set_problem: as muffin_set_problem, once for all starts; the weights
+ *                (alpha/beta NULL: the rule of Section 2.1) and beta_H are
+ *                computed by the first start and handed to the others, so
+ *                every start sees the same problem bit for bit.  chunk as
+ *                in muffin_batch_create (0: the least valid value).
+ *   run:         enqueues chunks x chunk iterations of every start on the
+ *                root stream, ordered after earlier work on the starts'
+ *                streams and before later work on them.
+ *   quality:     per start, SNR and WMSE of Section 4.1 against the true
+ *                sky (device [L][n][n], working type), FP64 sums;
+ *                snr_db, wmse: host double[starts].  Synchronises.
+ *   handle:      start i's handle for muffin_get_sky, muffin_get_history,
+ *                muffin_get_report (owned by the object; NULL if i is out
+ *                of range).
+ * Start i's results equal those of a lone muffin_run of its configuration
+ * on the same problem. */
+typedef struct muffin_multistart muffin_multistart;
+int muffin_multistart_create(muffin_multistart** m, const muffin_config* cfg, int32_t starts,
+                             const double* mu0, const double* gamma0, void* stream);
+int muffin_multistart_set_problem(muffin_multistart* m, const void* dirty, const void* psf,
+                                  const double* alpha, const double* beta, const void* delta,
+                                  int32_t chunk);
+int muffin_multistart_run(muffin_multistart* m, int32_t chunks);
+int muffin_multistart_quality(muffin_multistart* m, const void* truth, double* snr_db,
+                              double* wmse);
+muffin_handle* muffin_multistart_handle(muffin_multistart* m, int32_t i);
+int muffin_multistart_destroy(muffin_multistart* m);
+
+/* Reconstruction quality of the current sky estimate X against the true
+ * sky x* (Section 4.1): *snr_db = 10 log10(|x*|^2 / |x* - X|^2) and
+ * *wmse = |H (x* - X)|^2 / (N L), with |.| the Frobenius norm over the cube
+ * and FP64 sums.  truth: device [L][n][n] of the working type.  Either
+ * output may be NULL.  Requires muffin_set_problem; synchronises the stream. */
+int muffin_quality(muffin_handle* h, const void* truth, double* snr_db, double* wmse);
+
 /* ---- operator entry points (same kernels as the iteration) ----
  * in/out are device cubes of the handle's working type.
  *   op_H:   out = H_l in_l     (eq. `model`)

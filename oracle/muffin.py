@@ -16,6 +16,7 @@ Paper passages followed (arXiv 1905.08468):
   SUGAR-FDMC         Section 3.2, eq. `SUGAR`
   ADA-PT             Section 3.3, eq. `adaptgrad` and Algorithm 5
   objective          Section 2.1, eqs. `probopt`, `RegAll`
+  SNR, WMSE          Section 4.1, the two point estimates of quality
 
 Readings where the paper is silent (each also listed in the design notes):
   * X, U, V, T and all derivative states start at zero.
@@ -329,6 +330,17 @@ def objective(X, pb: Problem, mu: float, gamma: float) -> float:
     spec = np.sum(pb.gamma_n(gamma).ravel()
                   * np.sum(np.abs(Wl(X)).reshape(L, -1), axis=0))
     return float(data + spat + spec)
+
+
+def quality(X: np.ndarray, truth: np.ndarray, K: np.ndarray) -> tuple[float, float]:
+    """SNR (dB) and WMSE of an estimate X of the sky `truth` (Section 4.1):
+    SNR = 10 log10(sum_l |x*_l|^2 / sum_l |x*_l - x_l|^2) and
+    WMSE = (1 / (N L)) sum_l |H_l (x*_l - x_l)|^2, N pixels per band."""
+    L, n, _ = truth.shape
+    err = truth - X
+    snr = 10.0 * np.log10(np.sum(truth ** 2) / np.sum(err ** 2))
+    wmse = float(np.sum(H(err, K) ** 2)) / (n * n * L)
+    return float(snr), wmse
 
 
 def make_problem(dirty, psf, P=8, J=3, sigma=10.0, alpha=None, beta=None,

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <new>
 #include <numeric>
@@ -183,6 +184,8 @@ struct ImplBase {
   virtual int state_load(const void* buf, size_t bytes) = 0;
   virtual Timer& timer() = 0;
   virtual hipStream_t stream() = 0;
+  virtual int quality(const void* truth, double* snr_db, double* wmse) = 0;
+  virtual void preset_beta_H(double v) = 0;
 };
 
 size_t workspace_bytes_of(const muffin_config* c) {
@@ -224,6 +227,8 @@ struct Impl final : ImplBase {
   // the six FP64 sums of the relative change
   T *Usnap = nullptr, *Vsnap = nullptr;
   double* relsum = nullptr;
+  double* qsum = nullptr;        // quality sums (SNR, WMSE)
+  double preset_bH = 0.0;        // > 0: beta_H known, set-up skips the power iteration
   double last_rel = -1.0;
   bool stopped = false;
   // asynchronous chunks (serving): completion event, pinned copy of the sums
@@ -292,6 +297,7 @@ struct Impl final : ImplBase {
     hist = dev.alloc<double>((size_t)max_hist * kHistCols);
     dp = dev.alloc<DevParams>(1);
     flag = dev.alloc<int>(1);
+    qsum = dev.alloc<double>(4);
     if (cfg.stop_rel > 0) {
       Usnap = dev.alloc<T>(LN * P);
       Vsnap = dev.alloc<T>(LN);
@@ -466,7 +472,10 @@ struct Impl final : ImplBase {
     }
     // Lipschitz constant and tau (Section 2.2)
     beta_H = 0.0;
-    if (cfg.tau <= 0 || cfg.pi_iters > 0) RC(power_iteration(ps));
+    if (preset_bH > 0)
+      beta_H = preset_bH;
+    else if (cfg.tau <= 0 || cfg.pi_iters > 0)
+      RC(power_iteration(ps));
     hp = DevParams{};
     hp.mu = cfg.mu;
     hp.gamma = cfg.gamma;
@@ -988,6 +997,30 @@ struct Impl final : ImplBase {
     return avail;
   }
 
+  void preset_beta_H(double v) override { preset_bH = v; }
+
+  // Quality against a known sky (Section 4.1): SNR = 10 log10(|x*|^2 /
+  // |x* - X|^2) and WMSE = |H (x* - X)|^2 / (N L), FP64 sums.  G and S of
+  // the primal set are rebuilt at the start of every iteration, so between
+  // iterations they hold x* - X and its image under H.
+  int quality(const void* truth, double* snr_db, double* wmse) override {
+    if (!have_problem) return MUFFIN_E_STATE;
+    if (!truth) return MUFFIN_E_INVAL;
+    const T* xs = static_cast<const T*>(truth);
+    const int nb = dot_blocks();
+    RC(diff_sq<T>(xs, X[0], LN, partials, nb, qsum, st));
+    RC(axpy_copy<T>(G[0], xs, X[0], -1.0, LN, st));
+    RC(chain1(G[0], S[0], 0));
+    RC(diff_sq<T>(S[0], S[0], LN, partials, nb, qsum + 2, st));
+    double h[4];
+    MUFFIN_HIP_CHECK(hipMemcpyAsync(h, qsum, sizeof(h), hipMemcpyDeviceToHost, st));
+    MUFFIN_HIP_CHECK(hipStreamSynchronize(st));
+    if (snr_db)
+      *snr_db = h[0] > 0 ? 10.0 * std::log10(h[1] / h[0]) : std::numeric_limits<double>::infinity();
+    if (wmse) *wmse = h[3] / double(LN);
+    return 0;
+  }
+
   int weights(double* a, double* b) override {
     if (!have_problem) return MUFFIN_E_STATE;
     MUFFIN_HIP_CHECK(hipStreamSynchronize(st));
@@ -1061,6 +1094,7 @@ int handle_chunk_poll(muffin_handle* h, int* done, double* rel) {
   return h->impl->chunk_poll(done, rel);
 }
 size_t handle_workspace_bytes(const muffin_config* c) { return workspace_bytes_of(c); }
+void handle_preset_beta_H(muffin_handle* h, double v) { h->impl->preset_beta_H(v); }
 }  // namespace muffin
 
 // Many independent cubes as one graph: one chunk of iterations of every
@@ -1270,6 +1304,11 @@ int muffin_get_weights(muffin_handle* h, double* alpha, double* beta) {
 int muffin_get_report(muffin_handle* h, muffin_report* report) {
   if (!h || !report) return MUFFIN_E_INVAL;
   return h->impl->report(report);
+}
+
+int muffin_quality(muffin_handle* h, const void* truth, double* snr_db, double* wmse) {
+  if (!h) return MUFFIN_E_INVAL;
+  return h->impl->quality(truth, snr_db, wmse);
 }
 
 int muffin_set_initial(muffin_handle* h, const void* x0) {

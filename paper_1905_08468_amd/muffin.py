@@ -84,6 +84,9 @@ EXPORTS = [
     "muffin_server_poll", "muffin_server_wait", "muffin_server_cancel",
     "muffin_server_get_stats", "muffin_server_destroy",
     "muffin_batch_create", "muffin_batch_run", "muffin_batch_destroy",
+    "muffin_quality", "muffin_multistart_create", "muffin_multistart_set_problem",
+    "muffin_multistart_run", "muffin_multistart_quality", "muffin_multistart_handle",
+    "muffin_multistart_destroy",
 ]
 
 
@@ -129,6 +132,13 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "muffin_batch_create": ([C.POINTER(vp), C.POINTER(vp), i32, i32, vp], C.c_int),
         "muffin_batch_run": ([vp, i32], C.c_int),
         "muffin_batch_destroy": ([vp], C.c_int),
+        "muffin_quality": ([vp, vp, dp, dp], C.c_int),
+        "muffin_multistart_create": ([C.POINTER(vp), cfgp, i32, dp, dp, vp], C.c_int),
+        "muffin_multistart_set_problem": ([vp, vp, vp, dp, dp, vp, i32], C.c_int),
+        "muffin_multistart_run": ([vp, i32], C.c_int),
+        "muffin_multistart_quality": ([vp, vp, dp, dp], C.c_int),
+        "muffin_multistart_handle": ([vp, i32], vp),
+        "muffin_multistart_destroy": ([vp], C.c_int),
     }
     for name in ["muffin_op_H", "muffin_op_HT", "muffin_op_HTH", "muffin_op_Ws",
                  "muffin_op_WsT", "muffin_op_dct", "muffin_op_idct"]:
@@ -289,6 +299,16 @@ class Muffin:
         buf = np.zeros((max(cnt, 1), 8))
         _lib.muffin_get_history(self.h, buf.ctypes.data_as(C.POINTER(C.c_double)), cnt)
         return buf[:cnt]
+
+    def quality(self, truth):
+        """(SNR in dB, WMSE) of the current sky against the true sky
+        (Section 4.1), through muffin_quality."""
+        self._check(truth, self.cube, "truth")
+        snr, wmse = C.c_double(), C.c_double()
+        rc = _lib.muffin_quality(self.h, _ptr(truth), C.byref(snr), C.byref(wmse))
+        if rc:
+            raise MuffinError(rc, "muffin_quality")
+        return snr.value, wmse.value
 
     def weights(self):
         a = np.zeros(self.cfg.n * self.cfg.n)
@@ -475,6 +495,114 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             _lib.muffin_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _StartView(Muffin):
+    """A start's handle inside a MultiStart (owned and destroyed by it)."""
+
+    def __init__(self, h, cfg: Config, owner):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        self.dtype = torch.float64 if cfg.mode == F64 else torch.float32
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = None
+        self.h = h
+        self._owner = owner
+
+    def _settle(self):
+        # the start's stream belongs to the library: wait for the device
+        self.torch.cuda.synchronize()
+
+    def close(self):
+        self.h = None
+
+
+class MultiStart:
+    """One cube from several initial couples theta = (mu, gamma), iterated as
+    one batch (muffin_multistart_*).  The default starts are the four couples
+    of Section 4.2."""
+
+    PAPER_STARTS = ((1.0, 10.0), (1.0, 3.0), (0.005, 3.0), (0.005, 10.0))
+
+    def __init__(self, cfg: Config, starts=PAPER_STARTS, stream=None):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        self.starts = [(float(m), float(g)) for m, g in starts]
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        mu0 = np.array([m for m, _ in self.starts])
+        ga0 = np.array([g for _, g in self.starts])
+        m = C.c_void_p()
+        rc = _lib.muffin_multistart_create(
+            C.byref(m), C.byref(cfg), len(self.starts),
+            mu0.ctypes.data_as(C.POINTER(C.c_double)), ga0.ctypes.data_as(C.POINTER(C.c_double)),
+            C.c_void_p(self.stream.cuda_stream))
+        if rc:
+            raise MuffinError(rc, "muffin_multistart_create")
+        self.h = m
+        self.views = [_StartView(_lib.muffin_multistart_handle(m, i), cfg, self)
+                      for i in range(len(self.starts))]
+        self.chunk = 0
+
+    def set_problem(self, dirty, psf, alpha=None, beta=None, delta=None, chunk: int = 0):
+        v = self.views[0]
+        n, L = self.cfg.n, self.cfg.L
+        v._check(dirty, (L, n, n), "dirty")
+        v._check(psf, (L, 2 * n, 2 * n), "psf")
+        if delta is not None:
+            v._check(delta, (L, n, n), "delta")
+        a = _dptr(alpha)
+        b = _dptr(beta)
+        self._keep = (dirty, psf, delta)
+        # set-up runs on the starts' own streams: inputs must be complete
+        self.torch.cuda.current_stream().synchronize()
+        rc = _lib.muffin_multistart_set_problem(self.h, _ptr(dirty), _ptr(psf),
+                                                a[1] if a else None, b[1] if b else None,
+                                                _ptr(delta), int(chunk))
+        if rc:
+            raise MuffinError(rc, "muffin_multistart_set_problem")
+        need = 2
+        if self.cfg.sure:
+            need = np.lcm(2, int(self.cfg.delta_period))
+        self.chunk = int(chunk) if chunk else int(need)
+
+    def run(self, chunks: int):
+        """Enqueues chunks x self.chunk iterations of every start."""
+        rc = _lib.muffin_multistart_run(self.h, int(chunks))
+        if rc:
+            raise MuffinError(rc, "muffin_multistart_run")
+
+    def synchronize(self):
+        self.torch.cuda.synchronize()
+
+    def quality(self, truth):
+        """Per start (SNR dB, WMSE) of Section 4.1 against the true sky."""
+        self.views[0]._check(truth, self.views[0].cube, "truth")
+        k = len(self.starts)
+        snr, wmse = np.zeros(k), np.zeros(k)
+        rc = _lib.muffin_multistart_quality(self.h, _ptr(truth),
+                                            snr.ctypes.data_as(C.POINTER(C.c_double)),
+                                            wmse.ctypes.data_as(C.POINTER(C.c_double)))
+        if rc:
+            raise MuffinError(rc, "muffin_multistart_quality")
+        return snr, wmse
+
+    def start(self, i: int) -> Muffin:
+        return self.views[i]
+
+    def close(self):
+        if getattr(self, "h", None):
+            for v in self.views:
+                v.close()
+            _lib.muffin_multistart_destroy(self.h)
             self.h = None
 
     def __del__(self):
