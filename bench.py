@@ -100,6 +100,9 @@ def parse():
     ap.add_argument("--batch-chunks", type=int, default=3)
     ap.add_argument("--no-multistart", action="store_true")
     ap.add_argument("--ms-iters", type=int, default=200)
+    ap.add_argument("--ms-trace", type=int, default=0,
+                    help="record the multi-start curves every this many iterations "
+                         "(over --ms-iters iterations) instead of timing")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-rate", type=float, default=20.0)
@@ -190,12 +193,15 @@ def batch_form(mm, torch, synth, n_cubes, chunks, seed=7):
             "speedup_vs_one_after_another": round(ts / tb, 3), "setup_s": round(setup_s, 2)}
 
 
-def multistart_form(mm, torch, synth, iters, seed=0, eta_mu=1e-3, eta_gamma=2e-4):
+def multistart_form(mm, torch, synth, iters, seed=0, eta_mu=5e-3, eta_gamma=1e-3,
+                    trace_every=0):
     """Multi-start ADA-PT: the 256^2 px x 64 band cube (PSF 512^2) from the
     four initial couples (mu, gamma) of Section 4.2, FP32, Delta = 10, as one
     batch (one graph launch per 10 iterations of all four starts); then the
     same four starts one after the other.  theta, SNR and WMSE of each start
-    after the timed iterations."""
+    after the timed iterations.  trace_every > 0: instead, run `iters`
+    iterations untimed and record theta, SUGAR, SNR and WMSE of every start
+    each trace_every iterations (the curves of Section 4.2)."""
     p = synth.make_config("c1", seed=seed, device="cuda:0")
     d = lambda a: torch.from_numpy(a).to("cuda:0", torch.float32)
     dirty, psf, delta, truth = d(p.dirty), d(p.psf), d(p.delta), d(p.sky)
@@ -205,6 +211,26 @@ def multistart_form(mm, torch, synth, iters, seed=0, eta_mu=1e-3, eta_gamma=2e-4
     chunks = max(1, iters // 10)
     ms = mm.MultiStart(cfg)
     ms.set_problem(dirty, psf, delta=delta)
+    if trace_every > 0:
+        rows = [[] for _ in ms.starts]
+        t0 = time.perf_counter()
+        for k in range(trace_every, iters + 1, trace_every):
+            ms.run(trace_every // 10)
+            snr, wmse = ms.quality(truth)
+            for i in range(len(ms.starts)):
+                h = ms.start(i).history()[-1]
+                rows[i].append([k, round(h[1], 5), round(h[2], 5), float(f"{h[4]:.4g}"),
+                                float(f"{h[5]:.4g}"), round(float(snr[i]), 3),
+                                float(f"{wmse[i]:.4g}")])
+            log(f"[bench] multi-start trace k={k}: gamma "
+                + " ".join(f"{r[-1][2]:.3f}" for r in rows) + " snr "
+                + " ".join(f"{r[-1][5]:.2f}" for r in rows))
+        el = time.perf_counter() - t0
+        ms.close()
+        return {"form": "multi-start trace, ADA-PT FP32 256x256 px x 64 bands",
+                "eta": [eta_mu, eta_gamma], "iterations": iters, "seconds": round(el, 2),
+                "columns": ["k", "mu", "gamma", "sugar_mu", "sugar_gamma", "snr_db", "wmse"],
+                "starts": [{"theta0": list(t), "rows": r} for t, r in zip(ms.starts, rows)]}
     ms.run(1)                                  # eager chunk + graph capture
     ms.synchronize()
     t0 = time.perf_counter()
@@ -499,9 +525,11 @@ def main():
     multistart = None
     if not args.no_multistart:
         try:
-            multistart = multistart_form(mm, torch, synth, args.ms_iters)
-            log(f"[bench] multi-start: {multistart['start_iters_per_s']} start-it/s, "
-                f"x{multistart['speedup_vs_one_after_another']} vs one after another")
+            multistart = multistart_form(mm, torch, synth, args.ms_iters,
+                                         trace_every=args.ms_trace)
+            if not args.ms_trace:
+                log(f"[bench] multi-start: {multistart['start_iters_per_s']} start-it/s, "
+                    f"x{multistart['speedup_vs_one_after_another']} vs one after another")
         except Exception as e:  # report, do not hide
             multistart = {"error": str(e)}
     serve = None

@@ -20,6 +20,7 @@
 #include "internal.hpp"
 
 #include <complex>
+#include <type_traits>
 #include <cmath>
 #include <vector>
 
@@ -174,6 +175,41 @@ constexpr int kDwtMinWaves = MUFFIN_DWT_MIN_WAVES;
 constexpr int kHalo = 14;  // 2 * 8 - 2: longest filter
 constexpr int kSHal = 7;   // synthesis halo (8 - 1)
 
+// Raw buffer access: a resource over one plane (block-uniform base, size in
+// elements; reads past the end return 0, writes past it are dropped) and
+// loads/stores at 32-bit byte offsets, so the tile traffic spends no
+// per-lane 64-bit address arithmetic.  The base and size are taken from the
+// first lane, so the resource is known to be uniform wherever the compiler
+// places its computation (a resource it took for divergent would cost a
+// loop over lanes at every access).
+template <typename E>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const E* base, size_t count) {
+  const uint64_t pv = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)pv);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(pv >> 32));
+  const int bytes = __builtin_amdgcn_readfirstlane((int)(count * sizeof(E)));
+  return __builtin_amdgcn_make_buffer_rsrc(
+      reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), (short)0, bytes, 0x00020000);
+}
+// boff: per-lane byte offset; soff: block-uniform byte offset (e.g. of one
+// basis' plane inside a resource over all bases of a band)
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t boff, uint32_t soff = 0) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, boff, soff, 0));
+  else
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, boff, soff, 0));
+}
+typedef unsigned int muffin_u32x2 __attribute__((__vector_size__(8)));
+template <typename T>
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t boff, T v,
+                                       uint32_t soff = 0) {
+  if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, boff, soff, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(muffin_u32x2, v), r, boff, soff, 0);
+}
+
 template <typename T>
 struct AnArgs {
   const T* xt_a[kMaxSets];
@@ -230,29 +266,45 @@ __device__ __forceinline__ void an_rows(const T* in, T* rowbuf, int IN) {
 
 // Outputs of one thread in the column filter of a basis: rows kr0 + 2 kp + e
 // (e = 0, 1) of column q of the row-filtered tile, low (part 0) and high
-// (part 1) pass.  q < TO are the row-low columns, q >= TO the row-high ones.
-// Index of output (e, part) in the basis plane, or -1 for the low-low band
-// that goes to the next level (or out of range).
-template <int TO>
-__device__ __forceinline__ long an_out_index(int e, int part, int kr0, int kc0, int half, int n,
-                                             bool last) {
-  const int q = threadIdx.x % (2 * TO), kp = threadIdx.x / (2 * TO);
-  const bool dcol = q >= TO;
-  const int kc = kc0 + (dcol ? q - TO : q);
-  const int krow = kr0 + 2 * kp + e;
-  if (krow >= half || kc >= half) return -1;
-  if (part == 0 && !dcol && !last) return -1;
-  const int row = part == 0 ? krow : half + krow;
-  const int colq = dcol ? half + kc : kc;
-  return (long)row * n + colq;
-}
+// (part 1) pass; q < TO are the row-low columns, q >= TO the row-high ones.
+// Output i = 2 e + part updates U at element uoff[i] of the basis plane
+// (to_u), except the low-low band, which goes to the next level at element
+// loff[e] of its plane (to_ll).  Offsets of unused outputs are 0 (valid
+// reads).  The same for every basis: computed once per block.
+struct AnLanes {
+  uint32_t uoff[4], loff[2];
+  bool to_u[4], to_ll[2];
+  template <int TO>
+  __device__ __forceinline__ void init(int kr0, int kc0, int half, int n, bool last) {
+    const int q = threadIdx.x % (2 * TO), kp = threadIdx.x / (2 * TO);
+    const bool dcol = q >= TO;
+    const int kc = kc0 + (dcol ? q - TO : q);
+    const int colq = dcol ? half + kc : kc;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int krow = kr0 + 2 * kp + e;
+      const bool ok = krow < half && kc < half;
+      const bool ll = !dcol && !last;
+      to_ll[e] = ok && ll;
+      loff[e] = to_ll[e] ? (uint32_t)(krow * half + kc) : 0u;
+      to_u[2 * e] = ok && !ll;
+      uoff[2 * e] = to_u[2 * e] ? (uint32_t)(krow * n + colq) : 0u;
+      to_u[2 * e + 1] = ok;
+      uoff[2 * e + 1] = ok ? (uint32_t)((half + krow) * n + colq) : 0u;
+    }
+  }
+};
 
 // Column filter of basis PB and the dual update (or low-pass output) of this
 // thread's four outputs; u/m hold the prefetched dual values and masks.
+// rU, rM, rL: the band's planes of U, of the masks and of the next level;
+// sU, sM, sL: byte offsets of this basis' plane in them.
 template <typename T, int TO, int NT, int PB>
-__device__ __forceinline__ void an_cols(const AnArgs<T>& a, const T* rowbuf, int set, int band,
-                                        int kr0, int kc0, double scale, const T (&u)[4],
-                                        const uint8_t (&m)[4]) {
+__device__ __forceinline__ void an_cols(const AnArgs<T>& a, const T* rowbuf, const AnLanes& ln,
+                                        __amdgpu_buffer_rsrc_t rU, __amdgpu_buffer_rsrc_t rM,
+                                        __amdgpu_buffer_rsrc_t rL, uint32_t sU, uint32_t sM,
+                                        uint32_t sL, bool mask_out, bool mask_in, T scale,
+                                        const T (&u)[4], const uint8_t (&m)[4]) {
   constexpr int TAPS = 2 * PB;
   T h[TAPS], g[TAPS];
 #pragma unroll
@@ -260,19 +312,27 @@ __device__ __forceinline__ void an_cols(const AnArgs<T>& a, const T* rowbuf, int
     h[k] = filt_h<T>(PB - 1, k);
     g[k] = filt_g<T>(PB - 1, k);
   }
-  const int pidx = PB - 1;
-  const int n = a.n, half = a.Ms >> 1;
-  const size_t plane = (size_t)n * n;
-  T* U = a.U[set] + ((size_t)band * a.P + pidx) * plane;
-  uint8_t* M = a.mask[set] ? a.mask[set] + ((size_t)band * a.P + pidx) * plane : nullptr;
-  T* llo = a.last ? nullptr : a.llout[set] + ((size_t)band * a.P + pidx) * (size_t)half * half;
   const int q = threadIdx.x % (2 * TO), kp = threadIdx.x / (2 * TO);
-  const bool dcol = q >= TO;
-  const int kc = kc0 + (dcol ? q - TO : q);
-  const int kr = 2 * kp;
+  const T* col = rowbuf + (4 * kp) * (2 * TO) + q;
   T w[TAPS + 2];
 #pragma unroll
-  for (int i = 0; i < TAPS + 2; ++i) w[i] = rowbuf[(2 * kr + i) * (2 * TO) + q];
+  for (int i = 0; i < TAPS + 2; ++i) w[i] = col[i * (2 * TO)];
+  auto update = [&](int i, T c) {
+    const uint32_t bo = ln.uoff[i] * (uint32_t)sizeof(T);
+    if (a.pure) {
+      buf_st<T>(rU, bo, T(a.pure_scale) * c, sU);
+      return;
+    }
+    const T pv = u[i] + scale * c;
+    if (a.role == ROLE_PRIMAL) {
+      buf_st<T>(rU, bo, pv < T(-1) ? T(-1) : (pv > T(1) ? T(1) : pv), sU);
+      if (mask_out)
+        __builtin_amdgcn_raw_buffer_store_b8((pv >= T(-1) && pv <= T(1)) ? 1 : 0, rM, ln.uoff[i],
+                                             sM, 0);
+    } else {
+      buf_st<T>(rU, bo, (mask_in && m[i]) ? pv : T(0), sU);
+    }
+  };
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     T lo = T(0), hi = T(0);
@@ -281,29 +341,9 @@ __device__ __forceinline__ void an_cols(const AnArgs<T>& a, const T* rowbuf, int
       lo += h[k] * w[2 * e + k];
       hi += g[k] * w[2 * e + k];
     }
-    const int krow = kr0 + kr + e;
-    if (krow >= half || kc >= half) continue;
-#pragma unroll
-    for (int part = 0; part < 2; ++part) {
-      const T c = part == 0 ? lo : hi;
-      if (part == 0 && !dcol && !a.last) {
-        llo[(size_t)krow * half + kc] = c;  // LL goes to the next level
-        continue;
-      }
-      const int row = part == 0 ? krow : half + krow;
-      const size_t idx = (size_t)row * n + (dcol ? half + kc : kc);
-      if (a.pure) {
-        U[idx] = T(a.pure_scale) * c;
-        continue;
-      }
-      const T pv = u[2 * e + part] + T(scale) * c;
-      if (a.role == ROLE_PRIMAL) {
-        U[idx] = pv < T(-1) ? T(-1) : (pv > T(1) ? T(1) : pv);
-        if (M) M[idx] = (pv >= T(-1) && pv <= T(1)) ? 1 : 0;
-      } else {
-        U[idx] = (M && m[2 * e + part]) ? pv : T(0);
-      }
-    }
+    if (ln.to_ll[e]) buf_st<T>(rL, ln.loff[e] * (uint32_t)sizeof(T), lo, sL);  // LL: next level
+    if (ln.to_u[2 * e]) update(2 * e, lo);
+    if (ln.to_u[2 * e + 1]) update(2 * e + 1, hi);
   }
 }
 
@@ -322,7 +362,8 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_an(AnArgs<T> a) {
   const int lb = xcd_remap_d(blockIdx.x, a.nblocks);
   if (lb >= a.nblocks) return;
   const int tiles2 = a.tiles * a.tiles;
-  const int band = lb / tiles2;
+  // (block-uniform; kept in scalar registers so plane addressing stays scalar)
+  const int band = __builtin_amdgcn_readfirstlane(lb / tiles2);
   const int tile = lb - band * tiles2;
   const int kr0 = (tile / a.tiles) * TO, kc0 = (tile % a.tiles) * TO;
   const int set = blockIdx.y;
@@ -338,67 +379,77 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_an(AnArgs<T> a) {
   // the thread does not update are ignored) and land in a slot chosen at
   // compile time, so no register copy makes the wave wait for them before
   // they are used.
-  int oidx[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const long idx = an_out_index<TO>(i >> 1, i & 1, kr0, kc0, half, n, a.last);
-    oidx[i] = idx < 0 ? 0 : (int)idx;
-  }
+  AnLanes ln;
+  ln.init<TO>(kr0, kc0, half, n, a.last);
   const bool has_m = a.role == ROLE_DERIV && a.mask[set] != nullptr;
+  const bool mask_out = a.role == ROLE_PRIMAL && a.mask[set] != nullptr && !a.pure;
+  // the band's planes of U, masks and next-level outputs (all bases); a
+  // basis is selected by a uniform offset (planes a launch does not have:
+  // any valid base, never accessed)
+  const size_t bpl = (size_t)band * a.P;
+  const size_t hh = (size_t)half * half;
+  const auto rU = plane_rsrc(a.U[set] + bpl * plane, (size_t)a.P * plane);
+  const auto rM = plane_rsrc(a.mask[set] ? a.mask[set] + bpl * plane
+                                         : reinterpret_cast<uint8_t*>(a.U[set]),
+                             (size_t)a.P * plane);
+  const auto rL = plane_rsrc(a.last ? a.U[set] : a.llout[set] + bpl * hh,
+                             a.last ? plane : (size_t)a.P * hh);
   T u[2][4];
   uint8_t m[2][4];
   auto fetch_um = [&](int pidx, T (&uo)[4], uint8_t (&mo)[4]) {
-    const size_t pl = ((size_t)band * a.P + (pidx < a.P ? pidx : a.P - 1)) * plane;
-    const T* U = a.U[set] + pl;
+    const uint32_t sp = (uint32_t)((pidx < a.P ? pidx : a.P - 1) * plane);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) uo[i] = U[oidx[i]];
+    for (int i = 0; i < 4; ++i)
+      uo[i] = buf_ld<T>(rU, ln.uoff[i] * (uint32_t)sizeof(T), sp * (uint32_t)sizeof(T));
     if (has_m) {  // uniform; mo is only read when has_m
-      const uint8_t* M = a.mask[set] + pl;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) mo[i] = M[oidx[i]];
+      for (int i = 0; i < 4; ++i) mo[i] = __builtin_amdgcn_raw_buffer_load_b8(rM, ln.uoff[i], sp, 0);
     }
   };
   fetch_um(0, u[0], m[0]);
-  // ---- coarser levels: this thread's tile offsets in a basis' LL plane ----
+  // ---- this thread's tile offsets (bytes) in a plane of side Ms ----
   // (wrapped into the plane, so every offset is valid, also for t >= IN^2)
   constexpr int NI = (IN * IN + NT - 1) / NT;
-  int ioff[NI];
+  uint32_t ioff[NI];
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
     const int t = threadIdx.x + i * NT;
     const int r = t / IN, c = t - r * IN;
-    ioff[i] = ((2 * kr0 + r) & msk) * Ms + ((2 * kc0 + c) & msk);
+    ioff[i] = (uint32_t)((((2 * kr0 + r) & msk) * Ms + ((2 * kc0 + c) & msk)) * (int)sizeof(T));
   }
   T nxt[NI];
+  const size_t mpl = (size_t)Ms * Ms;
+  const auto rI = plane_rsrc(DEEP ? a.llin[set] + bpl * mpl : a.U[set], DEEP ? a.P * mpl : plane);
   auto fetch_ll = [&](int pidx) {
-    const T* src = a.llin[set] + ((size_t)band * a.P + pidx) * (size_t)Ms * Ms;
+    const uint32_t sp = (uint32_t)(pidx * mpl * sizeof(T));
 #pragma unroll
-    for (int i = 0; i < NI; ++i) nxt[i] = src[ioff[i]];
+    for (int i = 0; i < NI; ++i) nxt[i] = buf_ld<T>(rI, ioff[i], sp);
   };
   // ---- stage the input tile (periodic wrap) ----
   if constexpr (!DEEP) {
     // level 1: z = c1 (2 x~ - x) [+ c2 (2 x~b - xb)], all loads issued first
     const double c1 = coef_of(a.c1_sel[set], a.dp), c2 = coef_of(a.c2_sel[set], a.dp);
-    const T* xa = a.x_a[set] + (size_t)band * plane;
-    const T* ta = a.xt_a[set] + (size_t)band * plane;
+    const auto rxa = plane_rsrc(a.x_a[set] + (size_t)band * plane, plane);
+    const auto rta = plane_rsrc(a.xt_a[set] + (size_t)band * plane, plane);
     const bool has_b = a.x_b[set] != nullptr;
-    const T* xb = has_b ? a.x_b[set] + (size_t)band * plane : xa;
-    const T* tb = has_b ? a.xt_b[set] + (size_t)band * plane : ta;
+    const auto rxb = plane_rsrc((has_b ? a.x_b[set] : a.x_a[set]) + (size_t)band * plane, plane);
+    const auto rtb = plane_rsrc((has_b ? a.xt_b[set] : a.xt_a[set]) + (size_t)band * plane, plane);
     T v0[NI], v1[NI], v2[NI], v3[NI];
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-      v0[i] = ta[ioff[i]];
-      v1[i] = xa[ioff[i]];
+      v0[i] = buf_ld<T>(rta, ioff[i]);
+      v1[i] = buf_ld<T>(rxa, ioff[i]);
       if (has_b) {
-        v2[i] = tb[ioff[i]];
-        v3[i] = xb[ioff[i]];
+        v2[i] = buf_ld<T>(rtb, ioff[i]);
+        v3[i] = buf_ld<T>(rxb, ioff[i]);
       }
     }
+    const T tc1 = T(c1), tc2 = T(c2);
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
       const int t = threadIdx.x + i * NT;
-      T z = T(c1) * (T(2) * v0[i] - v1[i]);
-      if (has_b) z += T(c2) * (T(2) * v2[i] - v3[i]);
+      T z = tc1 * (T(2) * v0[i] - v1[i]);
+      if (has_b) z += tc2 * (T(2) * v2[i] - v3[i]);
       if (t < IN * IN) s_in[t] = z;
     }
   } else {
@@ -411,7 +462,13 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_an(AnArgs<T> a) {
   }
   lds_barrier();
   const double beta = a.beta ? a.beta[band] : 1.0;
-  const double scale = a.dp ? a.dp->sigma * beta / sqrt((double)a.P) : 0.0;
+  const T scale = T(a.dp ? a.dp->sigma * beta / sqrt((double)a.P) : 0.0);
+  auto cols = [&](auto pb, const T (&uu)[4], const uint8_t (&mm)[4]) {
+    constexpr int PB = decltype(pb)::value;
+    const uint32_t sp = (uint32_t)((PB - 1) * plane);
+    an_cols<T, TO, NT, PB>(a, s_row, ln, rU, rM, rL, sp * (uint32_t)sizeof(T), sp,
+                           (uint32_t)((PB - 1) * hh * sizeof(T)), mask_out, has_m, scale, uu, mm);
+  };
 #define MUFFIN_AN_STEP(PB)                                                      \
   if (PB - 1 >= p0 && PB - 1 < p1) {                                            \
     const bool more = DEEP && PB < p1;                                          \
@@ -419,8 +476,7 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_an(AnArgs<T> a) {
     if (PB < p1) fetch_um(PB, u[PB & 1], m[PB & 1]);                            \
     an_rows<T, TO, NT, PB>(s_in, s_row, IN);                                    \
     lds_barrier();                                                            \
-    an_cols<T, TO, NT, PB>(a, s_row, set, band, kr0, kc0, scale, u[(PB - 1) & 1], \
-                           m[(PB - 1) & 1]);                                    \
+    cols(std::integral_constant<int, PB>{}, u[(PB - 1) & 1], m[(PB - 1) & 1]);  \
     if (more) {                                                                 \
       _Pragma("unroll") for (int i = 0; i < NI; ++i) {                          \
         const int t = threadIdx.x + i * NT;                                     \
@@ -446,27 +502,56 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_an(AnArgs<T> a) {
 template <typename T>
 struct SyArgs {
   const T* Ua[kMaxSets];
-  const T* Ub[kMaxSets];
-  int a1_sel[kMaxSets], a2_sel[kMaxSets];
   const T* llin[kMaxSets];   // level < J: [L][P][half^2]
   T* llout[kMaxSets];        // level >= 2: [L][P][Ms^2]
   T* S[kMaxSets];            // level 1: [L][n][n]
-  const double* beta;
-  const DevParams* dp;
+  const double* beta;        // [L] or null (then 1)
   int n, L, P, level, J;
-  int Ms, tiles, nblocks, pure;
+  int Ms, tiles, nblocks;
+};
+
+// Per-thread LDS positions of the separable synthesis, the same for every
+// basis (computed once per block): the column pass slides over APT
+// coefficient rows of one column of a quadrant pair, the row pass produces
+// 2 BPT consecutive outputs of one row.
+template <int TC, int NT, int APT_, int BPT_>
+struct SyLanes {
+  static constexpr int W = TC + kSHal;
+  static constexpr int APT = APT_;
+  static constexpr int BPT = BPT_;
+  static constexpr int NA = TC / APT;
+  static_assert(NA * 2 * W <= NT, "one column-pass item per thread");
+  static_assert(2 * TC * (TC / BPT) == NT, "one row-pass output group per thread");
+  bool col_on;
+  int ql, qh;   // column pass: first coefficient (row a0) of the low/high quadrant
+  int rout;     // column pass: first output (row 2 a0, column col) in rbuf
+  int rc;       // row pass: first value (column b0) of the c half of row ri
+  __device__ __forceinline__ SyLanes() {
+    const int t = threadIdx.x;
+    col_on = t < NA * 2 * W;
+    const int col = t % (2 * W), a0 = (t / (2 * W)) * APT;
+    const int hf = col >= W;
+    const int cc = hf ? col - W : col;
+    ql = (hf ? 2 : 0) * W * W + a0 * W + cc;
+    qh = ql + W * W;
+    rout = (2 * a0) * (2 * W) + col;
+    const int ri = t / (TC / BPT), b0 = (t % (TC / BPT)) * BPT;
+    rc = ri * (2 * W) + b0;
+  }
 };
 
 // Column synthesis of basis PB: from the four quadrants (low/high rows of the
 // c and d column halves) into rbuf[2TC][2 (TC + HAL)].  Each thread slides
 // over APT consecutive coefficient rows, so every LDS value it loads feeds
-// several outputs.
-template <typename T, int TC, int NT, int PB>
-__device__ __forceinline__ void sy_cols(const T* q, T* rbuf) {
-  constexpr int W = TC + kSHal;
-  constexpr int APT = 4;
-  constexpr int NA = TC / APT;
+// several outputs.  Window entry i holds coefficient row a0 + HAL + 1 - PB + i
+// (output a - a0 uses entries a - a0 - e + PB - 1, e < PB), so every LDS
+// offset from the thread's base is a compile-time constant.
+template <typename T, int PB, typename Lanes>
+__device__ __forceinline__ void sy_cols(const T* q, T* rbuf, const Lanes& ln) {
+  constexpr int W = Lanes::W;
+  constexpr int APT = Lanes::APT;
   constexpr int NW = APT + PB - 1;
+  constexpr int R0 = kSHal + 1 - PB;  // first window row relative to a0
   T he[PB], ho[PB], ge[PB], go[PB];
 #pragma unroll
   for (int e = 0; e < PB; ++e) {
@@ -477,20 +562,16 @@ __device__ __forceinline__ void sy_cols(const T* q, T* rbuf) {
   }
   // q layout: [quad][W][W], quad 0 = low rows / c cols, 1 = high rows / c cols,
   // 2 = low rows / d cols, 3 = high rows / d cols
-  for (int t = threadIdx.x; t < NA * 2 * W; t += NT) {
-    const int col = t % (2 * W), a0 = (t / (2 * W)) * APT;
-    const int hf = col >= W;
-    const int cc = hf ? col - W : col;
-    const T* ql = q + (hf ? 2 : 0) * W * W + cc;
-    const T* qh = q + (hf ? 3 : 1) * W * W + cc;
-    // coefficient rows a - e + HAL for a in [a0, a0 + APT), e < PB
-    const int row0 = a0 - PB + 1 + kSHal;
+  if (ln.col_on) {
+    const T* ql = q + ln.ql;
+    const T* qh = q + ln.qh;
     T wl[NW], wh[NW];
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
-      wl[i] = ql[(row0 + i) * W];
-      wh[i] = qh[(row0 + i) * W];
+      wl[i] = ql[(R0 + i) * W];
+      wh[i] = qh[(R0 + i) * W];
     }
+    T* out = rbuf + ln.rout;
 #pragma unroll
     for (int a = 0; a < APT; ++a) {
       // explicit FMA chains: two fused operations per tap and output
@@ -503,20 +584,20 @@ __device__ __forceinline__ void sy_cols(const T* q, T* rbuf) {
         od = fma(ho[e], l, od);
         od = fma(go[e], hh, od);
       }
-      rbuf[(2 * (a0 + a)) * (2 * W) + col] = ev;
-      rbuf[(2 * (a0 + a) + 1) * (2 * W) + col] = od;
+      out[(2 * a) * (2 * W)] = ev;
+      out[(2 * a + 1) * (2 * W)] = od;
     }
   }
 }
 
 // Row synthesis of basis PB, accumulated into acc[b][0..1] = outputs
 // (ri, 2 (b0 + b)) and (ri, 2 (b0 + b) + 1) of this thread.
-template <typename T, int TC, int NT, int PB>
-__device__ __forceinline__ void sy_rows(const T* rbuf, T (&acc)[2][2]) {
-  constexpr int W = TC + kSHal;
-  constexpr int BPT = 2;
+template <typename T, int PB, typename Lanes>
+__device__ __forceinline__ void sy_rows(const T* rbuf, T (&acc)[Lanes::BPT][2], const Lanes& ln) {
+  constexpr int W = Lanes::W;
+  constexpr int BPT = Lanes::BPT;
   constexpr int NW = BPT + PB - 1;
-  static_assert(2 * TC * (TC / BPT) == NT, "one thread per output quad");
+  constexpr int C0 = kSHal + 1 - PB;  // first window column relative to b0
   T he[PB], ho[PB], ge[PB], go[PB];
 #pragma unroll
   for (int e = 0; e < PB; ++e) {
@@ -525,16 +606,13 @@ __device__ __forceinline__ void sy_rows(const T* rbuf, T (&acc)[2][2]) {
     ge[e] = filt_g<T>(PB - 1, 2 * e);
     go[e] = filt_g<T>(PB - 1, 2 * e + 1);
   }
-  const int t = threadIdx.x;
-  const int ri = t / (TC / BPT), b0 = (t % (TC / BPT)) * BPT;
-  const T* rc = rbuf + ri * (2 * W);
+  const T* rc = rbuf + ln.rc;
   const T* rd = rc + W;
-  const int c0 = b0 - PB + 1 + kSHal;
   T wc[NW], wd[NW];
 #pragma unroll
   for (int i = 0; i < NW; ++i) {
-    wc[i] = rc[c0 + i];
-    wd[i] = rd[c0 + i];
+    wc[i] = rc[C0 + i];
+    wd[i] = rd[C0 + i];
   }
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
@@ -550,58 +628,64 @@ __device__ __forceinline__ void sy_rows(const T* rbuf, T (&acc)[2][2]) {
   }
 }
 
-// Stores a thread's output quad (acc[b][e] -> dst[2 b + e]) scaled by sc;
-// only the first pair when the row ends after it.
-template <typename T>
-__device__ __forceinline__ void store4(T* dst, const T (&acc)[2][2], T sc, bool full) {
-  if (full) {
-    if constexpr (sizeof(T) == 4) {
-      *reinterpret_cast<float4*>(dst) =
-          make_float4(sc * acc[0][0], sc * acc[0][1], sc * acc[1][0], sc * acc[1][1]);
-    } else {
-      reinterpret_cast<double2*>(dst)[0] = make_double2(sc * acc[0][0], sc * acc[0][1]);
-      reinterpret_cast<double2*>(dst)[1] = make_double2(sc * acc[1][0], sc * acc[1][1]);
+// Stores a thread's 2 BPT outputs (acc[b][e] -> dst[2 b + e]) scaled by sc,
+// those before the row's end (room = values left in the row; groups of four,
+// or the first pair only when the row is shorter than four).
+template <typename T, int BPT>
+__device__ __forceinline__ void store_row(T* dst, const T (&acc)[BPT][2], T sc, int room) {
+#pragma unroll
+  for (int g = 0; g < BPT / 2; ++g) {
+    const T(&a0)[2] = acc[2 * g];
+    const T(&a1)[2] = acc[2 * g + 1];
+    T* d = dst + 4 * g;
+    if (room >= 4 * g + 4) {
+      if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4*>(d) = make_float4(sc * a0[0], sc * a0[1], sc * a1[0], sc * a1[1]);
+      } else {
+        reinterpret_cast<double2*>(d)[0] = make_double2(sc * a0[0], sc * a0[1]);
+        reinterpret_cast<double2*>(d)[1] = make_double2(sc * a1[0], sc * a1[1]);
+      }
+    } else if (room > 4 * g) {
+      d[0] = sc * a0[0];
+      d[1] = sc * a0[1];
     }
-  } else {
-    dst[0] = sc * acc[0][0];
-    dst[1] = sc * acc[0][1];
   }
 }
 
 // DEEP = false: level 1 (the bases' syntheses summed into S); true: the
 // coarser levels (one output per basis).
 // PN: number of bases when known at compile time, or 0 (see dwt_an).
-// UB: the set combines two dual arrays (a1 U_a + a2 U_b, the d/dmu sets).
-template <typename T, int TC, int NT, bool DEEP, int PN, bool UB>
+template <typename T, int TC, int NT, int APT, int BPT, bool DEEP, int PN>
 __device__ __forceinline__ void sy_block(const SyArgs<T>& a, int lb, T* s_q, T* s_r) {
+  using Lanes = SyLanes<TC, NT, APT, BPT>;
   constexpr int W = TC + kSHal;
   constexpr int NQ = (4 * W * W + NT - 1) / NT;  // tile values per thread
   const int tiles2 = a.tiles * a.tiles;
-  const int band = lb / tiles2;
+  // (block-uniform; kept in scalar registers so plane addressing stays scalar)
+  const int band = __builtin_amdgcn_readfirstlane(lb / tiles2);
   const int tile = lb - band * tiles2;
   const int kr0 = (tile / a.tiles) * TC, kc0 = (tile % a.tiles) * TC;
   const int set = blockIdx.y;
   const int n = a.n, Ms = a.Ms, half = Ms >> 1, hm = half - 1;
   const size_t plane = (size_t)n * n;
-  const double a1 = a.pure ? 1.0 : coef_of(a.a1_sel[set], a.dp);
-  const double a2 = a.pure ? 0.0 : coef_of(a.a2_sel[set], a.dp);
   // Every block runs through all bases (the next basis' tile is fetched while
   // the current one is filtered): at level 1 their syntheses are summed, at
   // the coarser levels each basis has an output of its own.
   const int p0 = 0, p1 = PN ? PN : a.P;
   const bool has_ll = a.level < a.J;
-  // this thread's outputs: 4 consecutive values of one row
+  // this thread's outputs: 2 BPT consecutive values of one row
   const int o0 = 2 * kr0, q0 = 2 * kc0;
-  const int ri = threadIdx.x / (TC / 2), b0 = (threadIdx.x % (TC / 2)) * 2;
+  const int ri = threadIdx.x / (TC / BPT), b0 = (threadIdx.x % (TC / BPT)) * BPT;
   const int row = o0 + ri, col = q0 + 2 * b0;
   // coarser levels: store the synthesis of basis pidx and clear acc
-  auto store_level = [&](int pidx, T (&acc)[2][2]) {
+  auto store_level = [&](int pidx, T (&acc)[BPT][2]) {
     if (row < Ms && col < Ms) {
       T* dst = a.llout[set] + ((size_t)band * a.P + pidx) * (size_t)Ms * Ms +
                (size_t)row * Ms + col;
-      store4(dst, acc, T(1), col + 3 < Ms);
+      store_row<T, BPT>(dst, acc, T(1), Ms - col);
     }
-    acc[0][0] = acc[0][1] = acc[1][0] = acc[1][1] = T(0);
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) acc[b][0] = acc[b][1] = T(0);
   };
   // Offsets of this thread's tile values inside one basis plane (periodic
   // wrap), computed once: the low-low quadrant reads the coarser level's
@@ -626,39 +710,29 @@ __device__ __forceinline__ void sy_block(const SyArgs<T>& a, int lb, T* s_q, T* 
       off[i] = (uint32_t)(((roff + kr) * n + (coff + kc)) * (int)sizeof(T));
     }
   }
-  const T ta1 = T(a1), ta2 = T(a2);
-  constexpr bool has_ub = UB;
-  auto ld = [](const T* base, uint32_t boff) {
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
-  };
-  // Raw tile values of one basis: ra from U (or the coarser level's output
-  // for the low-low quadrant), rb from the second dual array when the set
-  // combines two.  The source of slot i is known from i except for the one
-  // slot that straddles the low-low quadrant's end, so the loads take a
-  // uniform base and a 32-bit offset; they are unconditional (no branch
-  // between a load and its use), so all of them stay in flight while the
-  // previous basis is filtered, and the combination is applied when the tile
-  // is written to LDS.
-  T ra[NQ], rb[NQ];
+  // Raw tile values of one basis, from U (or the coarser level's output for
+  // the low-low quadrant).  The source of slot i is known from i except for
+  // the one slot that straddles the low-low quadrant's end (loaded from both
+  // planes, then selected).  The loads are unconditional (no branch between
+  // a load and its use), so all of them stay in flight while the previous
+  // basis is filtered.
+  T ra[NQ];
   auto fetch = [&](int pidx) {
-    const T* Ua = a.Ua[set] + ((size_t)band * a.P + pidx) * plane;
-    const T* Ub = has_ub ? a.Ub[set] + ((size_t)band * a.P + pidx) * plane : Ua;
-    const T* ll = has_ll ? a.llin[set] + ((size_t)band * a.P + pidx) * (size_t)half * half : Ua;
+    const auto ru = plane_rsrc(a.Ua[set] + ((size_t)band * a.P + pidx) * plane, plane);
+    const auto rl = has_ll ? plane_rsrc(a.llin[set] + ((size_t)band * a.P + pidx) *
+                                            (size_t)half * half, (size_t)half * half)
+                           : ru;  // (the coarsest level reads U everywhere)
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
-      const bool q0 = has_ll && (int)threadIdx.x + i * NT < Q0;
-      if constexpr (UB) {
-        // two arrays: per-lane source and address (measured faster here
-        // than two uniform-base loads per slot); the low-low values of
-        // the coarsest level are U values and are combined too
-        ra[i] = ld(q0 ? ll : Ua, off[i]);
-        rb[i] = ld(Ub, q0 ? 0u : off[i]);
-      } else if ((i + 1) * NT <= Q0) {
-        ra[i] = ld(ll, off[i]);  // (ll = Ua at the coarsest level)
+      if ((i + 1) * NT <= Q0) {
+        ra[i] = buf_ld<T>(rl, off[i]);
       } else if (i * NT >= Q0) {
-        ra[i] = ld(Ua, off[i]);
+        ra[i] = buf_ld<T>(ru, off[i]);
       } else {
-        ra[i] = ld(q0 ? ll : Ua, off[i]);
+        const bool q0 = has_ll && (int)threadIdx.x + i * NT < Q0;
+        const T vl = buf_ld<T>(rl, q0 ? off[i] : 0u);
+        const T vu = buf_ld<T>(ru, off[i]);
+        ra[i] = q0 ? vl : vu;
       }
     }
   };
@@ -666,18 +740,13 @@ __device__ __forceinline__ void sy_block(const SyArgs<T>& a, int lb, T* s_q, T* 
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
       const int t = threadIdx.x + i * NT;
-      if (t < 4 * W * W) {
-        const bool q0 = has_ll && t < Q0;
-        T v = ra[i];
-        if (!q0) {
-          v = ta1 * v;
-          if (has_ub) v = fma(ta2, rb[i], v);
-        }
-        s_q[t] = v;
-      }
+      if (t < 4 * W * W) s_q[t] = ra[i];
     }
   };
-  T acc[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
+  const Lanes lanes;
+  T acc[BPT][2];
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) acc[b][0] = acc[b][1] = T(0);
   fetch(p0);
   commit();
   lds_barrier();
@@ -685,9 +754,9 @@ __device__ __forceinline__ void sy_block(const SyArgs<T>& a, int lb, T* s_q, T* 
   if (PB - 1 >= p0 && PB - 1 < p1) {                                              \
     const bool more = PB < p1;                                                    \
     if (more) fetch(PB);                                                          \
-    sy_cols<T, TC, NT, PB>(s_q, s_r);                                             \
+    sy_cols<T, PB>(s_q, s_r, lanes);                                              \
     lds_barrier();                                                              \
-    sy_rows<T, TC, NT, PB>(s_r, acc);                                             \
+    sy_rows<T, PB>(s_r, acc, lanes);                                              \
     if constexpr (DEEP) store_level(PB - 1, acc);                                 \
     if (more) commit();                                                           \
     lds_barrier();                                                              \
@@ -705,20 +774,19 @@ __device__ __forceinline__ void sy_block(const SyArgs<T>& a, int lb, T* s_q, T* 
   if (!DEEP && row < Ms && col < Ms) {
     const double beta = a.beta ? a.beta[band] : 1.0;
     T* dst = a.S[set] + (size_t)band * plane + (size_t)row * n + col;
-    store4(dst, acc, T(beta / sqrt((double)a.P)), col + 3 < Ms);
+    store_row<T, BPT>(dst, acc, T(beta / sqrt((double)a.P)), Ms - col);
   }
 }
 
-// One launch per kind of set: UB (the sets combining two dual arrays) or not,
-// so each kernel holds one compact instantiation.
-template <typename T, int TC, int NT, bool DEEP, int PN, bool UB>
+// TC x TC coefficient tiles of every quadrant per block (2 TC x 2 TC outputs).
+template <typename T, int TC, int NT, int APT, int BPT, bool DEEP, int PN>
 __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_sy(SyArgs<T> a) {
   constexpr int W = TC + kSHal;
   __shared__ T s_q[4 * W * W];
   __shared__ T s_r[2 * TC * 2 * W];
   const int lb = xcd_remap_d(blockIdx.x, a.nblocks);
   if (lb >= a.nblocks) return;
-  sy_block<T, TC, NT, DEEP, PN, UB>(a, lb, s_q, s_r);
+  sy_block<T, TC, NT, APT, BPT, DEEP, PN>(a, lb, s_q, s_r);
 }
 
 // ---------------------------------------------------------------------------
@@ -726,6 +794,8 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_sy(SyArgs<T> a) {
 // ---------------------------------------------------------------------------
 constexpr int kTO = 16;
 constexpr int kNT = 256;
+constexpr int kSyTC1 = 32;   // level-1 synthesis tile (coefficients per side)
+constexpr int kSyNT1 = 512;
 
 template <typename T>
 int dwt_analysis(const DwtPlan<T>& p, const AnalysisIO<T>& io, const DevParams* dp,
@@ -784,47 +854,42 @@ int dwt_synthesis(const DwtPlan<T>& p, const SynthesisIO<T>& io, const DevParams
   if (lev_lo <= 0) lev_lo = 1;
   if (lev_hi <= 0 || lev_hi > p.J) lev_hi = p.J;
   for (int lev = lev_hi; lev >= lev_lo; --lev) {
-    // two launches: the sets without a second dual array, then those with one
-    for (int ub = 0; ub < 2; ++ub) {
-      SyArgs<T> a{};
-      int ns = 0;
-      for (int i = 0; i < io.nsets; ++i) {
-        if ((io.Ub[i] != nullptr) != (ub == 1)) continue;
-        a.Ua[ns] = io.Ua[i];
-        a.Ub[ns] = io.Ub[i];
-        a.a1_sel[ns] = io.a1_sel[i];
-        a.a2_sel[ns] = io.a2_sel[i];
-        // output of level j (j >= 2, side n >> (j-1)): tmp0 for even j, tmp1 for odd j
-        a.llin[ns] = lev < p.J ? ((lev + 1) % 2 == 0 ? io.tmp0[i] : io.tmp1[i]) : nullptr;
-        a.llout[ns] = lev >= 2 ? (lev % 2 == 0 ? io.tmp0[i] : io.tmp1[i]) : nullptr;
-        a.S[ns] = io.S[i];
-        ++ns;
-      }
-      if (ns == 0) continue;
-      a.beta = io.beta;
-      a.dp = dp;
-      a.n = p.n;
-      a.L = p.L;
-      a.P = p.P;
-      a.level = lev;
-      a.J = p.J;
-      a.Ms = p.n >> (lev - 1);
-      a.pure = io.pure;
-      const int half = a.Ms >> 1;
-      a.tiles = (half + kTO - 1) / kTO;
-      a.nblocks = a.tiles * a.tiles * p.L;
-      dim3 grid(xcd_grid_h(a.nblocks), ns);
-      // (the basis count stays a run-time value here: compiled for P = 8 the
-      // fully unrolled kernel needs 137 VGPRs and runs at half the occupancy)
-      if (lev == 1) {
-        if (ub) dwt_sy<T, kTO, kNT, false, 0, true><<<grid, kNT, 0, s>>>(a);
-        else dwt_sy<T, kTO, kNT, false, 0, false><<<grid, kNT, 0, s>>>(a);
-      } else {
-        if (ub) dwt_sy<T, kTO, kNT, true, 0, true><<<grid, kNT, 0, s>>>(a);
-        else dwt_sy<T, kTO, kNT, true, 0, false><<<grid, kNT, 0, s>>>(a);
-      }
-      MUFFIN_HIP_CHECK(hipGetLastError());
+    SyArgs<T> a{};
+    for (int i = 0; i < io.nsets; ++i) {
+      a.Ua[i] = io.Ua[i];
+      // output of level j (j >= 2, side n >> (j-1)): tmp0 for even j, tmp1 for odd j
+      a.llin[i] = lev < p.J ? ((lev + 1) % 2 == 0 ? io.tmp0[i] : io.tmp1[i]) : nullptr;
+      a.llout[i] = lev >= 2 ? (lev % 2 == 0 ? io.tmp0[i] : io.tmp1[i]) : nullptr;
+      a.S[i] = io.S[i];
     }
+    a.beta = io.beta;
+    a.n = p.n;
+    a.L = p.L;
+    a.P = p.P;
+    a.level = lev;
+    a.J = p.J;
+    a.Ms = p.n >> (lev - 1);
+    const int half = a.Ms >> 1;
+    // level 1 in FP32 (the bulk of the traffic): 32 x 32 coefficient tiles,
+    // whose halo re-reads (39^2 / 32^2 = 1.49x) are far below those of
+    // 16 x 16 tiles (23^2 / 16^2 = 2.07x); FP64 (twice the LDS per tile) and
+    // the coarser levels keep 16 x 16
+    constexpr bool big = sizeof(T) == 4;
+    const int tc = lev == 1 && big ? kSyTC1 : kTO;
+    a.tiles = (half + tc - 1) / tc;
+    a.nblocks = a.tiles * a.tiles * p.L;
+    dim3 grid(xcd_grid_h(a.nblocks), io.nsets);
+    // (the basis count stays a run-time value here: compiled for P = 8 the
+    // fully unrolled kernel needs 137 VGPRs and runs at half the occupancy)
+    if (lev == 1) {
+      if constexpr (big)
+        dwt_sy<T, kSyTC1, kSyNT1, 8, 4, false, 0><<<grid, kSyNT1, 0, s>>>(a);
+      else
+        dwt_sy<T, kTO, kNT, 4, 2, false, 0><<<grid, kNT, 0, s>>>(a);
+    } else {
+      dwt_sy<T, kTO, kNT, 4, 2, true, 0><<<grid, kNT, 0, s>>>(a);
+    }
+    MUFFIN_HIP_CHECK(hipGetLastError());
   }
   return 0;
 }

@@ -127,11 +127,8 @@ struct AnalysisIO {
 // S_s = beta_l / sqrt(P) * W^T c_s.
 template <typename T>
 struct SynthesisIO {
-  const T* Ua[kMaxSets];
-  const T* Ub[kMaxSets];
-  int a1_sel[kMaxSets];
-  int a2_sel[kMaxSets];
-  T* S[kMaxSets];
+  const T* Ua[kMaxSets];     // dual array U of each set
+  T* S[kMaxSets];            // out: beta_l / sqrt(P) W_s^T U
   T* tmp0[kMaxSets];
   T* tmp1[kMaxSets];
   int nsets;

@@ -551,9 +551,6 @@ struct Impl final : ImplBase {
       // mu S' + S of the primal set: the primal step combines them)
       for (int s = 0; s < nsets; ++s) {
         io.Ua[s] = U[s];
-        io.a1_sel[s] = SEL_ONE;
-        io.Ub[s] = nullptr;
-        io.a2_sel[s] = SEL_ZERO;
         io.S[s] = S[s];
         io.tmp0[s] = tmp0(s);
         io.tmp1[s] = tmp1(s);
