@@ -796,6 +796,8 @@ constexpr int kTO = 16;
 constexpr int kNT = 256;
 constexpr int kSyTC1 = 32;   // level-1 synthesis tile (coefficients per side)
 constexpr int kSyNT1 = 512;
+constexpr int kAnTO1 = 32;   // level-1 analysis tile (outputs per subband side)
+constexpr int kAnNT1 = 1024;
 
 template <typename T>
 int dwt_analysis(const DwtPlan<T>& p, const AnalysisIO<T>& io, const DevParams* dp,
@@ -826,13 +828,21 @@ int dwt_analysis(const DwtPlan<T>& p, const AnalysisIO<T>& io, const DevParams* 
     a.last = lev == p.J;
     a.Ms = p.n >> (lev - 1);
     const int half = a.Ms >> 1;
-    a.tiles = (half + kTO - 1) / kTO;
+    // level 1 in FP32 with the paper's 8 bases: 32 x 32 output tiles per
+    // subband (input halo re-reads (64 + 14)^2 / 64^2 = 1.49x instead of
+    // (32 + 14)^2 / 32^2 = 2.07x)
+    constexpr bool big = sizeof(T) == 4;
+    const bool wide = big && lev == 1 && p.P == 8;
+    const int to = wide ? kAnTO1 : kTO;
+    a.tiles = (half + to - 1) / to;
     a.nblocks = a.tiles * a.tiles * p.L;
     a.role = io.role;
     a.pure = io.pure;
     a.pure_scale = io.pure_scale;
     dim3 grid(xcd_grid_h(a.nblocks), io.nsets);
-    if (p.P == 8) {
+    if (wide) {
+      if constexpr (big) dwt_an<T, kAnTO1, kAnNT1, false, 8><<<grid, kAnNT1, 0, s>>>(a);
+    } else if (p.P == 8) {
       if (lev == 1)
         dwt_an<T, kTO, kNT, false, 8><<<grid, kNT, 0, s>>>(a);
       else
