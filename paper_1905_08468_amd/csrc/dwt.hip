@@ -828,11 +828,11 @@ int dwt_analysis(const DwtPlan<T>& p, const AnalysisIO<T>& io, const DevParams* 
     a.last = lev == p.J;
     a.Ms = p.n >> (lev - 1);
     const int half = a.Ms >> 1;
-    // level 1 in FP32 with the paper's 8 bases: 32 x 32 output tiles per
-    // subband (input halo re-reads (64 + 14)^2 / 64^2 = 1.49x instead of
-    // (32 + 14)^2 / 32^2 = 2.07x)
+    // FP32 with the paper's 8 bases, subbands of side >= 64: 32 x 32 output
+    // tiles per subband (input halo re-reads (64 + 14)^2 / 64^2 = 1.49x
+    // instead of (32 + 14)^2 / 32^2 = 2.07x)
     constexpr bool big = sizeof(T) == 4;
-    const bool wide = big && lev == 1 && p.P == 8;
+    const bool wide = big && half >= 64 && p.P == 8;
     const int to = wide ? kAnTO1 : kTO;
     a.tiles = (half + to - 1) / to;
     a.nblocks = a.tiles * a.tiles * p.L;
@@ -841,7 +841,12 @@ int dwt_analysis(const DwtPlan<T>& p, const AnalysisIO<T>& io, const DevParams* 
     a.pure_scale = io.pure_scale;
     dim3 grid(xcd_grid_h(a.nblocks), io.nsets);
     if (wide) {
-      if constexpr (big) dwt_an<T, kAnTO1, kAnNT1, false, 8><<<grid, kAnNT1, 0, s>>>(a);
+      if constexpr (big) {
+        if (lev == 1)
+          dwt_an<T, kAnTO1, kAnNT1, false, 8><<<grid, kAnNT1, 0, s>>>(a);
+        else
+          dwt_an<T, kAnTO1, kAnNT1, true, 8><<<grid, kAnNT1, 0, s>>>(a);
+      }
     } else if (p.P == 8) {
       if (lev == 1)
         dwt_an<T, kTO, kNT, false, 8><<<grid, kNT, 0, s>>>(a);
@@ -880,22 +885,22 @@ int dwt_synthesis(const DwtPlan<T>& p, const SynthesisIO<T>& io, const DevParams
     a.J = p.J;
     a.Ms = p.n >> (lev - 1);
     const int half = a.Ms >> 1;
-    // level 1 in FP32 (the bulk of the traffic): 32 x 32 coefficient tiles,
-    // whose halo re-reads (39^2 / 32^2 = 1.49x) are far below those of
-    // 16 x 16 tiles (23^2 / 16^2 = 2.07x); FP64 (twice the LDS per tile) and
-    // the coarser levels keep 16 x 16
+    // level 1 in FP32: 32 x 32 coefficient tiles, whose halo re-reads
+    // (39^2 / 32^2 = 1.49x) are far below those of 16 x 16 tiles
+    // (23^2 / 16^2 = 2.07x); FP64 (twice the LDS per tile) and the coarser
+    // levels keep 16 x 16 (measured: no gain there)
     constexpr bool big = sizeof(T) == 4;
-    const int tc = lev == 1 && big ? kSyTC1 : kTO;
+    const bool wide = big && lev == 1 && half >= 64;
+    const int tc = wide ? kSyTC1 : kTO;
     a.tiles = (half + tc - 1) / tc;
     a.nblocks = a.tiles * a.tiles * p.L;
     dim3 grid(xcd_grid_h(a.nblocks), io.nsets);
     // (the basis count stays a run-time value here: compiled for P = 8 the
     // fully unrolled kernel needs 137 VGPRs and runs at half the occupancy)
-    if (lev == 1) {
-      if constexpr (big)
-        dwt_sy<T, kSyTC1, kSyNT1, 8, 4, false, 0><<<grid, kSyNT1, 0, s>>>(a);
-      else
-        dwt_sy<T, kTO, kNT, 4, 2, false, 0><<<grid, kNT, 0, s>>>(a);
+    if (wide) {
+      if constexpr (big) dwt_sy<T, kSyTC1, kSyNT1, 8, 4, false, 0><<<grid, kSyNT1, 0, s>>>(a);
+    } else if (lev == 1) {
+      dwt_sy<T, kTO, kNT, 4, 2, false, 0><<<grid, kNT, 0, s>>>(a);
     } else {
       dwt_sy<T, kTO, kNT, 4, 2, true, 0><<<grid, kNT, 0, s>>>(a);
     }
