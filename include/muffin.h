@@ -324,6 +324,32 @@ int muffin_multistart_destroy(muffin_multistart* m);
  * output may be NULL.  Requires muffin_set_problem; synchronises the stream. */
 int muffin_quality(muffin_handle* h, const void* truth, double* snr_db, double* wmse);
 
+/* ---- spectral unmixing of a reconstructed cube ----
+ * Section 4.3 separates the sources of a reconstructed cube by their
+ * spectra: k chosen endmember spectra (three in the paper, taken at bright
+ * pixels) and, for every pixel n, the abundances
+ *     a^n = argmin_{a >= 0} |x^n - E a|^2
+ * (positivity-constrained least squares, x^n the pixel's spectrum, E the
+ * L x k matrix whose columns are the spectra).  The solution is exact (all
+ * 2^k supports are examined; FP64 arithmetic whatever the cube's type).
+ *   plan_create: spectra host double[k][L] (row j = spectrum j), 1 <= k <= 4,
+ *                k <= L; E_INVAL if a value is not finite or the spectra are
+ *                linearly dependent.  Allocates a few KB of device memory.
+ *   run:         cube device [L][n][n] (double if mode is MUFFIN_F64, else
+ *                float); abund device [k][n][n] (same type); resid NULL or
+ *                device [n][n] (same type) receiving |x^n - E a^n|^2,
+ *                computed as |x^n|^2 - b^T a (b = E^T x^n): its absolute
+ *                error is of order cond(E^T E) eps |x^n|^2.
+ *                Enqueues one kernel on `stream` (NULL: the default stream);
+ *                does not synchronise.
+ * A plan may be used for any number of cubes with the same L. */
+typedef struct muffin_unmix_plan muffin_unmix_plan;
+int muffin_unmix_plan_create(muffin_unmix_plan** plan, const double* spectra, int32_t k,
+                             int32_t L);
+int muffin_unmix_run(const muffin_unmix_plan* plan, const void* cube, int32_t n, int32_t mode,
+                     void* abund, void* resid, void* stream);
+int muffin_unmix_plan_destroy(muffin_unmix_plan* plan);
+
 /* ---- operator entry points (same kernels as the iteration) ----
  * in/out are device cubes of the handle's working type.
  *   op_H:   out = H_l in_l     (eq. `model`)

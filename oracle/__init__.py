@@ -16,11 +16,14 @@ operators   H_l / H_l^T (windowed linear convolution, direct and FFT forms),
             the orthonormal DCT W_lambda and its adjoint.
 muffin      weights, step sizes, power iteration, one MUFFIN iteration
             (Algs. 1-2), the derivative recursions (Algs. 3-4), PSURE-FDMC,
-            SUGAR-FDMC and the ADA-PT loop (Alg. 5), the objective.
+            SUGAR-FDMC and the ADA-PT loop (Alg. 5), the objective, the
+            quality measures SNR and WMSE (Section 4.1).
+unmix       per-pixel positivity-constrained least squares against chosen
+            endmember spectra (the unmixing step of Section 4.3).
 
 Every function states the passage of the paper it follows.  Functions whose
 result no independent pin checks are marked "parity unpinned" in their
 docstring.
 """
 from .daubechies import daubechies_lowpass, daubechies_bank  # noqa: F401
-from . import operators, muffin  # noqa: F401
+from . import operators, muffin, unmix  # noqa: F401

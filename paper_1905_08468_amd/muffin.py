@@ -87,6 +87,7 @@ EXPORTS = [
     "muffin_quality", "muffin_multistart_create", "muffin_multistart_set_problem",
     "muffin_multistart_run", "muffin_multistart_quality", "muffin_multistart_handle",
     "muffin_multistart_destroy",
+    "muffin_unmix_plan_create", "muffin_unmix_run", "muffin_unmix_plan_destroy",
 ]
 
 
@@ -139,6 +140,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "muffin_multistart_quality": ([vp, vp, dp, dp], C.c_int),
         "muffin_multistart_handle": ([vp, i32], vp),
         "muffin_multistart_destroy": ([vp], C.c_int),
+        "muffin_unmix_plan_create": ([C.POINTER(vp), dp, i32, i32], C.c_int),
+        "muffin_unmix_run": ([vp, vp, i32, i32, vp, vp, vp], C.c_int),
+        "muffin_unmix_plan_destroy": ([vp], C.c_int),
     }
     for name in ["muffin_op_H", "muffin_op_HT", "muffin_op_HTH", "muffin_op_Ws",
                  "muffin_op_WsT", "muffin_op_dct", "muffin_op_idct"]:
@@ -603,6 +607,60 @@ class MultiStart:
             for v in self.views:
                 v.close()
             _lib.muffin_multistart_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Unmixer:
+    """Spectral unmixing against k endmember spectra (muffin_unmix_*): per
+    pixel, the non-negative least-squares abundances of Section 4.3."""
+
+    def __init__(self, spectra):
+        import torch
+        self.torch = torch
+        e = np.ascontiguousarray(spectra, dtype=np.float64)
+        if e.ndim != 2:
+            raise ValueError("spectra: (k, L) array")
+        self.k, self.L = e.shape
+        p = C.c_void_p()
+        rc = _lib.muffin_unmix_plan_create(C.byref(p), e.ctypes.data_as(C.POINTER(C.c_double)),
+                                           self.k, self.L)
+        if rc:
+            raise MuffinError(rc, "muffin_unmix_plan_create")
+        self.h = p
+
+    @staticmethod
+    def spectra_at(cube, pixels):
+        """Spectra of the cube at pixels [(i, j), ...] as a host (k, L)
+        array (the paper picks them at bright pixels)."""
+        return np.stack([cube[:, i, j].double().cpu().numpy() for i, j in pixels])
+
+    def run(self, cube, residual: bool = False, stream=None):
+        """cube: device (L, n, n) float32/float64 tensor.  Returns the
+        abundances (k, n, n) (and the squared residual (n, n))."""
+        torch = self.torch
+        L, n, n2 = cube.shape
+        if L != self.L or n != n2 or not cube.is_cuda or not cube.is_contiguous() \
+                or cube.dtype not in (torch.float32, torch.float64):
+            raise ValueError("cube: contiguous float32/float64 cuda tensor (L, n, n)")
+        mode = F64 if cube.dtype == torch.float64 else F32
+        a = torch.empty((self.k, n, n), dtype=cube.dtype, device=cube.device)
+        r = torch.empty((n, n), dtype=cube.dtype, device=cube.device) if residual else None
+        s = stream if stream is not None else torch.cuda.current_stream()
+        rc = _lib.muffin_unmix_run(self.h, _ptr(cube), n, mode, _ptr(a), _ptr(r),
+                                   C.c_void_p(s.cuda_stream))
+        if rc:
+            raise MuffinError(rc, "muffin_unmix_run")
+        return (a, r) if residual else a
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.muffin_unmix_plan_destroy(self.h)
             self.h = None
 
     def __del__(self):
