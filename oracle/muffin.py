@@ -16,6 +16,9 @@ Paper passages followed (arXiv 1905.08468):
   SUGAR-FDMC         Section 3.2, eq. `SUGAR`
   ADA-PT             Section 3.3, eq. `adaptgrad` and Algorithm 5
   objective          Section 2.1, eqs. `probopt`, `RegAll`
+  W_s choices        Section 2.1: the union of Daubechies bases or the IUWT
+                     (operators.StarletDictionary); the step rule carries
+                     ||W_s||^2 of the condition of Section 2.2
   SNR, WMSE          Section 4.1, the two point estimates of quality
 
 Readings where the paper is silent (each also listed in the design notes):
@@ -36,7 +39,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .operators import H, HT, SpatialDictionary, Wl, WlT, psf_spectrum
+from .operators import H, HT, SpatialDictionary, StarletDictionary, Wl, WlT, psf_spectrum
 
 # --------------------------------------------------------------------------
 # prox operators and weak derivatives (eqs. projpos, sat; Section 3.2)
@@ -79,6 +82,11 @@ def weights(X0: np.ndarray, Ws: SpatialDictionary, eps_w: float):
     return alpha, beta
 
 
+def ws_norm2_of(Ws, n: int) -> float:
+    """||W_s||^2 of a spatial dictionary on n x n images."""
+    return Ws.frame_norm2(n) if hasattr(Ws, "frame_norm2") else Ws.norm2
+
+
 def lipschitz(K: np.ndarray, n: int, iters: int = 1000, tol: float = 1e-13,
               seed: int = 7) -> float:
     """beta_H = max_l lambda_max(H_l^T H_l), the Lipschitz constant of the
@@ -99,13 +107,14 @@ def lipschitz(K: np.ndarray, n: int, iters: int = 1000, tol: float = 1e-13,
     return float(np.max(lam))
 
 
-def tau_rule(beta_H, sigma, mu_l, gamma_n, rule="opnorm", rho=0.99):
-    """Primal step tau satisfying the convergence condition of Section 2.2
-    with ||W_s|| = ||W_lambda|| = 1."""
+def tau_rule(beta_H, sigma, mu_l, gamma_n, rule="opnorm", rho=0.99, ws_norm2=1.0):
+    """Primal step tau satisfying the convergence condition of Section 2.2;
+    ||W_lambda|| = 1, ||W_s||^2 = ws_norm2 (1 for the union of orthonormal
+    bases)."""
     if rule == "opnorm":
-        k = np.max(mu_l ** 2) + np.max(gamma_n ** 2)
+        k = ws_norm2 * np.max(mu_l ** 2) + np.max(gamma_n ** 2)
     elif rule == "sum":
-        k = np.sum(mu_l ** 2) + np.sum(gamma_n ** 2)
+        k = ws_norm2 * np.sum(mu_l ** 2) + np.sum(gamma_n ** 2)
     else:
         raise ValueError(rule)
     return rho / (beta_H / 2.0 + sigma * k)
@@ -287,7 +296,8 @@ def run_adapt(pb: Problem, mu0: float, gamma0: float, iters: int, delta,
         if tau is not None:
             return float(tau)
         return float(tau_rule(beta_H, pb.sigma, pb.mu_l(mu),
-                              pb.gamma_n(gamma).ravel(), tau_mode, rho))
+                              pb.gamma_n(gamma).ravel(), tau_mode, rho,
+                              ws_norm2_of(pb.Ws, pb.Y.shape[-1])))
 
     t_now = cur_tau()
     S, Sb = State.zeros(L, n, P), State.zeros(L, n, P)
@@ -344,11 +354,12 @@ def quality(X: np.ndarray, truth: np.ndarray, K: np.ndarray) -> tuple[float, flo
 
 
 def make_problem(dirty, psf, P=8, J=3, sigma=10.0, alpha=None, beta=None,
-                 eps_w=1e-6) -> Problem:
+                 eps_w=1e-6, dictionary="daubechies") -> Problem:
     """Assemble a Problem; weights default to the rule of Section 2.1 with
-    the dirty cube as the initial estimate."""
+    the dirty cube as the initial estimate.  dictionary: "daubechies" (the
+    union of db1..dbP, J levels) or "starlet" (the IUWT with J scales)."""
     K = psf_spectrum(psf)
-    Ws = SpatialDictionary(P, J)
+    Ws = SpatialDictionary(P, J) if dictionary == "daubechies" else StarletDictionary(J)
     if alpha is None or beta is None:
         a, b = weights(dirty, Ws, eps_w)
         alpha = a if alpha is None else alpha

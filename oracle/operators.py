@@ -13,6 +13,10 @@ W_s  (spatial analysis dictionary, eq. `RegAll`; Section 4.2): the union of
      so that W_s^T W_s = I.  Coefficients are (L, P, n, n).
 W_lambda (spectral analysis dictionary): the orthonormal DCT-II along the
      band axis of every pixel spectrum; W_lambda^T is the DCT-III.
+W_s, IUWT form (the other choice named in Section 2.1): the isotropic
+     undecimated ("starlet") wavelet transform with J scales, coefficients
+     (L, J + 1, n, n): planes 0..J-1 the wavelet scales, plane J the coarse
+     approximation (see StarletDictionary).
 """
 from __future__ import annotations
 
@@ -147,6 +151,8 @@ def idwt2(coef: np.ndarray, h: np.ndarray, g: np.ndarray, J: int) -> np.ndarray:
 class SpatialDictionary:
     """W_s = P^{-1/2} [Psi_1; ...; Psi_P] (union of db1..dbP bases)."""
 
+    norm2 = 1.0   # ||W_s||^2: the union of orthonormal bases is a Parseval frame
+
     def __init__(self, P: int = 8, J: int = 3):
         self.P, self.J = P, J
         self.bank = daubechies_bank(P)
@@ -163,6 +169,66 @@ class SpatialDictionary:
         for p, (h, g) in enumerate(self.bank):
             acc += s * idwt2(u[:, p], h, g, self.J)
         return acc
+
+
+# --------------------------------------------------------------------------
+# W_s, IUWT form: the starlet transform
+# --------------------------------------------------------------------------
+
+B3 = np.array([1.0, 4.0, 6.0, 4.0, 1.0]) / 16.0   # cubic B-spline scaling filter
+
+
+def b3_smooth(c: np.ndarray, d: int) -> np.ndarray:
+    """Separable periodic smoothing of every band with the B3-spline filter
+    dilated by d ("a trous": taps at offsets -2d .. 2d):
+        out[i, j] = sum_{a, b} h[a] h[b] c[(i + (a-2) d) mod n, (j + (b-2) d) mod n]."""
+    rows = sum(B3[a] * np.roll(c, -(a - 2) * d, axis=-2) for a in range(5))
+    return sum(B3[b] * np.roll(rows, -(b - 2) * d, axis=-1) for b in range(5))
+
+
+class StarletDictionary:
+    """W_s as the isotropic undecimated wavelet transform with J scales
+    (the IUWT of Section 2.1): c_0 = x, c_j = h_(2^(j-1)) * c_(j-1),
+    w_j = c_(j-1) - c_j (j = 1..J); W_s x = (w_1, ..., w_J, c_J), so the
+    planes add up to x.  Not orthonormal: the adjoint is the transpose of
+    the analysis (not the sum of the planes), and ||W_s|| > 1."""
+
+    def __init__(self, J: int = 3):
+        self.J = J
+        self.P = J + 1   # planes per band
+
+    def forward(self, x: np.ndarray) -> np.ndarray:
+        """(L, n, n) -> (L, J + 1, n, n)."""
+        c = np.asarray(x, np.float64)
+        planes = []
+        for j in range(1, self.J + 1):
+            cn = b3_smooth(c, 2 ** (j - 1))
+            planes.append(c - cn)
+            c = cn
+        planes.append(c)
+        return np.stack(planes, axis=1)
+
+    def adjoint(self, u: np.ndarray) -> np.ndarray:
+        """W_s^T: (L, J + 1, n, n) -> (L, n, n).  With H_j the (symmetric)
+        smoothing of scale j, W_s^T u = sum_j C_(j-1)^T (I - H_j) u_j
+        + C_J^T u_c, C_j = H_j ... H_1, evaluated from the coarsest scale:
+        r_J = u_c, r_(j-1) = u_j + H_j (r_j - u_j), W_s^T u = r_0."""
+        r = np.asarray(u[:, self.J], np.float64)
+        for j in range(self.J, 0, -1):
+            uj = u[:, j - 1]
+            r = uj + b3_smooth(r - uj, 2 ** (j - 1))
+        return r
+
+    def frame_norm2(self, n: int) -> float:
+        """||W_s||^2 = largest eigenvalue of W_s^T W_s.  Every scale is a
+        periodic convolution, so W_s^T W_s is diagonal in the 2-D DFT: its
+        eigenvalues are sum_j |W_j(f)|^2 + |C_J(f)|^2 over the n x n
+        frequencies, with the filters' responses taken from the DFT of the
+        transform of a unit impulse."""
+        e = np.zeros((1, n, n))
+        e[0, 0, 0] = 1.0
+        resp = np.fft.fft2(self.forward(e)[0])          # (J + 1, n, n)
+        return float(np.max(np.sum(np.abs(resp) ** 2, axis=0)))
 
 
 # --------------------------------------------------------------------------

@@ -183,7 +183,8 @@ def _admm_dense(Hd, y, A, w, iters=40000, rho=1.0):
     return np.maximum(x, 0)
 
 
-def test_dense_solve_matches_objective():
+@pytest.mark.parametrize("dictionary", ["daubechies", "starlet"])
+def test_dense_solve_matches_objective(dictionary):
     rng = np.random.default_rng(7)
     L, n, P, J = 2, 4, 2, 1
     psf = _blur_psf(L, n)
@@ -193,7 +194,8 @@ def test_dense_solve_matches_objective():
     alpha = rng.uniform(0.5, 1.5, n * n)
     beta = rng.uniform(0.5, 1.5, L)
     mu, gamma = 0.3, 0.2
-    pb = mf.make_problem(Y, psf, P=P, J=J, alpha=alpha, beta=beta)
+    pb = mf.make_problem(Y, psf, P=P, J=J, alpha=alpha, beta=beta, dictionary=dictionary)
+    P = pb.Ws.P
     # dense operators, built from the defining sums (not the FFT form)
     Hd = np.zeros((L * n * n, L * n * n))
     for l in range(L):
@@ -209,7 +211,8 @@ def test_dense_solve_matches_objective():
     xs = _admm_dense(Hd, Y.ravel(), A, w)
     F_star = mf.objective(xs.reshape(L, n, n), pb, mu, gamma)
     beta_H = mf.lipschitz(pb.K, n)
-    tau = mf.tau_rule(beta_H, pb.sigma, pb.mu_l(mu), pb.gamma_n(gamma).ravel())
+    tau = mf.tau_rule(beta_H, pb.sigma, pb.mu_l(mu), pb.gamma_n(gamma).ravel(),
+                      ws_norm2=mf.ws_norm2_of(pb.Ws, n))
     X = mf.run_muffin(pb, mu, gamma, tau, 6000).X
     F = mf.objective(X, pb, mu, gamma)
     assert abs(F - F_star) <= 1e-8 * abs(F_star)
@@ -238,23 +241,27 @@ def _deriv_window(pb, Y, st0, mu, gamma, tau, steps):
     return st, dm, dg
 
 
-def _fd_problem(seed=8):
+def _fd_problem(seed=8, dictionary="daubechies"):
     import synth
     rng = np.random.default_rng(seed)
     L, n, P, J = 4, 8, 3, 2
     prob = synth.make_problem(n, L, n_src=6, n_blob=2, n_base=40, seed=seed)
     alpha, beta = synth.random_weights(L, n, seed)
-    pb = mf.make_problem(prob.dirty, prob.psf, P=P, J=J, alpha=alpha, beta=beta)
+    pb = mf.make_problem(prob.dirty, prob.psf, P=P, J=J, alpha=alpha, beta=beta,
+                         dictionary=dictionary)
+    P = pb.Ws.P
     X, U, V, T = synth.random_state(L, n, P, seed, scale=float(np.abs(prob.dirty).mean()))
     return pb, mf.State(X, U, V, T), prob
 
 
+@pytest.mark.parametrize("dictionary", ["daubechies", "starlet"])
 @pytest.mark.parametrize("which", ["mu", "gamma"])
-def test_derivative_recursions_match_finite_differences(which):
-    pb, st0, _ = _fd_problem()
+def test_derivative_recursions_match_finite_differences(which, dictionary):
+    pb, st0, _ = _fd_problem(dictionary=dictionary)
     mu, gamma = 0.8, 0.6
     beta_H = mf.lipschitz(pb.K, pb.Y.shape[1], iters=300, tol=1e-12)
-    tau = mf.tau_rule(beta_H, pb.sigma, pb.mu_l(mu), pb.gamma_n(gamma).ravel())
+    tau = mf.tau_rule(beta_H, pb.sigma, pb.mu_l(mu), pb.gamma_n(gamma).ravel(),
+                      ws_norm2=mf.ws_norm2_of(pb.Ws, pb.Y.shape[1]))
     steps = 5
     _, dm, dg = _deriv_window(pb, pb.Y, st0, mu, gamma, tau, steps)
     d = dm if which == "mu" else dg
