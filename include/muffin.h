@@ -62,6 +62,14 @@ enum { MUFFIN_F64 = 0, MUFFIN_F32 = 1, MUFFIN_F32_BF16DCT = 2 };
  * K = sum_l mu_l^2 + sum_n gamma_n^2 (PAPER_SUM). */
 enum { MUFFIN_TAU_OPNORM = 0, MUFFIN_TAU_PAPER_SUM = 1 };
 
+/* Spatial dictionaries W_s (Section 2.1 names both).  DAUBECHIES: the union
+ * of the db1..dbP bases, J levels each, scaled by 1/sqrt(P) (a Parseval
+ * frame, ||W_s|| = 1; the paper's experiments).  STARLET: the isotropic
+ * undecimated wavelet transform with J scales (B3-spline filter, a trous,
+ * periodic): J + 1 planes per band (the scales, then the coarse plane),
+ * unscaled; the step rule then uses ||W_s||^2 > 1, computed exactly. */
+enum { MUFFIN_DICT_DAUBECHIES = 0, MUFFIN_DICT_STARLET = 1 };
+
 typedef struct {
   int32_t n;            /* image side, power of two, 8 <= n <= 2048 */
   int32_t L;            /* bands, 1 <= L <= 256 */
@@ -93,6 +101,9 @@ typedef struct {
                            residual of the serving form.  0: run exactly
                            the requested iterations. */
   int32_t check_every;  /* iterations between checks of stop_rel, >= 1 */
+  int32_t dictionary;   /* MUFFIN_DICT_DAUBECHIES or MUFFIN_DICT_STARLET; with
+                           STARLET, levels = J scales (1..5) and n_bases is
+                           unused: U and the masks hold J + 1 planes per band */
 } muffin_config;
 
 typedef struct {
@@ -111,7 +122,7 @@ typedef struct {
 /* Fills *cfg with the paper's defaults for an n x n x L cube: P = 8 bases,
  * J = 3 levels (fewer when n is small), sigma = 10, Delta = 10, OPNORM rule,
  * rho = 0.99, eps_w = 1e-6, plain MUFFIN (sure = 0), mu = gamma = 1, no
- * stopping rule (stop_rel = 0, check_every = 10). */
+ * stopping rule (stop_rel = 0, check_every = 10), the Daubechies union. */
 int muffin_default_config(muffin_config* cfg, int32_t n, int32_t L);
 
 /* Device bytes the handle will hold for *cfg (admission control).  Returns 0
@@ -355,7 +366,8 @@ int muffin_unmix_plan_destroy(muffin_unmix_plan* plan);
  *   op_H:   out = H_l in_l     (eq. `model`)
  *   op_HT:  out = H_l^T in_l
  *   op_HTH: out = H_l^T H_l in_l (the data-fidelity gradient without y)
- *   op_Ws:  out[L][P][n][n] = W_s in (1/sqrt(P) scaling included)
+ *   op_Ws:  out[L][P][n][n] = W_s in (1/sqrt(P) scaling included; with the
+ *           starlet dictionary P = J + 1 planes, unscaled)
  *   op_WsT: out[L][n][n] = W_s^T in
  *   op_dct: out = W_lambda in (DCT-II along bands), op_idct: W_lambda^T in.
  * Require muffin_set_problem (for H) or only muffin_create (W_s, DCT). */

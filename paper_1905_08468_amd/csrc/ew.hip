@@ -136,8 +136,9 @@ int reduce_to_buffer(const double* partials, int count, double* out, hipStream_t
 __device__ void tau_from_rule(DevParams* dp) {
   if (dp->tau_rule < 0) return;  // fixed step
   const double mu2 = dp->mu * dp->mu, ga2 = dp->gamma * dp->gamma;
-  const double k = dp->tau_rule == 0 ? mu2 * dp->max_beta2 + ga2 * dp->max_alpha2
-                                     : mu2 * dp->sum_beta2 + ga2 * dp->sum_alpha2;
+  const double k = dp->tau_rule == 0
+                       ? dp->ws_norm2 * mu2 * dp->max_beta2 + ga2 * dp->max_alpha2
+                       : dp->ws_norm2 * mu2 * dp->sum_beta2 + ga2 * dp->sum_alpha2;
   dp->tau = dp->rho / (0.5 * dp->beta_H + dp->sigma * k);
 }
 
@@ -365,6 +366,21 @@ int weights_from(const T* x0, int L, int N, double eps, double* alpha, double* b
   MUFFIN_HIP_CHECK(hipGetLastError());
   return 0;
 }
+
+// beta_l = 1 / (||w_l|| + eps) from per-band coefficient blocks w_l of
+// `per_band` values (a redundant dictionary's analysis of the dirty cube)
+template <typename T>
+int beta_from(const T* w, int L, int per_band, double eps, double* beta, double* partials,
+              hipStream_t s) {
+  const int bpb = 64;
+  band_sq_kernel<T><<<dim3(bpb, L), kEwNT, 0, s>>>(w, per_band, partials, bpb);
+  MUFFIN_HIP_CHECK(hipGetLastError());
+  beta_kernel<<<(L + kEwNT - 1) / kEwNT, kEwNT, 0, s>>>(partials, L, bpb, eps, beta);
+  MUFFIN_HIP_CHECK(hipGetLastError());
+  return 0;
+}
+template int beta_from<double>(const double*, int, int, double, double*, double*, hipStream_t);
+template int beta_from<float>(const float*, int, int, double, double*, double*, hipStream_t);
 
 // --------------------------------------------------------- power iteration --
 __device__ __forceinline__ unsigned long long splitmix64(unsigned long long z) {

@@ -32,6 +32,7 @@ struct DevParams {
   double beta_H;             // Lipschitz constant of the least-squares gradient
   double max_beta2, sum_beta2, max_alpha2, sum_alpha2;
   double rho;
+  double ws_norm2;           // ||W_s||^2 in the step rule (1 for the Daubechies union)
   double eta_mu, eta_gamma;  // ADA-PT gradient steps
   double eps_fd, sigma_w;    // FDMC perturbation size and noise std
   int32_t tau_rule;          // 0: operator-norm form, 1: printed sum form
@@ -149,6 +150,22 @@ int dwt_synthesis(const DwtPlan<T>& p, const SynthesisIO<T>& io, const DevParams
                   hipStream_t s, int lev_lo = 0, int lev_hi = 0);
 int dwt_upload_filters(int P);  // host: derive db1..dbP, copy to device constants
 
+// ------------------------------------------------------------ starlet ----
+// W_s as the isotropic undecimated wavelet transform (J scales, J + 1
+// planes per band: the wavelet scales, then the coarse plane).  Same IO as
+// the Daubechies union; U and the masks are [L][J+1][n][n], no 1/sqrt(P)
+// scaling (the analysis step is sigma * beta_l, the synthesis beta_l W^T u);
+// tmp0/tmp1 each hold one [L][n][n] intermediate.
+struct StarletPlan {
+  int n = 0, L = 0, J = 0;
+};
+template <typename T>
+int starlet_analysis(const StarletPlan& p, const AnalysisIO<T>& io, const DevParams* dp,
+                     hipStream_t s);
+template <typename T>
+int starlet_synthesis(const StarletPlan& p, const SynthesisIO<T>& io, hipStream_t s);
+double starlet_norm2(int n, int J);  // host: ||W_s||^2 on n x n images
+
 // ---------------------------------------------------------------- DCT ----
 enum DctKind { DCT_F64 = 0, DCT_F32 = 1, DCT_BF16X3 = 2 };
 
@@ -226,6 +243,9 @@ template <typename T, typename U>
 int convert(U* out, const T* in, size_t count, hipStream_t s);
 
 // K-W: alpha_n = 1/(||x0^n|| + eps), beta_l = 1/(||x0_l|| + eps).
+template <typename T>
+int beta_from(const T* w, int L, int per_band, double eps, double* beta, double* partials,
+              hipStream_t s);
 template <typename T>
 int weights_from(const T* x0, int L, int N, double eps, double* alpha, double* beta,
                  double* partials, hipStream_t s);

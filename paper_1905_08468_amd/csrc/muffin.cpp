@@ -115,8 +115,18 @@ struct Timer {
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// U planes per band: the P bases of the Daubechies union, or the J scales
+// and the coarse plane of the starlet transform
+size_t planes_of(const muffin_config* c) {
+  return c->dictionary == MUFFIN_DICT_STARLET ? (size_t)c->levels + 1 : (size_t)c->n_bases;
+}
+
 int validate(const muffin_config* c) {
   if (!c) return MUFFIN_E_INVAL;
+  if (c->dictionary != MUFFIN_DICT_DAUBECHIES && c->dictionary != MUFFIN_DICT_STARLET)
+    return MUFFIN_E_INVAL;
+  if (c->dictionary == MUFFIN_DICT_STARLET && (c->levels < 1 || c->levels > 5))
+    return MUFFIN_E_SHAPE;
   if (!is_pow2(c->n) || c->n < 8 || c->n > 2048) return MUFFIN_E_SHAPE;
   if (c->L < 1 || c->L > 256) return MUFFIN_E_SHAPE;
   if (c->n_bases < 1 || c->n_bases > kMaxBases) return MUFFIN_E_SHAPE;
@@ -189,7 +199,7 @@ struct ImplBase {
 };
 
 size_t workspace_bytes_of(const muffin_config* c) {
-  const size_t n = c->n, L = c->L, P = c->n_bases;
+  const size_t n = c->n, L = c->L, P = planes_of(c);
   const size_t N = n * n, LN = L * N;
   const size_t es = c->mode == MUFFIN_F64 ? 8 : 4;
   const size_t nsets = c->sure ? 6 : 1;
@@ -214,6 +224,8 @@ struct Impl final : ImplBase {
   Dev dev;
   FftPlan<T> fft;
   DwtPlan<T> dwt;
+  bool star = false;  // spatial dictionary: starlet (else the Daubechies union)
+  StarletPlan spl;
   DctPlan<T> dct;
   DevParams* dp = nullptr;
   DevParams hp{};
@@ -248,8 +260,12 @@ struct Impl final : ImplBase {
   Impl(const muffin_config& c, hipStream_t s) : cfg(c), st(s) {
     n = c.n;
     L = c.L;
-    P = c.n_bases;
+    P = (int)planes_of(&c);
     J = c.levels;
+    star = c.dictionary == MUFFIN_DICT_STARLET;
+    spl.n = n;
+    spl.L = L;
+    spl.J = J;
     N = n * n;
     LN = (size_t)L * N;
     nsets = c.sure ? 6 : 1;
@@ -312,7 +328,7 @@ struct Impl final : ImplBase {
     dwt.L = L;
     dwt.P = P;
     dwt.J = J;
-    RC(dwt_upload_filters(P));
+    if (!star) RC(dwt_upload_filters(P));
     RC(dct_make_plan(dct, L, N,
                       sizeof(T) == 8 ? DCT_F64
                                      : (cfg.mode == MUFFIN_F32_BF16DCT ? DCT_BF16X3 : DCT_F32)));
@@ -445,6 +461,23 @@ struct Impl final : ImplBase {
     std::vector<double> ha(N), hb(L);
     if (!a_host || !b_host) {
       RC(weights_from(Y, L, N, cfg.eps_w, alpha, beta, partials, st));
+      if (star) {
+        // the starlet is not norm-preserving: beta_l = 1/(||W_s y_l|| + eps)
+        // from the transform of the dirty cube (U of set 0 is zeroed below)
+        AnalysisIO<T> io{};
+        io.nsets = 1;
+        io.xt_a[0] = Y;
+        io.x_a[0] = Y;
+        io.c1_sel[0] = SEL_ONE;
+        io.c2_sel[0] = SEL_ZERO;
+        io.U[0] = U[0];
+        io.tmp0[0] = tmp0(0);
+        io.tmp1[0] = tmp1(0);
+        io.pure = 1;
+        io.pure_scale = 1.0;
+        RC(starlet_analysis(spl, io, nullptr, st));
+        RC(beta_from<T>(U[0], L, (int)(P * N), cfg.eps_w, beta, partials, st));
+      }
       MUFFIN_HIP_CHECK(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * N,
                                       hipMemcpyDeviceToHost, st));
       MUFFIN_HIP_CHECK(hipMemcpyAsync(hb.data(), beta, sizeof(double) * L,
@@ -486,6 +519,7 @@ struct Impl final : ImplBase {
     hp.max_alpha2 = ma;
     hp.sum_alpha2 = sa;
     hp.rho = cfg.rho;
+    hp.ws_norm2 = star ? starlet_norm2(n, J) : 1.0;
     hp.eta_mu = cfg.eta_mu;
     hp.eta_gamma = cfg.eta_gamma;
     hp.eps_fd = cfg.eps_fd;
@@ -496,8 +530,8 @@ struct Impl final : ImplBase {
     } else {
       hp.tau_rule = cfg.tau_rule;
       const double k = cfg.tau_rule == MUFFIN_TAU_OPNORM
-                           ? cfg.mu * cfg.mu * mb + cfg.gamma * cfg.gamma * ma
-                           : cfg.mu * cfg.mu * sb + cfg.gamma * cfg.gamma * sa;
+                           ? hp.ws_norm2 * cfg.mu * cfg.mu * mb + cfg.gamma * cfg.gamma * ma
+                           : hp.ws_norm2 * cfg.mu * cfg.mu * sb + cfg.gamma * cfg.gamma * sa;
       hp.tau = cfg.rho / (0.5 * beta_H + cfg.sigma * k);
     }
     MUFFIN_HIP_CHECK(hipMemcpyAsync(dp, &hp, sizeof(hp), hipMemcpyHostToDevice, st));
@@ -555,14 +589,20 @@ struct Impl final : ImplBase {
         io.tmp0[s] = tmp0(s);
         io.tmp1[s] = tmp1(s);
       }
-      if (J >= 2) {
-        tm.begin(ST_SYN_DEEP, st);
-        RC(dwt_synthesis(dwt, io, dp, st, 2, J));
+      if (star) {
+        tm.begin(ST_SYN_L1, st);
+        RC(starlet_synthesis(spl, io, st));
+        tm.end(st);
+      } else {
+        if (J >= 2) {
+          tm.begin(ST_SYN_DEEP, st);
+          RC(dwt_synthesis(dwt, io, dp, st, 2, J));
+          tm.end(st);
+        }
+        tm.begin(ST_SYN_L1, st);
+        RC(dwt_synthesis(dwt, io, dp, st, 1, 1));
         tm.end(st);
       }
-      tm.begin(ST_SYN_L1, st);
-      RC(dwt_synthesis(dwt, io, dp, st, 1, 1));
-      tm.end(st);
     }
     // 3. primal step and its derivatives
     {
@@ -602,9 +642,9 @@ struct Impl final : ImplBase {
         io.tmp1[s] = tmp1(s);
       }
       tm.begin(ST_AN_L1_PRIMAL, st);
-      RC(dwt_analysis(dwt, io, dp, st, 1, 1));
+      RC(star ? starlet_analysis(spl, io, dp, st) : dwt_analysis(dwt, io, dp, st, 1, 1));
       tm.end(st);
-      if (J >= 2) {
+      if (J >= 2 && !star) {
         tm.begin(ST_AN_DEEP_PRIMAL, st);
         RC(dwt_analysis(dwt, io, dp, st, 2, J));
         tm.end(st);
@@ -629,9 +669,9 @@ struct Impl final : ImplBase {
           d.tmp1[i] = tmp1(s);
         }
         tm.begin(ST_AN_L1_DERIV, st);
-        RC(dwt_analysis(dwt, d, dp, st, 1, 1));
+        RC(star ? starlet_analysis(spl, d, dp, st) : dwt_analysis(dwt, d, dp, st, 1, 1));
         tm.end(st);
-        if (J >= 2) {
+        if (J >= 2 && !star) {
           tm.begin(ST_AN_DEEP_DERIV, st);
           RC(dwt_analysis(dwt, d, dp, st, 2, J));
           tm.end(st);
@@ -855,7 +895,7 @@ struct Impl final : ImplBase {
   // ---- checkpoint: header, device scalars, per set X, U, V, T, history ----
   struct StateHeader {
     char magic[8];
-    int32_t version, n, L, P, J, mode, sure, nsets, elem, k_done, n_upd, max_hist;
+    int32_t version, n, L, P, J, mode, sure, nsets, elem, k_done, n_upd, max_hist, dict, pad;
     DevParams params;
   };
   size_t state_bytes() override {
@@ -876,7 +916,8 @@ struct Impl final : ImplBase {
     if (!buf || bytes < state_bytes()) return MUFFIN_E_INVAL;
     StateHeader hd{};
     std::memcpy(hd.magic, "MUFFINST", 8);
-    hd.version = 1;
+    hd.version = 2;
+    hd.dict = cfg.dictionary;
     hd.n = n;
     hd.L = L;
     hd.P = P;
@@ -906,8 +947,9 @@ struct Impl final : ImplBase {
     if (!buf || bytes < sizeof(StateHeader)) return MUFFIN_E_INVAL;
     StateHeader hd;
     std::memcpy(&hd, buf, sizeof(hd));
-    if (std::memcmp(hd.magic, "MUFFINST", 8) != 0 || hd.version != 1) return MUFFIN_E_INVAL;
+    if (std::memcmp(hd.magic, "MUFFINST", 8) != 0 || hd.version != 2) return MUFFIN_E_INVAL;
     if (hd.n != n || hd.L != L || hd.P != P || hd.J != J || hd.mode != cfg.mode ||
+        hd.dict != cfg.dictionary ||
         hd.sure != cfg.sure || hd.nsets != nsets || hd.elem != (int)sizeof(T) ||
         hd.max_hist != max_hist)
       return MUFFIN_E_SHAPE;
@@ -1047,8 +1089,8 @@ struct Impl final : ImplBase {
         io.tmp0[0] = tmp0(0);
         io.tmp1[0] = tmp1(0);
         io.pure = 1;
-        io.pure_scale = 1.0 / std::sqrt((double)P);
-        return dwt_analysis(dwt, io, nullptr, st);
+        io.pure_scale = star ? 1.0 : 1.0 / std::sqrt((double)P);
+        return star ? starlet_analysis(spl, io, nullptr, st) : dwt_analysis(dwt, io, nullptr, st);
       }
       case 4: {
         SynthesisIO<T> io{};
@@ -1058,7 +1100,7 @@ struct Impl final : ImplBase {
         io.tmp0[0] = tmp0(0);
         io.tmp1[0] = tmp1(0);
         io.pure = 1;
-        return dwt_synthesis(dwt, io, nullptr, st);
+        return star ? starlet_synthesis(spl, io, st) : dwt_synthesis(dwt, io, nullptr, st);
       }
       case 5:
       case 6: {

@@ -41,7 +41,8 @@ bool same_config(const muffin_config& a, const muffin_config& b) {
          a.sure == b.sure && a.delta_period == b.delta_period && a.eta_mu == b.eta_mu &&
          a.eta_gamma == b.eta_gamma && a.eps_fd == b.eps_fd && a.sigma_w == b.sigma_w &&
          a.deriv_reset == b.deriv_reset && a.pi_iters == b.pi_iters && a.pi_tol == b.pi_tol &&
-         a.stop_rel == b.stop_rel && a.check_every == b.check_every;
+         a.stop_rel == b.stop_rel && a.check_every == b.check_every &&
+         a.dictionary == b.dictionary;
 }
 
 struct Request {

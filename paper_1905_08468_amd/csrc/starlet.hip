@@ -1,0 +1,315 @@
+// W_s as the isotropic undecimated wavelet transform (IUWT, "starlet"), the
+// other spatial dictionary named in Section 2.1.  With h the cubic B-spline
+// filter [1 4 6 4 1] / 16 and H_j the separable periodic smoothing by h
+// dilated by 2^(j-1) ("a trous": taps 2^(j-1) apart):
+//   analysis   c_0 = z, c_j = H_j c_(j-1), w_j = c_(j-1) - c_j (j = 1..J),
+//              W_s z = (w_1, ..., w_J, c_J)              planes [L][J+1][n][n]
+//   adjoint    r_J = u_c, r_(j-1) = u_j + H_j (r_j - u_j), W_s^T u = r_0
+// (H_j is symmetric, so the adjoint of each scale is the same smoothing).
+//
+// One launch per scale, every state set in it (blockIdx.y).  A block owns a
+// TS x TS tile: it stages the tile and a halo of 2 * 2^(j-1) samples on
+// each side in LDS (periodic wrap), filters rows then columns, and applies
+// the scale's step at its outputs.  The analysis fuses the dual update of
+// the MUFFIN iteration (the same roles as the Daubechies analysis: primal
+// step with clip and mask, derivative step under the primal's mask, or a
+// plain transform); the synthesis of scale 1 writes beta_l W_s^T u.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace muffin {
+namespace {
+
+constexpr int kStTS = 32;   // outputs per tile side
+constexpr int kStNT = 256;
+
+template <typename T>
+__device__ __forceinline__ T b3(int m) {  // h[m], m = 0..4
+  return m == 2 ? T(0.375) : (m == 1 || m == 3 ? T(0.25) : T(0.0625));
+}
+
+__device__ __forceinline__ double st_coef(int sel, const DevParams* dp) {
+  switch (sel) {
+    case SEL_ONE: return 1.0;
+    case SEL_MU: return dp->mu;
+    case SEL_GAMMA: return dp->gamma;
+    default: return 0.0;
+  }
+}
+
+template <typename T>
+struct StArgs {
+  // analysis, scale 1: z = c1 (2 xt_a - x_a) + c2 (2 xt_b - x_b)
+  const T* xt_a[kMaxSets];
+  const T* x_a[kMaxSets];
+  const T* xt_b[kMaxSets];
+  const T* x_b[kMaxSets];
+  int c1_sel[kMaxSets], c2_sel[kMaxSets];
+  // the scale's input plane: analysis c_(j-1) (scales >= 2), synthesis r_j,
+  // at in[set] + (band * in_planes + in_plane) * N
+  const T* in[kMaxSets];
+  int in_planes, in_plane;
+  T* out[kMaxSets];          // analysis c_j (j < J) / synthesis r_(j-1) or S
+  T* U[kMaxSets];            // [L][J+1][n][n]
+  uint8_t* mask[kMaxSets];   // [L][J+1][n][n]
+  const double* beta;        // [L] or null (then 1)
+  const DevParams* dp;       // null for the plain transform
+  int n, L, J, level, planes;
+  int role, pure;
+  double pure_scale;
+  int tiles, nblocks;
+};
+
+// separable smoothing of the staged tile: rows of s_in into s_row, then the
+// column at (r, c) of the output tile
+template <typename T>
+__device__ __forceinline__ void st_rows(const T* s_in, T* s_row, int W, int R, int d) {
+  for (int t = threadIdx.x; t < W * kStTS; t += kStNT) {
+    const int r = t / kStTS, c = t - r * kStTS;
+    const T* p = s_in + r * W + c + R;
+    T acc = T(0);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) acc = fma(b3<T>(m), p[(m - 2) * d], acc);
+    s_row[t] = acc;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T st_col(const T* s_row, int r, int c, int R, int d) {
+  const T* p = s_row + (r + R) * kStTS + c;
+  T acc = T(0);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) acc = fma(b3<T>(m), p[(m - 2) * d * kStTS], acc);
+  return acc;
+}
+
+// analysis scale `level` with the fused dual update of planes level-1 (and J)
+template <typename T>
+__global__ void __launch_bounds__(kStNT) st_an(StArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char st_smem[];
+  T* s_in = reinterpret_cast<T*>(st_smem);
+  const int d = 1 << (a.level - 1), R = 2 * d, W = kStTS + 2 * R;
+  T* s_row = s_in + W * W;
+  const int lb = blockIdx.x;
+  if (lb >= a.nblocks) return;
+  const int tiles2 = a.tiles * a.tiles;
+  const int band = lb / tiles2, tile = lb - band * tiles2;
+  const int i0 = (tile / a.tiles) * kStTS, j0 = (tile % a.tiles) * kStTS;
+  const int set = blockIdx.y, n = a.n, msk = n - 1;
+  const size_t N = (size_t)n * n;
+  const size_t boff = (size_t)band * N;
+  if (a.level == 1) {
+    const double c1 = st_coef(a.c1_sel[set], a.dp), c2 = st_coef(a.c2_sel[set], a.dp);
+    const T* xa = a.x_a[set] + boff;
+    const T* ta = a.xt_a[set] + boff;
+    const bool has_b = a.x_b[set] != nullptr;
+    const T* xb = has_b ? a.x_b[set] + boff : xa;
+    const T* tb = has_b ? a.xt_b[set] + boff : ta;
+    for (int t = threadIdx.x; t < W * W; t += kStNT) {
+      const int r = t / W, c = t - r * W;
+      const size_t g = (size_t)((i0 - R + r) & msk) * n + ((j0 - R + c) & msk);
+      T z = T(c1) * (T(2) * ta[g] - xa[g]);
+      if (has_b) z += T(c2) * (T(2) * tb[g] - xb[g]);
+      s_in[t] = z;
+    }
+  } else {
+    const T* src = a.in[set] + ((size_t)band * a.in_planes + a.in_plane) * N;
+    for (int t = threadIdx.x; t < W * W; t += kStNT) {
+      const int r = t / W, c = t - r * W;
+      s_in[t] = src[(size_t)((i0 - R + r) & msk) * n + ((j0 - R + c) & msk)];
+    }
+  }
+  lds_barrier();
+  st_rows(s_in, s_row, W, R, d);
+  lds_barrier();
+  const double beta = a.beta ? a.beta[band] : 1.0;
+  const T scale = T(a.dp ? a.dp->sigma * beta : 0.0);
+  const bool mask_out = a.role == ROLE_PRIMAL && a.mask[set] != nullptr && !a.pure;
+  const bool mask_in = a.role == ROLE_DERIV && a.mask[set] != nullptr;
+  T* U = a.U[set];
+  uint8_t* M = a.mask[set];
+  auto update = [&](int plane, size_t pix, T val) {
+    const size_t idx = ((size_t)band * a.planes + plane) * N + pix;
+    if (a.pure) {
+      U[idx] = T(a.pure_scale) * val;
+      return;
+    }
+    const T pv = U[idx] + scale * val;
+    if (a.role == ROLE_PRIMAL) {
+      U[idx] = pv < T(-1) ? T(-1) : (pv > T(1) ? T(1) : pv);
+      if (mask_out) M[idx] = (pv >= T(-1) && pv <= T(1)) ? 1 : 0;
+    } else {
+      U[idx] = (mask_in && M[idx]) ? pv : T(0);
+    }
+  };
+  const bool last = a.level == a.J;
+  for (int t = threadIdx.x; t < kStTS * kStTS; t += kStNT) {
+    const int r = t / kStTS, c = t - r * kStTS;
+    const int gi = i0 + r, gj = j0 + c;
+    if (gi >= n || gj >= n) continue;
+    const T cj = st_col(s_row, r, c, R, d);
+    const T z0 = s_in[(r + R) * W + c + R];
+    const size_t pix = (size_t)gi * n + gj;
+    update(a.level - 1, pix, z0 - cj);  // w_j
+    if (last)
+      update(a.J, pix, cj);             // the coarse plane c_J
+    else
+      a.out[set][boff + pix] = cj;      // c_j for the next scale
+  }
+}
+
+// synthesis scale `level`: r_(level-1) = u_level + H (r_level - u_level)
+template <typename T>
+__global__ void __launch_bounds__(kStNT) st_sy(StArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char st_smem[];
+  T* s_in = reinterpret_cast<T*>(st_smem);
+  const int d = 1 << (a.level - 1), R = 2 * d, W = kStTS + 2 * R;
+  T* s_row = s_in + W * W;
+  const int lb = blockIdx.x;
+  if (lb >= a.nblocks) return;
+  const int tiles2 = a.tiles * a.tiles;
+  const int band = lb / tiles2, tile = lb - band * tiles2;
+  const int i0 = (tile / a.tiles) * kStTS, j0 = (tile % a.tiles) * kStTS;
+  const int set = blockIdx.y, n = a.n, msk = n - 1;
+  const size_t N = (size_t)n * n;
+  const T* rin = a.in[set] + ((size_t)band * a.in_planes + a.in_plane) * N;
+  const T* u = a.U[set] + ((size_t)band * a.planes + (a.level - 1)) * N;
+  for (int t = threadIdx.x; t < W * W; t += kStNT) {
+    const int r = t / W, c = t - r * W;
+    const size_t g = (size_t)((i0 - R + r) & msk) * n + ((j0 - R + c) & msk);
+    s_in[t] = rin[g] - u[g];
+  }
+  lds_barrier();
+  st_rows(s_in, s_row, W, R, d);
+  lds_barrier();
+  const T sc = T(a.level == 1 && a.beta ? a.beta[band] : 1.0);
+  T* out = a.out[set] + (size_t)band * N;
+  for (int t = threadIdx.x; t < kStTS * kStTS; t += kStNT) {
+    const int r = t / kStTS, c = t - r * kStTS;
+    const int gi = i0 + r, gj = j0 + c;
+    if (gi >= n || gj >= n) continue;
+    const size_t pix = (size_t)gi * n + gj;
+    out[pix] = sc * (u[pix] + st_col(s_row, r, c, R, d));
+  }
+}
+
+template <typename T>
+size_t st_lds_bytes(int level) {
+  const int R = 2 << (level - 1), W = kStTS + 2 * R;
+  return sizeof(T) * ((size_t)W * W + (size_t)W * kStTS);
+}
+
+template <typename T>
+int st_prepare(StArgs<T>& a, const StarletPlan& p, int level) {
+  a.n = p.n;
+  a.L = p.L;
+  a.J = p.J;
+  a.level = level;
+  a.planes = p.J + 1;
+  a.tiles = (p.n + kStTS - 1) / kStTS;
+  a.nblocks = a.tiles * a.tiles * p.L;
+  return 0;
+}
+
+}  // namespace
+
+double starlet_norm2(int n, int J) {
+  // W_s^T W_s is diagonal in the 2-D DFT; its eigenvalue at (kx, ky) is
+  // sum_j |C_(j-1) - C_j|^2 + |C_J|^2 with C_j the product of the scales'
+  // (real, separable) filter responses.
+  std::vector<std::vector<double>> g(J, std::vector<double>(n));
+  const double tw = 2.0 * M_PI / n;
+  for (int j = 0; j < J; ++j) {
+    const int d = 1 << j;
+    for (int k = 0; k < n; ++k) {
+      const double w = tw * k * d;
+      g[j][k] = (6.0 + 8.0 * std::cos(w) + 2.0 * std::cos(2.0 * w)) / 16.0;
+    }
+  }
+  double best = 0.0;
+  for (int kx = 0; kx < n; ++kx)
+    for (int ky = 0; ky < n; ++ky) {
+      double c = 1.0, s = 0.0;
+      for (int j = 0; j < J; ++j) {
+        const double cn = c * g[j][kx] * g[j][ky];
+        s += (c - cn) * (c - cn);
+        c = cn;
+      }
+      s += c * c;
+      best = std::max(best, s);
+    }
+  return best;
+}
+
+template <typename T>
+int starlet_analysis(const StarletPlan& p, const AnalysisIO<T>& io, const DevParams* dp,
+                     hipStream_t s) {
+  for (int lev = 1; lev <= p.J; ++lev) {
+    StArgs<T> a{};
+    st_prepare(a, p, lev);
+    for (int i = 0; i < io.nsets; ++i) {
+      a.xt_a[i] = io.xt_a[i];
+      a.x_a[i] = io.x_a[i];
+      a.xt_b[i] = io.xt_b[i];
+      a.x_b[i] = io.x_b[i];
+      a.c1_sel[i] = io.c1_sel[i];
+      a.c2_sel[i] = io.c2_sel[i];
+      a.U[i] = io.U[i];
+      a.mask[i] = io.mask[i];
+      // c_j lives in tmp0 for odd j, tmp1 for even j
+      a.in[i] = lev >= 2 ? ((lev - 1) % 2 == 1 ? io.tmp0[i] : io.tmp1[i]) : nullptr;
+      a.out[i] = lev < p.J ? (lev % 2 == 1 ? io.tmp0[i] : io.tmp1[i]) : nullptr;
+    }
+    a.in_planes = 1;
+    a.in_plane = 0;
+    a.beta = io.beta;
+    a.dp = dp;
+    a.role = io.role;
+    a.pure = io.pure;
+    a.pure_scale = io.pure_scale;
+    const size_t shm = st_lds_bytes<T>(lev);
+    MUFFIN_ALLOW_BIG_LDS((st_an<T>));
+    st_an<T><<<dim3(a.nblocks, io.nsets), kStNT, shm, s>>>(a);
+    MUFFIN_HIP_CHECK(hipGetLastError());
+  }
+  return 0;
+}
+
+template <typename T>
+int starlet_synthesis(const StarletPlan& p, const SynthesisIO<T>& io, hipStream_t s) {
+  for (int lev = p.J; lev >= 1; --lev) {
+    StArgs<T> a{};
+    st_prepare(a, p, lev);
+    for (int i = 0; i < io.nsets; ++i) {
+      a.U[i] = const_cast<T*>(io.Ua[i]);
+      // r_j (j < J) lives in tmp0 for odd j, tmp1 for even j; r_J is the
+      // coarse plane of U
+      a.in[i] = lev == p.J ? io.Ua[i] : (lev % 2 == 1 ? io.tmp0[i] : io.tmp1[i]);
+      a.out[i] = lev == 1 ? io.S[i] : ((lev - 1) % 2 == 1 ? io.tmp0[i] : io.tmp1[i]);
+    }
+    a.in_planes = lev == p.J ? p.J + 1 : 1;
+    a.in_plane = lev == p.J ? p.J : 0;
+    a.beta = io.beta;
+    const size_t shm = st_lds_bytes<T>(lev);
+    MUFFIN_ALLOW_BIG_LDS((st_sy<T>));
+    st_sy<T><<<dim3(a.nblocks, io.nsets), kStNT, shm, s>>>(a);
+    MUFFIN_HIP_CHECK(hipGetLastError());
+  }
+  return 0;
+}
+
+template int starlet_analysis<double>(const StarletPlan&, const AnalysisIO<double>&,
+                                      const DevParams*, hipStream_t);
+template int starlet_analysis<float>(const StarletPlan&, const AnalysisIO<float>&,
+                                     const DevParams*, hipStream_t);
+template int starlet_synthesis<double>(const StarletPlan&, const SynthesisIO<double>&,
+                                       hipStream_t);
+template int starlet_synthesis<float>(const StarletPlan&, const SynthesisIO<float>&,
+                                      hipStream_t);
+
+}  // namespace muffin

@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("MUFFIN_LIB", os.path.join(_HERE, "libmuffin.so"))
 
 F64, F32, F32_BF16DCT = 0, 1, 2
 TAU_OPNORM, TAU_PAPER_SUM = 0, 1
+DICT_DAUBECHIES, DICT_STARLET = 0, 1
 
 ERRORS = {0: "ok", -1: "E_INVAL", -2: "E_SHAPE", -3: "E_NOMEM", -4: "E_NONFINITE",
           -5: "E_HIP", -6: "E_STATE", -7: "E_BUSY"}
@@ -41,6 +42,7 @@ class Config(C.Structure):
         ("eps_fd", C.c_double), ("sigma_w", C.c_double),
         ("deriv_reset", C.c_int32), ("pi_iters", C.c_int32), ("pi_tol", C.c_double),
         ("stop_rel", C.c_double), ("check_every", C.c_int32),
+        ("dictionary", C.c_int32),
     ]
 
 
@@ -277,8 +279,15 @@ class Muffin:
         self._settle()
         return out
 
+    @property
+    def planes(self):
+        """U planes per band: the bases of the Daubechies union, or the J
+        scales and the coarse plane of the starlet."""
+        c = self.cfg
+        return c.levels + 1 if c.dictionary == DICT_STARLET else c.n_bases
+
     def _state_shape(self, which):
-        n, L, P = self.cfg.n, self.cfg.L, self.cfg.n_bases
+        n, L, P = self.cfg.n, self.cfg.L, self.planes
         return (L, P, n, n) if which == 1 else (L, n, n)
 
     def get_state(self, which: int, set_: int = 0):
@@ -324,7 +333,7 @@ class Muffin:
         return a, b
 
     def op(self, name: str, x):
-        n, L, P = self.cfg.n, self.cfg.L, self.cfg.n_bases
+        n, L, P = self.cfg.n, self.cfg.L, self.planes
         fn = getattr(_lib, f"muffin_op_{name}")
         if name == "WsT":
             self._check(x, (L, P, n, n), "in")
