@@ -104,6 +104,7 @@ def parse():
                     help="record the multi-start curves every this many iterations "
                          "(over --ms-iters iterations) instead of timing")
     ap.add_argument("--no-unmix", action="store_true")
+    ap.add_argument("--no-starlet", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-rate", type=float, default=20.0)
@@ -424,13 +425,14 @@ def accuracy_form(mm, torch, synth, prob_c2, iters_plain=20, iters_adapt=40):
     return out
 
 
-def run_form(mm, torch, prob, mode, sure, steps, warmup, Delta=10):
+def run_form(mm, torch, prob, mode, sure, steps, warmup, Delta=10, dictionary=0):
     n, L = prob.n, prob.L
     dt = torch.float64 if mode == mm.F64 else torch.float32
     eps = 0.01 * prob.sigma_w
     cfg = mm.default_config(n, L, mode=mode, mu=1.0, gamma=1.0, sure=1 if sure else 0,
                             delta_period=Delta, eps_fd=eps, sigma_w=prob.sigma_w,
-                            eta_mu=1e-6, eta_gamma=1e-6, pi_iters=50, pi_tol=1e-6)
+                            eta_mu=1e-6, eta_gamma=1e-6, pi_iters=50, pi_tol=1e-6,
+                            dictionary=dictionary)
     h = mm.Muffin(cfg)
     dirty = torch.from_numpy(prob.dirty).to("cuda:0", dt)
     psf = torch.from_numpy(prob.psf).to("cuda:0", dt)
@@ -564,6 +566,19 @@ def main():
                 f"x{batch['speedup_vs_one_after_another']} vs one after another")
         except Exception as e:  # report, do not hide
             batch = {"error": str(e)}
+    starlet = None
+    if not args.no_starlet:
+        try:
+            k_st = max(3, args.steps // 4)
+            f = run_form(mm, torch, prob, mode, True, k_st, 1, dictionary=mm.DICT_STARLET)
+            st_stages = {k: round(ms / k_st, 3) for k, (ms, calls) in f["timing"].items() if calls}
+            starlet = {"form": f"ADA-PT with the IUWT (starlet, J=3) spatial dictionary, same "
+                               f"cube and precision form", "value": round(k_st / f["elapsed"], 4),
+                       "unit": "iters/s", "ms_per_step": round(1e3 * f["elapsed"] / k_st, 2),
+                       "stages_ms_per_step": st_stages}
+            log(f"[bench] starlet ADA-PT: {starlet['value']} it/s")
+        except Exception as e:  # report, do not hide
+            starlet = {"error": str(e)}
     unmix = None
     if not args.no_unmix and args.workload == "c2":
         try:
@@ -623,6 +638,7 @@ def main():
         "batch": batch,
         "multistart": multistart,
         "unmix": unmix,
+        "starlet": starlet,
         "serve": serve,
         "cpu_baseline": cpu,
     }
