@@ -320,6 +320,40 @@ def test_full_side_operators(mode):
     h.close()
 
 
+@pytest.mark.parametrize("mode", ["f64", "f32"])
+def test_max_side_operators(mode):
+    """n = 2048, the largest image side (4096-point column transforms, the
+    generic FFT path), one band, element by element against the oracle;
+    the starlet dictionary at the same side."""
+    mm = _mm()
+    torch = _torch()
+    n, L = 2048, 1
+    m = mm.F64 if mode == "f64" else mm.F32
+    dt = torch.float64 if mode == "f64" else torch.float32
+    tol = 1e-12 if mode == "f64" else 3e-6
+    rng = np.random.default_rng(202)
+    prob = synth.make_problem(n, L, n_src=300, n_blob=10, n_base=20000, seed=202)
+    x = np.abs(rng.standard_normal((L, n, n)))
+    h = mm.Muffin(mm.default_config(n, L, mode=m, tau=1.0, pi_iters=0))
+    h.set_problem(dev(prob.dirty, dt), dev(prob.psf, dt), np.ones(n * n), np.ones(L))
+    xd = dev(x, dt)
+    xr = host(xd)
+    K = op.psf_spectrum(host(dev(prob.psf, dt)))
+    assert rel(host(h.op("HTH", xd)), op.HT(op.H(xr, K), K)) < tol
+    W = op.SpatialDictionary(8, 3)
+    u = h.op("Ws", xd)
+    assert rel(host(u), W.forward(xr)) < tol
+    assert rel(host(h.op("WsT", u)), W.adjoint(host(u))) < tol
+    h.close()
+    hs = mm.Muffin(mm.default_config(n, L, mode=m, tau=1.0, pi_iters=0,
+                                     dictionary=mm.DICT_STARLET, levels=3))
+    Ws = op.StarletDictionary(3)
+    us = hs.op("Ws", xd)
+    assert rel(host(us), Ws.forward(xr)) < tol
+    assert rel(host(hs.op("WsT", us)), Ws.adjoint(host(us))) < tol
+    hs.close()
+
+
 def test_full_cube_dct_sampled_f32():
     """1024^2 pixels x 256 bands (the benchmark's DCT configuration); sampled
     pixel spectra against the oracle's DCT."""
