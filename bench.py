@@ -156,6 +156,7 @@ def batch_form(mm, torch, synth, n_cubes, chunks, seed=7):
         inputs[(n, L)] = _class_inputs(synth, torch, n, L, 1000 + n + L, torch.float32)
     torch.cuda.synchronize()
     hs = []
+    tuned = {}
     t0 = time.perf_counter()
     for n, L in sizes:
         p, d, ps, dl = inputs[(n, L)]
@@ -163,6 +164,9 @@ def batch_form(mm, torch, synth, n_cubes, chunks, seed=7):
                                 eps_fd=0.01 * p.sigma_w, sigma_w=p.sigma_w, eta_mu=1e-6,
                                 eta_gamma=1e-6, pi_iters=30, pi_tol=1e-4)
         h = mm.Muffin(cfg, stream=torch.cuda.Stream())
+        # tile shapes per size class (timed once per class, then recorded)
+        r = h.autotune(3)
+        tuned[f"{n}x{L}"] = [r["syn_tile1"], r["an_tile1"]]
         h.set_problem(d, ps, None, None, dl)
         hs.append(h)
     setup_s = time.perf_counter() - t0
@@ -192,7 +196,8 @@ def batch_form(mm, torch, synth, n_cubes, chunks, seed=7):
             "voxel_updates_per_s": round(vox * iters / tb, 1),
             "ms_per_chunk": round(1e3 * tb / chunks, 2),
             "one_after_another_cube_iters_per_s": round(n_cubes * iters / ts, 2),
-            "speedup_vs_one_after_another": round(ts / tb, 3), "setup_s": round(setup_s, 2)}
+            "speedup_vs_one_after_another": round(ts / tb, 3), "setup_s": round(setup_s, 2),
+            "tile_shapes": tuned}
 
 
 def multistart_form(mm, torch, synth, iters, seed=0, eta_mu=5e-3, eta_gamma=1e-3,

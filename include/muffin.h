@@ -361,6 +361,30 @@ int muffin_unmix_run(const muffin_unmix_plan* plan, const void* cube, int32_t n,
                      void* abund, void* resid, void* stream);
 int muffin_unmix_plan_destroy(muffin_unmix_plan* plan);
 
+/* ---- autotuner: wavelet tile shapes per size class ----
+ * The FP32 level-1 wavelet kernels of the Daubechies union come in two tile
+ * shapes, 16 x 16 and 32 x 32 (coefficients per subband side); both give
+ * bit-identical results, their speed depends on the cube's size and the
+ * number of state sets.  muffin_autotune times both shapes of the level-1
+ * synthesis and analysis launches (as the iteration issues them, `reps`
+ * launches each after a warm-up) on the handle's own buffers, keeps the
+ * faster shape for the handle, and records it for the size class
+ * (n, L, P, mode precision, state sets) in a process-wide table: a later
+ * handle of the same class takes the recorded shapes without timing
+ * (cached = 1).  Call between muffin_create and muffin_set_problem
+ * (E_STATE otherwise: the timing overwrites the state buffers).
+ * Synchronises the stream.  Without it the built-in rule applies (32 x 32
+ * when the subband side is at least 64). */
+typedef struct {
+  int32_t tunable;     /* 0: one shape only (FP64, the starlet, or P != 8) */
+  int32_t cached;      /* 1: shapes taken from an earlier tuning of the class */
+  int32_t syn_tile1;   /* level-1 synthesis tile side in use (16 or 32) */
+  int32_t an_tile1;    /* level-1 analysis tile side in use (16 or 32) */
+  double syn_ms[2];    /* measured ms per launch with tiles 16 and 32 (0: not timed) */
+  double an_ms[2];
+} muffin_tune_result;
+int muffin_autotune(muffin_handle* h, int32_t reps, muffin_tune_result* out);
+
 /* ---- operator entry points (same kernels as the iteration) ----
  * in/out are device cubes of the handle's working type.
  *   op_H:   out = H_l in_l     (eq. `model`)

@@ -832,7 +832,8 @@ int dwt_analysis(const DwtPlan<T>& p, const AnalysisIO<T>& io, const DevParams* 
     // tiles per subband (input halo re-reads (64 + 14)^2 / 64^2 = 1.49x
     // instead of (32 + 14)^2 / 32^2 = 2.07x)
     constexpr bool big = sizeof(T) == 4;
-    const bool wide = big && half >= 64 && p.P == 8;
+    const bool wide = big && p.P == 8 &&
+                      (lev == 1 && p.an_tile1 ? p.an_tile1 == kAnTO1 : half >= 64);
     const int to = wide ? kAnTO1 : kTO;
     a.tiles = (half + to - 1) / to;
     a.nblocks = a.tiles * a.tiles * p.L;
@@ -890,7 +891,7 @@ int dwt_synthesis(const DwtPlan<T>& p, const SynthesisIO<T>& io, const DevParams
     // (23^2 / 16^2 = 2.07x); FP64 (twice the LDS per tile) and the coarser
     // levels keep 16 x 16 (measured: no gain there)
     constexpr bool big = sizeof(T) == 4;
-    const bool wide = big && lev == 1 && half >= 64;
+    const bool wide = big && lev == 1 && (p.syn_tile1 ? p.syn_tile1 == kSyTC1 : half >= 64);
     const int tc = wide ? kSyTC1 : kTO;
     a.tiles = (half + tc - 1) / tc;
     a.nblocks = a.tiles * a.tiles * p.L;

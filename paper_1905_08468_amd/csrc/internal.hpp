@@ -98,6 +98,9 @@ int fft_res_blocks(int n, int L, int elem_bytes);
 template <typename T>
 struct DwtPlan {
   int n = 0, L = 0, P = 0, J = 0;
+  // level-1 tile side of the FP32 kernels: 0 = built-in rule (32 when the
+  // subband side is >= 64), 16 or 32 = forced (the autotuner's choice)
+  int syn_tile1 = 0, an_tile1 = 0;
 };
 
 // Dual-update roles.

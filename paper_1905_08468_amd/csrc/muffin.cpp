@@ -23,6 +23,9 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <memory>
 #include <new>
 #include <numeric>
@@ -196,6 +199,7 @@ struct ImplBase {
   virtual hipStream_t stream() = 0;
   virtual int quality(const void* truth, double* snr_db, double* wmse) = 0;
   virtual void preset_beta_H(double v) = 0;
+  virtual int autotune(int reps, muffin_tune_result* r) = 0;
 };
 
 size_t workspace_bytes_of(const muffin_config* c) {
@@ -212,6 +216,17 @@ size_t workspace_bytes_of(const muffin_config* c) {
   shared += (N + L) * 8 + 4096 * 8 + 64 * 1024;                  // weights, partials, params
   if (c->stop_rel > 0) shared += (P + 1) * LN * es;              // U, V snapshots (stop rule)
   return nsets * per_set + shared;
+}
+
+// Level-1 tile shapes chosen by muffin_autotune, per size class
+// (n, L, P, element size, state sets).
+struct TuneTable {
+  std::mutex mu;
+  std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> shapes;
+};
+TuneTable& tune_table() {
+  static TuneTable t;
+  return t;
 }
 
 template <typename T>
@@ -1038,6 +1053,132 @@ struct Impl final : ImplBase {
 
   void preset_beta_H(double v) override { preset_bH = v; }
 
+  // Level-1 launches as the iteration issues them (synthesis of every set;
+  // analysis of the primal sets, then of the derivative sets), with the
+  // state buffers as operands: the values do not matter for the timing.
+  int tune_synthesis() {
+    SynthesisIO<T> io{};
+    io.nsets = nsets;
+    io.beta = beta;
+    for (int s = 0; s < nsets; ++s) {
+      io.Ua[s] = U[s];
+      io.S[s] = S[s];
+      io.tmp0[s] = tmp0(s);
+      io.tmp1[s] = tmp1(s);
+    }
+    return dwt_synthesis(dwt, io, dp, st, 1, 1);
+  }
+  int tune_analysis() {
+    const bool sure = cfg.sure != 0;
+    AnalysisIO<T> io{};
+    io.role = ROLE_PRIMAL;
+    io.nsets = sure ? 2 : 1;
+    io.beta = beta;
+    for (int s = 0; s < io.nsets; ++s) {
+      io.xt_a[s] = Xt[s];
+      io.x_a[s] = X[s];
+      io.c1_sel[s] = SEL_MU;
+      io.c2_sel[s] = SEL_ZERO;
+      io.U[s] = U[s];
+      io.mask[s] = sure ? maskU[s] : nullptr;
+      io.tmp0[s] = tmp0(s);
+      io.tmp1[s] = tmp1(s);
+    }
+    RC(dwt_analysis(dwt, io, dp, st, 1, 1));
+    if (!sure) return 0;
+    AnalysisIO<T> d{};
+    d.role = ROLE_DERIV;
+    d.nsets = 4;
+    d.beta = beta;
+    for (int i = 0; i < 4; ++i) {
+      const int s = 2 + i, prim = i < 2 ? 0 : 1;
+      d.xt_a[i] = Xt[s];
+      d.x_a[i] = X[s];
+      d.c1_sel[i] = SEL_MU;
+      d.xt_b[i] = (i % 2) == 0 ? Xt[prim] : nullptr;
+      d.x_b[i] = (i % 2) == 0 ? X[prim] : nullptr;
+      d.c2_sel[i] = (i % 2) == 0 ? SEL_ONE : SEL_ZERO;
+      d.U[i] = U[s];
+      d.mask[i] = maskU[prim];
+      d.tmp0[i] = tmp0(s);
+      d.tmp1[i] = tmp1(s);
+    }
+    return dwt_analysis(dwt, d, dp, st, 1, 1);
+  }
+
+  int autotune(int reps, muffin_tune_result* r) override {
+    if (have_problem) return MUFFIN_E_STATE;
+    *r = muffin_tune_result{};
+    const bool can_syn = sizeof(T) == 4 && !star;
+    const bool can_an = can_syn && P == 8;
+    auto in_use = [&](int forced, int side) { return forced ? forced : (side >= 64 ? 32 : 16); };
+    r->tunable = can_syn ? 1 : 0;
+    if (!can_syn) {
+      r->syn_tile1 = r->an_tile1 = 16;
+      return 0;
+    }
+    const auto key = std::make_tuple(n, L, P, (int)sizeof(T), nsets);
+    {
+      std::lock_guard<std::mutex> lk(tune_table().mu);
+      auto it = tune_table().shapes.find(key);
+      if (it != tune_table().shapes.end()) {
+        dwt.syn_tile1 = it->second.first;
+        dwt.an_tile1 = it->second.second;
+        r->cached = 1;
+        r->syn_tile1 = dwt.syn_tile1;
+        r->an_tile1 = can_an ? dwt.an_tile1 : 16;
+        return 0;
+      }
+    }
+    // defined operands (the buffers are uninitialised before set_problem)
+    for (int s = 0; s < nsets; ++s) {
+      RC(fill_zero(X[s], LN, st));
+      RC(fill_zero(Xt[s], LN, st));
+      RC(fill_zero(U[s], LN * P, st));
+    }
+    RC(fill_zero(beta, (size_t)L, st));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    MUFFIN_HIP_CHECK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return MUFFIN_E_HIP;
+    }
+    auto time_it = [&](auto launch, double* ms) -> int {
+      RC(launch());  // warm-up (also loads the kernel)
+      if (hipEventRecord(e0, st) != hipSuccess) return MUFFIN_E_HIP;
+      for (int i = 0; i < reps; ++i) RC(launch());
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+        return MUFFIN_E_HIP;
+      float f = 0.f;
+      if (hipEventElapsedTime(&f, e0, e1) != hipSuccess) return MUFFIN_E_HIP;
+      *ms = f / reps;
+      return 0;
+    };
+    int rc = 0;
+    const int tiles[2] = {16, 32};
+    for (int v = 0; v < 2 && !rc; ++v) {
+      dwt.syn_tile1 = tiles[v];
+      rc = time_it([&] { return tune_synthesis(); }, &r->syn_ms[v]);
+    }
+    for (int v = 0; v < 2 && !rc && can_an; ++v) {
+      dwt.an_tile1 = tiles[v];
+      rc = time_it([&] { return tune_analysis(); }, &r->an_ms[v]);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+      dwt.syn_tile1 = dwt.an_tile1 = 0;
+      return rc;
+    }
+    dwt.syn_tile1 = r->syn_ms[1] < r->syn_ms[0] ? 32 : 16;
+    dwt.an_tile1 = can_an ? (r->an_ms[1] < r->an_ms[0] ? 32 : 16) : 0;
+    r->syn_tile1 = dwt.syn_tile1;
+    r->an_tile1 = can_an ? dwt.an_tile1 : in_use(0, 0);
+    std::lock_guard<std::mutex> lk(tune_table().mu);
+    tune_table().shapes[key] = {dwt.syn_tile1, dwt.an_tile1};
+    return 0;
+  }
+
   // Quality against a known sky (Section 4.1): SNR = 10 log10(|x*|^2 /
   // |x* - X|^2) and WMSE = |H (x* - X)|^2 / (N L), FP64 sums.  G and S of
   // the primal set are rebuilt at the start of every iteration, so between
@@ -1343,6 +1484,11 @@ int muffin_get_weights(muffin_handle* h, double* alpha, double* beta) {
 int muffin_get_report(muffin_handle* h, muffin_report* report) {
   if (!h || !report) return MUFFIN_E_INVAL;
   return h->impl->report(report);
+}
+
+int muffin_autotune(muffin_handle* h, int32_t reps, muffin_tune_result* out) {
+  if (!h || !out || reps < 1) return MUFFIN_E_INVAL;
+  return h->impl->autotune(reps, out);
 }
 
 int muffin_quality(muffin_handle* h, const void* truth, double* snr_db, double* wmse) {

@@ -59,6 +59,16 @@ class Report(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("tunable", C.c_int32), ("cached", C.c_int32), ("syn_tile1", C.c_int32),
+                ("an_tile1", C.c_int32), ("syn_ms", C.c_double * 2), ("an_ms", C.c_double * 2)]
+
+    def as_dict(self):
+        return {"tunable": self.tunable, "cached": self.cached, "syn_tile1": self.syn_tile1,
+                "an_tile1": self.an_tile1, "syn_ms": list(self.syn_ms),
+                "an_ms": list(self.an_ms)}
+
+
 class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int32),
                 ("max_queue", C.c_int32), ("chunk", C.c_int32)]
@@ -90,6 +100,7 @@ EXPORTS = [
     "muffin_multistart_run", "muffin_multistart_quality", "muffin_multistart_handle",
     "muffin_multistart_destroy",
     "muffin_unmix_plan_create", "muffin_unmix_run", "muffin_unmix_plan_destroy",
+    "muffin_autotune",
 ]
 
 
@@ -145,6 +156,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "muffin_unmix_plan_create": ([C.POINTER(vp), dp, i32, i32], C.c_int),
         "muffin_unmix_run": ([vp, vp, i32, i32, vp, vp, vp], C.c_int),
         "muffin_unmix_plan_destroy": ([vp], C.c_int),
+        "muffin_autotune": ([vp, i32, C.POINTER(TuneResult)], C.c_int),
     }
     for name in ["muffin_op_H", "muffin_op_HT", "muffin_op_HTH", "muffin_op_Ws",
                  "muffin_op_WsT", "muffin_op_dct", "muffin_op_idct"]:
@@ -212,6 +224,15 @@ class Muffin:
     @property
     def cube(self):
         return (self.cfg.L, self.cfg.n, self.cfg.n)
+
+    def autotune(self, reps: int = 3):
+        """Level-1 wavelet tile shapes for this size class (muffin_autotune);
+        call before set_problem."""
+        r = TuneResult()
+        rc = _lib.muffin_autotune(self.h, int(reps), C.byref(r))
+        if rc:
+            raise MuffinError(rc, "muffin_autotune")
+        return r.as_dict()
 
     def set_problem(self, dirty, psf, alpha=None, beta=None, delta=None):
         n, L = self.cfg.n, self.cfg.L
