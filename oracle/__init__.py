@@ -18,6 +18,8 @@ muffin      weights, step sizes, power iteration, one MUFFIN iteration
             (Algs. 1-2), the derivative recursions (Algs. 3-4), PSURE-FDMC,
             SUGAR-FDMC and the ADA-PT loop (Alg. 5), the objective, the
             quality measures SNR and WMSE (Section 4.1).
+visibility  the visibility-domain direct operator (exact Fourier sums at the
+            bands' sample positions), its adjoint and point spread function.
 unmix       per-pixel positivity-constrained least squares against chosen
             endmember spectra (the unmixing step of Section 4.3).
 
@@ -26,4 +28,4 @@ result no independent pin checks are marked "parity unpinned" in their
 docstring.
 """
 from .daubechies import daubechies_lowpass, daubechies_bank  # noqa: F401
-from . import operators, muffin, unmix  # noqa: F401
+from . import operators, muffin, unmix, visibility  # noqa: F401

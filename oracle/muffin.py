@@ -20,6 +20,8 @@ Paper passages followed (arXiv 1905.08468):
                      (operators.StarletDictionary); the step rule carries
                      ||W_s||^2 of the condition of Section 2.2
   SNR, WMSE          Section 4.1, the two point estimates of quality
+  visibilities       Section 1 (the same algorithm with the visibility-domain
+                     direct operator, oracle.visibility)
 
 Readings where the paper is silent (each also listed in the design notes):
   * X, U, V, T and all derivative states start at zero.
@@ -143,23 +145,37 @@ class State:
 
 @dataclass
 class Problem:
-    """Everything one solve keeps fixed."""
-    Y: np.ndarray          # (L, n, n) dirty cube
-    K: np.ndarray          # (L, 2n, 2n) PSF transfer functions
+    """Everything one solve keeps fixed.  With `vis` set (a visibility
+    operator), Y holds the complex visibilities (L, K) and H is `vis`;
+    otherwise Y is the dirty cube and H the convolution by the PSFs."""
+    Y: np.ndarray          # (L, n, n) dirty cube, or (L, K) visibilities
+    K: np.ndarray          # (L, 2n, 2n) PSF transfer functions (image domain)
     Ws: SpatialDictionary
     alpha: np.ndarray      # (N,)
     beta: np.ndarray       # (L,)
     sigma: float = 10.0
+    vis: object = None
+    n: int = 0
 
     @property
     def shape(self):
-        return self.Y.shape
+        L = self.Y.shape[0]
+        n = self.n or self.Y.shape[-1]
+        return (L, n, n)
+
+    def fwd(self, x):
+        """H x (eq. `model`)."""
+        return self.vis.forward(x) if self.vis is not None else H(x, self.K)
+
+    def adj(self, r):
+        """(Re) H^T r."""
+        return self.vis.adjoint(r) if self.vis is not None else HT(r, self.K)
 
     def mu_l(self, mu):
         return mu * self.beta                      # eq. `2regpar`
 
     def gamma_n(self, gamma):
-        L, n, _ = self.Y.shape
+        L, n, _ = self.shape
         return (gamma * self.alpha).reshape(n, n)  # eq. `2regpar`
 
 
@@ -172,7 +188,7 @@ def muffin_step(st: State, Y: np.ndarray, pb: Problem, mu: float, gamma: float,
     gam = pb.gamma_n(gamma)[None]
     sig = pb.sigma
     x = st.X                                              # eq. updatenode2
-    grad = HT(H(x, pb.K) - Y, pb.K)                       # eq. grad2
+    grad = pb.adj(pb.fwd(x) - Y)                          # eq. grad2
     s = mu_l * pb.Ws.adjoint(st.U)                        # eq. adjointspat2
     m = x - tau * (grad + s + st.T)                       # eq. stpm
     xt = pos(m)                                           # eq. stpx
@@ -194,7 +210,7 @@ def deriv_step_mu(d: State, it: dict, pb: Problem, mu: float, gamma: float,
     alpha = pb.gamma_n(1.0)[None]
     sig = pb.sigma
     x_d = d.X
-    grad_d = HT(H(x_d, pb.K), pb.K)
+    grad_d = pb.adj(pb.fwd(x_d))
     s_d = mu * beta * pb.Ws.adjoint(d.U) + beta * pb.Ws.adjoint(it["u_in"])
     m_d = x_d - tau * (grad_d + s_d + d.T)
     xt_d = U_weak(it["m"]) * m_d
@@ -214,7 +230,7 @@ def deriv_step_gamma(d: State, it: dict, pb: Problem, mu: float, gamma: float,
     alpha = pb.gamma_n(1.0)[None]
     sig = pb.sigma
     x_d = d.X
-    grad_d = HT(H(x_d, pb.K), pb.K)
+    grad_d = pb.adj(pb.fwd(x_d))
     s_d = mu * beta * pb.Ws.adjoint(d.U)
     m_d = x_d - tau * (grad_d + s_d + d.T)
     xt_d = U_weak(it["m"]) * m_d
@@ -231,23 +247,35 @@ def deriv_step_gamma(d: State, it: dict, pb: Problem, mu: float, gamma: float,
 # --------------------------------------------------------------------------
 
 
-def psure(Y, X, Xbar, K, delta, sigma_w, eps):
-    """PSURE-FDMC summed over bands (eqs. `PSURE`, `PSURE0`)."""
-    L, n, _ = Y.shape
-    d = H(X, K)
-    dbar = H(Xbar, K)
-    N = n * n
-    return float(np.sum((Y - d) ** 2) - L * N * sigma_w ** 2
-                 + sigma_w ** 2 * (2.0 / eps) * np.sum((dbar - d) * delta))
+def _rdot(a, b):
+    """Real inner product (of complex data: the sum over real and imaginary
+    parts)."""
+    return float(np.sum(np.real(np.conj(a) * b)))
 
 
-def sugar(Y, X, Xd, Xbar_d, K, delta, sigma_w, eps):
+def _meas(Y):
+    """Number of real measurements (complex data count twice)."""
+    return Y.size * (2 if np.iscomplexobj(Y) else 1)
+
+
+def psure(Y, X, Xbar, K, delta, sigma_w, eps, fwd=None):
+    """PSURE-FDMC summed over bands (eqs. `PSURE`, `PSURE0`); fwd: the
+    direct operator (default: the convolution by the PSFs of K)."""
+    fwd = fwd or (lambda z: H(z, K))
+    d = fwd(X)
+    dbar = fwd(Xbar)
+    return float(_rdot(Y - d, Y - d) - _meas(Y) * sigma_w ** 2
+                 + sigma_w ** 2 * (2.0 / eps) * _rdot(dbar - d, delta))
+
+
+def sugar(Y, X, Xd, Xbar_d, K, delta, sigma_w, eps, fwd=None):
     """SUGAR-FDMC summed over bands for one parameter (eq. `SUGAR`)."""
-    d = H(X, K)
-    dd = H(Xd, K)
-    dbar_d = H(Xbar_d, K)
-    return float(2.0 * np.sum((d - Y) * dd)
-                 + (2.0 * sigma_w ** 2 / eps) * np.sum((dbar_d - dd) * delta))
+    fwd = fwd or (lambda z: H(z, K))
+    d = fwd(X)
+    dd = fwd(Xd)
+    dbar_d = fwd(Xbar_d)
+    return float(2.0 * _rdot(d - Y, dd)
+                 + (2.0 * sigma_w ** 2 / eps) * _rdot(dbar_d - dd, delta))
 
 
 # --------------------------------------------------------------------------
@@ -258,7 +286,7 @@ def sugar(Y, X, Xd, Xbar_d, K, delta, sigma_w, eps):
 def run_muffin(pb: Problem, mu: float, gamma: float, tau: float, iters: int,
                state: State | None = None) -> State:
     """Plain MUFFIN (fixed theta): `iters` iterations of Algorithm 2."""
-    L, n, _ = pb.Y.shape
+    L, n, _ = pb.shape
     st = state.copy() if state is not None else State.zeros(L, n, pb.Ws.P)
     for _ in range(iters):
         st, _ = muffin_step(st, pb.Y, pb, mu, gamma, tau)
@@ -287,7 +315,7 @@ def run_adapt(pb: Problem, mu0: float, gamma0: float, iters: int, delta,
 
     tau: if given, a fixed step used throughout; otherwise recomputed from
     beta_H with `tau_mode` at the start and after every theta update."""
-    L, n, _ = pb.Y.shape
+    L, n, _ = pb.shape
     P = pb.Ws.P
     Ybar = pb.Y + eps * delta
     mu, gamma = float(mu0), float(gamma0)
@@ -297,7 +325,7 @@ def run_adapt(pb: Problem, mu0: float, gamma0: float, iters: int, delta,
             return float(tau)
         return float(tau_rule(beta_H, pb.sigma, pb.mu_l(mu),
                               pb.gamma_n(gamma).ravel(), tau_mode, rho,
-                              ws_norm2_of(pb.Ws, pb.Y.shape[-1])))
+                              ws_norm2_of(pb.Ws, pb.shape[-1])))
 
     t_now = cur_tau()
     S, Sb = State.zeros(L, n, P), State.zeros(L, n, P)
@@ -313,9 +341,9 @@ def run_adapt(pb: Problem, mu0: float, gamma0: float, iters: int, delta,
         Dbg = deriv_step_gamma(Dbg, itb, pb, mu, gamma, t_now)
         S, Sb = S_new, Sb_new
         if k % Delta == 0:
-            g_mu = sugar(pb.Y, S.X, Dm.X, Dbm.X, pb.K, delta, sigma_w, eps)
-            g_ga = sugar(pb.Y, S.X, Dg.X, Dbg.X, pb.K, delta, sigma_w, eps)
-            r = psure(pb.Y, S.X, Sb.X, pb.K, delta, sigma_w, eps)
+            g_mu = sugar(pb.Y, S.X, Dm.X, Dbm.X, pb.K, delta, sigma_w, eps, pb.fwd)
+            g_ga = sugar(pb.Y, S.X, Dg.X, Dbg.X, pb.K, delta, sigma_w, eps, pb.fwd)
+            r = psure(pb.Y, S.X, Sb.X, pb.K, delta, sigma_w, eps, pb.fwd)
             mu = max(mu - eta_mu * g_mu, 0.0)
             gamma = max(gamma - eta_gamma * g_ga, 0.0)
             t_now = cur_tau()
@@ -335,7 +363,8 @@ def objective(X, pb: Problem, mu: float, gamma: float) -> float:
     if np.any(X < 0):
         return np.inf
     L, n, _ = X.shape
-    data = 0.5 * np.sum((pb.Y - H(X, pb.K)) ** 2)
+    r = pb.Y - pb.fwd(X)
+    data = 0.5 * _rdot(r, r)
     spat = np.sum(pb.mu_l(mu) * np.sum(np.abs(pb.Ws.forward(X)).reshape(L, -1), axis=1))
     spec = np.sum(pb.gamma_n(gamma).ravel()
                   * np.sum(np.abs(Wl(X)).reshape(L, -1), axis=0))
@@ -351,6 +380,43 @@ def quality(X: np.ndarray, truth: np.ndarray, K: np.ndarray) -> tuple[float, flo
     snr = 10.0 * np.log10(np.sum(truth ** 2) / np.sum(err ** 2))
     wmse = float(np.sum(H(err, K) ** 2)) / (n * n * L)
     return float(snr), wmse
+
+
+def make_vis_problem(vis, uv, n, P=8, J=3, sigma=10.0, alpha=None, beta=None,
+                     eps_w=1e-6, dictionary="daubechies") -> Problem:
+    """A Problem whose data are visibilities (L, K) at the sample positions
+    uv (L, K, 2) of an n x n cube (the visibility-domain operator of
+    oracle.visibility).  Weights default to the rule of Section 2.1 with the
+    back-projected (dirty) cube Re H^* v as the initial estimate."""
+    from .visibility import VisibilityOperator
+    op = VisibilityOperator(uv, n)
+    Ws = SpatialDictionary(P, J) if dictionary == "daubechies" else StarletDictionary(J)
+    if alpha is None or beta is None:
+        a, b = weights(op.adjoint(vis), Ws, eps_w)
+        alpha = a if alpha is None else alpha
+        beta = b if beta is None else beta
+    L = vis.shape[0]
+    return Problem(Y=np.asarray(vis, np.complex128), K=np.zeros((L, 1, 1)), Ws=Ws,
+                   alpha=np.asarray(alpha, np.float64), beta=np.asarray(beta, np.float64),
+                   sigma=sigma, vis=op, n=n)
+
+
+def lipschitz_op(pb: Problem, iters: int = 1000, tol: float = 1e-13, seed: int = 7) -> float:
+    """beta_H for any direct operator: max over bands of lambda_max(H^T H)
+    by power iteration with the Rayleigh quotient."""
+    L, n, _ = pb.shape
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = rng.standard_normal((L, n, n))
+    lam = np.zeros(L)
+    for _ in range(iters):
+        w = pb.adj(pb.fwd(v))
+        new = np.sum(v * w, axis=(1, 2)) / np.sum(v * v, axis=(1, 2))
+        v = w / np.sqrt(np.sum(w * w, axis=(1, 2)))[:, None, None]
+        done = np.max(np.abs(new - lam) / np.abs(new)) <= tol
+        lam = new
+        if done:
+            break
+    return float(np.max(lam))
 
 
 def make_problem(dirty, psf, P=8, J=3, sigma=10.0, alpha=None, beta=None,
