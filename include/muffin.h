@@ -104,6 +104,18 @@ typedef struct {
   int32_t dictionary;   /* MUFFIN_DICT_DAUBECHIES or MUFFIN_DICT_STARLET; with
                            STARLET, levels = J scales (1..5) and n_bases is
                            unused: U and the masks hold J + 1 planes per band */
+  int32_t visibilities; /* 0: dirty images (eq. `model`); 1: visibilities
+                           (Section 1: only the direct operator changes).
+                           muffin_set_problem then takes, from
+                           muffin_vis_prepare, the back-projected cube
+                           Re H^* v as `dirty`, the point spread function as
+                           `psf` and the back-projected probe Re H^* delta as
+                           `delta`; the gradient is psf * x - dirty (the
+                           windowed convolution by the PSF is Re H^* H) */
+  double vis_norm2;     /* visibilities: |v|^2 over all bands (the residual
+                           |v - H x|^2 of PSURE is computed from it) */
+  double vis_count;     /* visibilities: number of real measurements (two per
+                           complex sample), > 0 with sure */
 } muffin_config;
 
 typedef struct {
@@ -360,6 +372,28 @@ int muffin_unmix_plan_create(muffin_unmix_plan** plan, const double* spectra, in
 int muffin_unmix_run(const muffin_unmix_plan* plan, const void* cube, int32_t n, int32_t mode,
                      void* abund, void* resid, void* stream);
 int muffin_unmix_plan_destroy(muffin_unmix_plan* plan);
+
+/* ---- visibility-domain direct operator ----
+ * Band l samples the sky's Fourier transform at K positions (u, v) in
+ * cycles across the image (|u|, |v| < n/2), phases referred to the image
+ * centre c = n/2: (H x)_k = sum_ij x[i][j] exp(-2 pi i (u_k (i-c) + v_k (j-c)) / n).
+ * All sums are exact (no gridding approximation), in FP64, O(K) per output.
+ *   uv:    device double [L][K][2];  vis, delta: device double [L][K][2]
+ *          (real, imaginary parts).
+ *   muffin_vis_prepare: dirty_out = Re H^* vis ([L][n][n]), psf_out = the
+ *          real point spread function [L][2n][2n] with offset (0, 0) at
+ *          (n, n), i.e. psf[n+a][n+b] = sum_k cos(2 pi (u_k a + v_k b) / n),
+ *          delta_out = Re H^* delta (NULL with delta NULL); outputs in the
+ *          working type of `mode`; *vis_norm2 = |vis|^2 (NULL: skipped;
+ *          otherwise synchronises the stream).  These are the inputs of
+ *          muffin_set_problem for a configuration with visibilities = 1.
+ *   muffin_vis_degrid: vis_out ([L][K][2] double) = H x, x a device cube
+ *          of the working type.  Enqueued on `stream`. */
+int muffin_vis_prepare(const double* uv, const double* vis, const double* delta, int32_t L,
+                       int32_t K, int32_t n, int32_t mode, void* dirty_out, void* psf_out,
+                       void* delta_out, double* vis_norm2, void* stream);
+int muffin_vis_degrid(const double* uv, int32_t L, int32_t K, int32_t n, int32_t mode,
+                      const void* x, double* vis_out, void* stream);
 
 /* ---- autotuner: wavelet tile shapes per size class ----
  * The FP32 level-1 wavelet kernels of the Daubechies union come in two tile

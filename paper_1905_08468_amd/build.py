@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.environ.get("MUFFIN_BUILD_OUT", os.path.join(HERE, "libmuffin.so"))
 BUILD = os.environ.get("MUFFIN_BUILD_DIR", os.path.join(ROOT, "_build"))
 EXTRA = os.environ.get("MUFFIN_EXTRA_FLAGS", "").split()
-SOURCES = ["fft.hip", "dwt.hip", "dct.hip", "ew.hip", "muffin.cpp", "server.cpp", "multistart.cpp", "unmix.hip", "starlet.hip"]
+SOURCES = ["fft.hip", "dwt.hip", "dct.hip", "ew.hip", "muffin.cpp", "server.cpp", "multistart.cpp", "unmix.hip", "starlet.hip", "vis.hip"]
 ARCH = os.environ.get("MUFFIN_ARCH", "gfx950")
 
 FLAGS = [

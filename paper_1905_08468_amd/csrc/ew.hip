@@ -146,7 +146,7 @@ __device__ void tau_from_rule(DevParams* dp) {
 // counter (updates happen after every `period` iterations), so the kernel
 // can be replayed from a captured graph.
 __global__ void theta_kernel(DevParams* dp, double* hist, int max_hist, int period,
-                             long long LN, int apply) {
+                             int apply) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int q = dp->n_updates;  // this update's index
   double* hist_row = (hist && q < max_hist) ? hist + (size_t)q * kHistCols : nullptr;
@@ -154,8 +154,11 @@ __global__ void theta_kernel(DevParams* dp, double* hist, int max_hist, int peri
   const double c = 2.0 * dp->sigma_w * dp->sigma_w / dp->eps_fd;
   const double s_mu = 2.0 * dp->sums[SLOT_GX_MU] + c * dp->sums[SLOT_FD_MU];
   const double s_ga = 2.0 * dp->sums[SLOT_GX_GA] + c * dp->sums[SLOT_FD_GA];
-  const double psure =
-      dp->sums[SLOT_RES2] - double(LN) * dp->sigma_w * dp->sigma_w + c * dp->sums[SLOT_FD_X];
+  // ||Y - H X||^2: from the FFT chain (dirty images), or for visibilities
+  // |v|^2 + <X, psf * X - 2 Re H^* v> (two dot products)
+  const double res2 = dp->vis ? dp->res_const + dp->sums[SLOT_RES2] - dp->sums[SLOT_AUX0]
+                              : dp->sums[SLOT_RES2];
+  const double psure = res2 - dp->n_meas * dp->sigma_w * dp->sigma_w + c * dp->sums[SLOT_FD_X];
   if (apply) {
     const double mu = dp->mu - dp->eta_mu * s_mu;
     const double ga = dp->gamma - dp->eta_gamma * s_ga;
@@ -172,13 +175,13 @@ __global__ void theta_kernel(DevParams* dp, double* hist, int max_hist, int peri
     hist_row[4] = s_mu;
     hist_row[5] = s_ga;
     hist_row[6] = psure;
-    hist_row[7] = dp->sums[SLOT_RES2];
+    hist_row[7] = res2;
   }
 }
 
-int theta_update(DevParams* dp, double* hist, int max_hist, int period, long long LN, int apply,
+int theta_update(DevParams* dp, double* hist, int max_hist, int period, int apply,
                  hipStream_t s) {
-  theta_kernel<<<1, 64, 0, s>>>(dp, hist, max_hist, period, LN, apply);
+  theta_kernel<<<1, 64, 0, s>>>(dp, hist, max_hist, period, apply);
   MUFFIN_HIP_CHECK(hipGetLastError());
   return 0;
 }

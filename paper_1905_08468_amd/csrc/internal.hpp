@@ -35,6 +35,10 @@ struct DevParams {
   double ws_norm2;           // ||W_s||^2 in the step rule (1 for the Daubechies union)
   double eta_mu, eta_gamma;  // ADA-PT gradient steps
   double eps_fd, sigma_w;    // FDMC perturbation size and noise std
+  double res_const;          // visibilities: |v|^2 (0 for dirty images)
+  double n_meas;             // real measurements (PSURE's noise term)
+  int32_t vis;               // 1: visibility data (residual from dot products)
+  int32_t pad_;
   int32_t tau_rule;          // 0: operator-norm form, 1: printed sum form
   int32_t n_updates;         // theta updates done
   double sums[8];            // reduction results (see Slot)
@@ -255,7 +259,7 @@ int weights_from(const T* x0, int L, int N, double eps, double* alpha, double* b
 
 // K-THETA: SUGAR from the reduction slots, theta update, tau recompute,
 // history row (hist[n_updates], iteration (n_updates + 1) * period).
-int theta_update(DevParams* dp, double* hist, int max_hist, int period, long long LN, int apply,
+int theta_update(DevParams* dp, double* hist, int max_hist, int period, int apply,
                  hipStream_t s);
 int tau_refresh(DevParams* dp, hipStream_t s);
 

@@ -130,6 +130,9 @@ int validate(const muffin_config* c) {
     return MUFFIN_E_INVAL;
   if (c->dictionary == MUFFIN_DICT_STARLET && (c->levels < 1 || c->levels > 5))
     return MUFFIN_E_SHAPE;
+  if (c->visibilities != 0 && c->visibilities != 1) return MUFFIN_E_INVAL;
+  if (c->visibilities && (!(c->vis_norm2 >= 0) || (c->sure && !(c->vis_count > 0))))
+    return MUFFIN_E_INVAL;
   if (!is_pow2(c->n) || c->n < 8 || c->n > 2048) return MUFFIN_E_SHAPE;
   if (c->L < 1 || c->L > 256) return MUFFIN_E_SHAPE;
   if (c->n_bases < 1 || c->n_bases > kMaxBases) return MUFFIN_E_SHAPE;
@@ -240,6 +243,9 @@ struct Impl final : ImplBase {
   FftPlan<T> fft;
   DwtPlan<T> dwt;
   bool star = false;  // spatial dictionary: starlet (else the Daubechies union)
+  bool vis = false;   // data are visibilities: the gradient's operator is the
+                      // PSF convolution (chain op 0) instead of H^T H (op 2)
+  int gop() const { return vis ? 0 : 2; }
   StarletPlan spl;
   DctPlan<T> dct;
   DevParams* dp = nullptr;
@@ -278,6 +284,7 @@ struct Impl final : ImplBase {
     P = (int)planes_of(&c);
     J = c.levels;
     star = c.dictionary == MUFFIN_DICT_STARLET;
+    vis = c.visibilities != 0;
     spl.n = n;
     spl.L = L;
     spl.J = J;
@@ -420,7 +427,7 @@ struct Impl final : ImplBase {
       io.specA[0] = sa;
       io.specB[0] = sb;
       io.nsets = 1;
-      if ((rc = fft_chain(*pf, io, 2, st))) break;
+      if ((rc = fft_chain(*pf, io, gop(), st))) break;
       if ((rc = pi_band_dots(v, w, L, N, partials, bpb, st))) break;
       if ((rc = pi_band_finish(partials, L, bpb, stats, st))) break;
       if ((rc = pi_normalise(v, w, stats, L, N, st))) break;
@@ -539,6 +546,9 @@ struct Impl final : ImplBase {
     hp.eta_gamma = cfg.eta_gamma;
     hp.eps_fd = cfg.eps_fd;
     hp.sigma_w = cfg.sigma_w;
+    hp.vis = vis ? 1 : 0;
+    hp.res_const = vis ? cfg.vis_norm2 : 0.0;
+    hp.n_meas = vis ? cfg.vis_count : double(LN);
     if (cfg.tau > 0) {
       hp.tau_rule = -1;
       hp.tau = cfg.tau;
@@ -551,11 +561,19 @@ struct Impl final : ImplBase {
     }
     MUFFIN_HIP_CHECK(hipMemcpyAsync(dp, &hp, sizeof(hp), hipMemcpyHostToDevice, st));
     // H^T y, and for ADA-PT the perturbed data Ybar = Y + eps delta (Alg. 5)
-    RC(chain1(Y, HTy, 1));
+    // (visibilities: the inputs are already back-projected, Re H^* v and
+    // Re H^* delta, so they stand for H^T y and H^T delta)
+    if (vis) RC(copy_dev<T>(HTy, Y, LN, st));
+    else RC(chain1(Y, HTy, 1));
     if (cfg.sure) {
       RC(axpy_copy(Ybar, Y, de, cfg.eps_fd, LN, st));
-      RC(chain1(Ybar, HTybar, 1));
-      RC(chain1(de, HTd, 1));
+      if (vis) {
+        RC(copy_dev<T>(HTybar, Ybar, LN, st));
+        RC(copy_dev<T>(HTd, de, LN, st));
+      } else {
+        RC(chain1(Ybar, HTybar, 1));
+        RC(chain1(de, HTd, 1));
+      }
     }
     // zero state
     for (int s = 0; s < nsets; ++s) {
@@ -587,7 +605,7 @@ struct Impl final : ImplBase {
         out[s] = G[s];
       }
       tm.begin(ST_FFT, st);
-      RC(chain(in, out, sets, nsets, 2));
+      RC(chain(in, out, sets, nsets, gop()));
       tm.end(st);
     }
     // 2. synthesis
@@ -756,14 +774,23 @@ struct Impl final : ImplBase {
     const int q = n_upd++;
     // H^T H X^(k) of the Y trajectory, with ||Y - H X||^2 on the way
     const int nres = fft_res_blocks(n, L, sizeof(T));
+    const int nb = dot_blocks();
     {
       const int s0 = 0;
       const T* in = X[0];
       T* out = G[0];
-      RC(chain(&in, &out, &s0, 1, 2, Y, partials));
-      RC(reduce_to_slot(partials, nres, dp, SLOT_RES2, st));
+      if (vis) {
+        // psf * X, then |v - H X|^2 = |v|^2 + <psf * X - Re H^* v, X> - <Re H^* v, X>
+        RC(chain(&in, &out, &s0, 1, 0));
+        RC(dot_partials<T>(G[0], HTy, X[0], LN, partials, nb, st));
+        RC(reduce_to_slot(partials, nb, dp, SLOT_RES2, st));
+        RC(dot_partials<T>(HTy, nullptr, X[0], LN, partials, nb, st));
+        RC(reduce_to_slot(partials, nb, dp, SLOT_AUX0, st));
+      } else {
+        RC(chain(&in, &out, &s0, 1, 2, Y, partials));
+        RC(reduce_to_slot(partials, nres, dp, SLOT_RES2, st));
+      }
     }
-    const int nb = dot_blocks();
     RC(dot_partials<T>(G[0], HTy, X[2], LN, partials, nb, st));
     RC(reduce_to_slot(partials, nb, dp, SLOT_GX_MU, st));
     RC(dot_partials<T>(G[0], HTy, X[3], LN, partials, nb, st));
@@ -775,7 +802,7 @@ struct Impl final : ImplBase {
     RC(dot_partials<T>(X[1], X[0], HTd, LN, partials, nb, st));
     RC(reduce_to_slot(partials, nb, dp, SLOT_FD_X, st));
     (void)q;
-    RC(theta_update(dp, hist, max_hist, cfg.delta_period, (long long)LN, 1, st));
+    RC(theta_update(dp, hist, max_hist, cfg.delta_period, 1, st));
     if (cfg.deriv_reset) {
       for (int s = 2; s < 6; ++s) {
         RC(fill_zero(X[s], LN, st));
@@ -1191,7 +1218,13 @@ struct Impl final : ImplBase {
     RC(diff_sq<T>(xs, X[0], LN, partials, nb, qsum, st));
     RC(axpy_copy<T>(G[0], xs, X[0], -1.0, LN, st));
     RC(chain1(G[0], S[0], 0));
-    RC(diff_sq<T>(S[0], S[0], LN, partials, nb, qsum + 2, st));
+    if (vis) {
+      // |H e|^2 = <e, Re H^* H e> = <e, psf * e> (as the third sum)
+      RC(dot_partials<T>(S[0], nullptr, G[0], LN, partials, nb, st));
+      RC(reduce_to_buffer(partials, nb, qsum + 3, st));
+    } else {
+      RC(diff_sq<T>(S[0], S[0], LN, partials, nb, qsum + 2, st));
+    }
     double h[4];
     MUFFIN_HIP_CHECK(hipMemcpyAsync(h, qsum, sizeof(h), hipMemcpyDeviceToHost, st));
     MUFFIN_HIP_CHECK(hipStreamSynchronize(st));

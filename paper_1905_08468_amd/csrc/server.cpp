@@ -42,7 +42,8 @@ bool same_config(const muffin_config& a, const muffin_config& b) {
          a.eta_gamma == b.eta_gamma && a.eps_fd == b.eps_fd && a.sigma_w == b.sigma_w &&
          a.deriv_reset == b.deriv_reset && a.pi_iters == b.pi_iters && a.pi_tol == b.pi_tol &&
          a.stop_rel == b.stop_rel && a.check_every == b.check_every &&
-         a.dictionary == b.dictionary;
+         a.dictionary == b.dictionary && a.visibilities == b.visibilities &&
+         a.vis_norm2 == b.vis_norm2 && a.vis_count == b.vis_count;
 }
 
 struct Request {

@@ -43,6 +43,7 @@ class Config(C.Structure):
         ("deriv_reset", C.c_int32), ("pi_iters", C.c_int32), ("pi_tol", C.c_double),
         ("stop_rel", C.c_double), ("check_every", C.c_int32),
         ("dictionary", C.c_int32),
+        ("visibilities", C.c_int32), ("vis_norm2", C.c_double), ("vis_count", C.c_double),
     ]
 
 
@@ -100,7 +101,7 @@ EXPORTS = [
     "muffin_multistart_run", "muffin_multistart_quality", "muffin_multistart_handle",
     "muffin_multistart_destroy",
     "muffin_unmix_plan_create", "muffin_unmix_run", "muffin_unmix_plan_destroy",
-    "muffin_autotune",
+    "muffin_autotune", "muffin_vis_prepare", "muffin_vis_degrid",
 ]
 
 
@@ -157,6 +158,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "muffin_unmix_run": ([vp, vp, i32, i32, vp, vp, vp], C.c_int),
         "muffin_unmix_plan_destroy": ([vp], C.c_int),
         "muffin_autotune": ([vp, i32, C.POINTER(TuneResult)], C.c_int),
+        "muffin_vis_prepare": ([vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, dp, vp], C.c_int),
+        "muffin_vis_degrid": ([vp, i32, i32, i32, i32, vp, vp, vp], C.c_int),
     }
     for name in ["muffin_op_H", "muffin_op_HT", "muffin_op_HTH", "muffin_op_Ws",
                  "muffin_op_WsT", "muffin_op_dct", "muffin_op_idct"]:
@@ -698,3 +701,53 @@ class Unmixer:
             self.close()
         except Exception:
             pass
+
+
+def _vis_dev(a, torch):
+    """Complex (L, K) or real (L, K, 2) host/device data -> contiguous device
+    float64 (L, K, 2)."""
+    if isinstance(a, np.ndarray):
+        if np.iscomplexobj(a):
+            a = np.stack([a.real, a.imag], axis=-1)
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+    if a.is_complex():
+        a = torch.view_as_real(a)
+    return a.to(torch.float64).contiguous()
+
+
+def vis_prepare(uv, vis, n: int, mode: int = F32, delta=None, stream=None):
+    """Inputs of a visibility solve (muffin_vis_prepare): returns
+    (dirty = Re H^* v, psf, delta_img = Re H^* delta or None, |v|^2).  uv:
+    (L, K, 2) sample positions; vis, delta: complex (L, K)."""
+    import torch
+    u = _vis_dev(uv, torch)
+    v = _vis_dev(vis, torch)
+    d = _vis_dev(delta, torch) if delta is not None else None
+    L, K = u.shape[0], u.shape[1]
+    dt = torch.float64 if mode == F64 else torch.float32
+    dirty = torch.empty((L, n, n), dtype=dt, device=u.device)
+    psf = torch.empty((L, 2 * n, 2 * n), dtype=dt, device=u.device)
+    dimg = torch.empty((L, n, n), dtype=dt, device=u.device) if d is not None else None
+    nrm = C.c_double()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = _lib.muffin_vis_prepare(_ptr(u), _ptr(v), _ptr(d), L, K, n, int(mode), _ptr(dirty),
+                                 _ptr(psf), _ptr(dimg), C.byref(nrm), C.c_void_p(s.cuda_stream))
+    if rc:
+        raise MuffinError(rc, "muffin_vis_prepare")
+    return dirty, psf, dimg, nrm.value
+
+
+def vis_degrid(uv, x, stream=None):
+    """H x at the sample positions (muffin_vis_degrid): complex (L, K) tensor."""
+    import torch
+    u = _vis_dev(uv, torch)
+    L, K = u.shape[0], u.shape[1]
+    n = x.shape[-1]
+    mode = F64 if x.dtype == torch.float64 else F32
+    out = torch.empty((L, K, 2), dtype=torch.float64, device=u.device)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = _lib.muffin_vis_degrid(_ptr(u), L, K, n, int(mode), _ptr(x.contiguous()), _ptr(out),
+                                C.c_void_p(s.cuda_stream))
+    if rc:
+        raise MuffinError(rc, "muffin_vis_degrid")
+    return torch.view_as_complex(out)

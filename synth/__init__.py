@@ -22,6 +22,14 @@ SKA1-MID PSFs are not available, so the recipe below stands in for them:
                variance sigma_w^2 = ||H X*||^2 / (N L 10^(SNR/10));
 * probe        delta ~ N(0, I), the Monte-Carlo direction of SURE-FDMC.
 
+Visibility data (make_vis_problem), the same sky observed in the visibility
+domain: B baselines uniform in a disc of radius 0.22 n cycles across the
+image at nu0, scaled by nu_l/nu0 (continuous positions, below the n/2
+Nyquist limit in every band); complex visibilities are the exact Fourier
+sums of the sky at those positions (phases referred to the image centre
+n/2), plus complex noise of variance sigma_w^2 per real component at the
+given SNR; the probe is complex N(0, 1) per component.
+
 All draws come from one numpy PCG64 stream per seed in a fixed order, so the
 CPU oracle and the GPU path always see bit-identical inputs.  The smoothing
 (PSF synthesis and the observation convolution) uses library FFT routines
@@ -194,6 +202,54 @@ def make_problem(n: int, L: int, n_src: int, n_blob: int, n_base: int,
     delta = rng.standard_normal(size=sky.shape)
     return Problem(n=n, L=L, nu=nu, sky=sky, psf=psf, dirty=dirty,
                    sigma_w=sigma_w, delta=delta, seed=seed)
+
+
+@dataclass
+class VisProblem:
+    n: int
+    L: int
+    nu: np.ndarray
+    sky: np.ndarray       # (L, n, n)
+    uv: np.ndarray        # (L, K, 2) sample positions, cycles across the image
+    vis: np.ndarray       # (L, K) complex visibilities
+    sigma_w: float        # noise std per real component
+    delta: np.ndarray     # (L, K) complex N(0, 1) probe
+    seed: int
+
+
+def _fourier_samples(sky_l: np.ndarray, uv_l: np.ndarray, device=None) -> np.ndarray:
+    """sum_ij x[i, j] exp(-2 pi i (u (i - n/2) + v (j - n/2)) / n) at every
+    (u, v) of one band."""
+    n = sky_l.shape[0]
+    idx = np.arange(n) - n / 2.0
+    if device is not None:
+        import torch
+        t = lambda a: torch.from_numpy(a).to(device)
+        er = torch.exp(-2j * np.pi * torch.outer(t(uv_l[:, 0]), t(idx)) / n)
+        ec = torch.exp(-2j * np.pi * torch.outer(t(uv_l[:, 1]), t(idx)) / n)
+        x = t(sky_l).to(torch.complex128)
+        return ((er @ x) * ec).sum(dim=1).cpu().numpy()
+    er = np.exp(-2j * np.pi * np.outer(uv_l[:, 0], idx) / n)
+    ec = np.exp(-2j * np.pi * np.outer(uv_l[:, 1], idx) / n)
+    return np.sum((er @ sky_l) * ec, axis=1)
+
+
+def make_vis_problem(n: int, L: int, n_src: int, n_blob: int, n_base: int,
+                     snr_db: float = 20.0, seed: int = 0, device=None) -> VisProblem:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nu = frequencies(L)
+    sky = make_sky(rng, n, nu, n_src, n_blob)
+    rad = 0.22 * n * np.sqrt(rng.uniform(0.0, 1.0, size=n_base))
+    ang = rng.uniform(0.0, 2 * np.pi, size=n_base)
+    base = np.stack([rad * np.cos(ang), rad * np.sin(ang)], axis=-1)
+    uv = np.stack([base * (nu[l] / nu[0]) for l in range(L)])
+    clean = np.stack([_fourier_samples(sky[l], uv[l], device) for l in range(L)])
+    power = np.sum(np.abs(clean) ** 2)
+    sigma_w = float(np.sqrt(power / (2 * clean.size * 10 ** (snr_db / 10))))
+    noise = rng.standard_normal(clean.shape) + 1j * rng.standard_normal(clean.shape)
+    delta = rng.standard_normal(clean.shape) + 1j * rng.standard_normal(clean.shape)
+    return VisProblem(n=n, L=L, nu=nu, sky=sky, uv=uv, vis=clean + sigma_w * noise,
+                      sigma_w=sigma_w, delta=delta, seed=seed)
 
 
 def make_config(name: str, seed: int = 0, **over) -> Problem:
