@@ -771,6 +771,204 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 4) col_pass(ColArgs<T
   }
 }
 
+// ---- column pass with pruned end stages (one column per block) ----
+// The forward transform's input is zero in its upper half, so its first
+// stage is computed in registers from the n loaded values (the upper half of
+// each butterfly's inputs is zero) and stored to LDS without a read.  Its
+// last stage writes every output back to the slot it read (butterfly j owns
+// elements j + r Ns), so the product with K (or conj K) is applied in
+// registers before that store and no barrier separates the read from the
+// write.  The inverse transform's last stage computes only the n kept rows
+// and stores them straight to global memory.
+
+// DONE (log2 of Ns) of the last stage of the radix schedule, and the offset
+// of a stage's twiddles in the stage tables.
+constexpr int last_stage_done(int lognf) {
+  int done = 0;
+  while (done + radix_log_c(lognf - done) < lognf) done += radix_log_c(lognf - done);
+  return done;
+}
+constexpr int stage_table_off(int lognf, int upto) {
+  int done = 0, off = 0;
+  while (done < upto) {
+    const int lr = radix_log_c(lognf - done);
+    if (done > 0) off += (1 << done) * ((1 << lr) - 1);
+    done += lr;
+  }
+  return off;
+}
+
+// Stages DONE .. STOP-1 of a length-2^LOGNF transform of one sequence.
+template <typename T, int NT, int EMAX, int LOGNF, int DONE, int OFF, int STOP>
+__device__ __forceinline__ void lds_fft_range(cplx<T>* buf, const cplx<T>* __restrict__ twtab) {
+  if constexpr (DONE < STOP) {
+    constexpr int LR = radix_log_c(LOGNF - DONE);
+    fft_stage_ct<T, (1 << LR), NT, EMAX, LOGNF, DONE>(buf, 1, 0, twtab + OFF);
+    constexpr int NOFF = DONE > 0 ? OFF + (1 << DONE) * ((1 << LR) - 1) : OFF;
+    lds_fft_range<T, NT, EMAX, LOGNF, DONE + LR, NOFF, STOP>(buf, twtab);
+  }
+}
+
+// First stage (Ns = 1) from x[r] = element threadIdx.x + r * NT, r < R/2;
+// elements of the upper half are zero.
+template <typename T, int NT, int LOGNF>
+__device__ __forceinline__ void stage_first_half(cplx<T>* buf, const cplx<T>* x) {
+  constexpr int LR = radix_log_c(LOGNF), R = 1 << LR;
+  static_assert((1 << (LOGNF - LR)) == NT, "one first-stage butterfly per thread");
+  cplx<T> v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = r < R / 2 ? x[r] : cplx<T>{T(0), T(0)};
+  dft_small<T, R>(v);
+  const int base = threadIdx.x * R;
+#pragma unroll
+  for (int r = 0; r < R; ++r) buf[sw<T>(base + r)] = v[r];
+}
+
+// Loads and twiddles of the last stage: butterfly j = threadIdx.x + q NT
+// takes elements j + r Ns.
+template <typename T, int NT, int LOGNF, int MAXQ, int R>
+__device__ __forceinline__ void stage_last_load(const cplx<T>* buf, const cplx<T>* __restrict__ tws,
+                                                cplx<T> (&v)[MAXQ][R]) {
+  constexpr int NS = 1 << last_stage_done(LOGNF);
+  constexpr int S = sw_shift<T>();
+  static_assert((NS & ((1 << S) - 1)) == 0, "last-stage stride is a swizzle multiple");
+  cplx<T> w[MAXQ][R - 1];
+#pragma unroll
+  for (int q = 0; q < MAXQ; ++q) {
+    const int j = threadIdx.x + q * NT;
+#pragma unroll
+    for (int r = 1; r < R; ++r) w[q][r - 1] = tws[j * (R - 1) + r - 1];
+    const int sj = sw<T>(j);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[q][r] = buf[sj + r * NS + ((r * NS) >> S)];
+  }
+#pragma unroll
+  for (int q = 0; q < MAXQ; ++q) {
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[q][r - 1]);
+    dft_small<T, R>(v[q]);
+  }
+}
+
+// Last forward stage.  mul: store conj(X K[element]) (K staged at Ks),
+// else X.  Ends with a barrier.
+template <typename T, int NT, int LOGNF>
+__device__ __forceinline__ void stage_last_fwd(cplx<T>* buf, const cplx<T>* __restrict__ tws,
+                                               const cplx<T>* Ks, bool mul) {
+  constexpr int DL = last_stage_done(LOGNF);
+  constexpr int R = 1 << (LOGNF - DL), NS = 1 << DL, MAXQ = NS / NT;
+  constexpr int S = sw_shift<T>();
+  static_assert(NS % NT == 0, "whole last-stage butterflies per thread");
+  cplx<T> v[MAXQ][R];
+  stage_last_load<T, NT, LOGNF, MAXQ, R>(buf, tws, v);
+#pragma unroll
+  for (int q = 0; q < MAXQ; ++q) {
+    const int j = threadIdx.x + q * NT;
+    const int sj = sw<T>(j);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      cplx<T> x = v[q][r];
+      if (mul) x = cconj(cmul(x, Ks[j + r * NS]));
+      buf[sj + r * NS + ((r * NS) >> S)] = x;
+    }
+  }
+  lds_barrier();
+}
+
+// Last inverse stage: the elements below 2^(LOGNF-1) (r < R/2), conjugated,
+// to dst.
+template <typename T, int NT, int LOGNF>
+__device__ __forceinline__ void stage_last_out(const cplx<T>* buf, const cplx<T>* __restrict__ tws,
+                                               cplx<T>* __restrict__ dst) {
+  constexpr int DL = last_stage_done(LOGNF);
+  constexpr int R = 1 << (LOGNF - DL), NS = 1 << DL, MAXQ = NS / NT;
+  cplx<T> v[MAXQ][R];
+  stage_last_load<T, NT, LOGNF, MAXQ, R>(buf, tws, v);
+#pragma unroll
+  for (int q = 0; q < MAXQ; ++q) {
+    const int j = threadIdx.x + q * NT;
+#pragma unroll
+    for (int r = 0; r < R / 2; ++r) dst[j + r * NS] = cconj(v[q][r]);
+  }
+}
+
+template <typename T, int NT, bool TWL, int LOGN>
+__global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 4) col_pass_pruned(ColArgs<T> a) {
+  constexpr int LOGNF = LOGN + 1, N = 1 << LOGN, M2 = 2 * N;
+  constexpr int IPT = (1 << radix_log_c(LOGNF)) / 2;  // inputs per thread
+  static_assert(N == IPT * NT, "the first stage's inputs are the loaded values");
+  constexpr int EMAX = M2;
+  constexpr int DL = last_stage_done(LOGNF);
+  constexpr int OFFL = stage_table_off(LOGNF, DL);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int lb = xcd_remap(blockIdx.x, a.nblocks);
+  if (lb >= a.nblocks) return;
+  const int band = lb >> LOGN;
+  const int kx0 = lb - (band << LOGN);
+  cplx<T>* Ks = buf + sw_stride<T>(M2);
+  const cplx<T>* Kb = a.Kh + (size_t)band * (N + 1) * M2;
+  const cplx<T>* twc;
+  if constexpr (TWL) {
+    cplx<T>* twl = Ks + M2;
+    tables_to_lds<T, NT>(twl, a.twc, stage_table_len(LOGNF));
+    twc = twl;  // made visible by the barrier after the first stage
+  } else {
+    twc = a.twc;
+  }
+  const size_t col_off = ((size_t)band * N + kx0) * N;
+  cplx<T> pre[IPT];
+#pragma unroll
+  for (int q = 0; q < IPT; ++q) pre[q] = a.in[0][col_off + threadIdx.x + q * NT];
+  {
+    const cplx<T>* src = Kb + (size_t)kx0 * M2;
+#pragma unroll 4
+    for (int t = threadIdx.x; t < M2; t += NT) {
+      const cplx<T> k = src[t];
+      Ks[t] = a.conj ? cconj(k) : k;
+    }
+  }
+  // slot 0 packs the two real columns kx = 0 and kx = n (see col_pass)
+  const bool slot0 = kx0 == 0;
+  for (int set = 0; set < a.nsets; ++set) {
+    stage_first_half<T, NT, LOGNF>(buf, pre);
+    if (set + 1 < a.nsets) {
+#pragma unroll
+      for (int q = 0; q < IPT; ++q) pre[q] = a.in[set + 1][col_off + threadIdx.x + q * NT];
+    }
+    lds_barrier();
+    lds_fft_range<T, NT, EMAX, LOGNF, radix_log_c(LOGNF), 0, DL>(buf, twc);
+    stage_last_fwd<T, NT, LOGNF>(buf, twc + OFFL, Ks, !slot0);
+    if (slot0) {
+      for (int ky = threadIdx.x; ky <= N; ky += NT) {
+        const int kz = (M2 - ky) & (M2 - 1);
+        const int iy = sw<T>(ky), iz = sw<T>(kz);
+        const cplx<T> F = buf[iy], Fm = buf[iz];
+        const cplx<T> K0 = Ks[ky], K0m = Ks[kz];
+        cplx<T> Kn = Kb[(size_t)N * M2 + ky], Knm = Kb[(size_t)N * M2 + kz];
+        if (a.conj) {
+          Kn = cconj(Kn);
+          Knm = cconj(Knm);
+        }
+        const cplx<T> Sp = cadd(F, cconj(Fm)), Dp = csub(F, cconj(Fm));
+        cplx<T> G = cadd(cmul(Sp, K0), cmul(Dp, Kn));
+        G = {T(0.5) * G.x, T(0.5) * G.y};
+        if (kz != ky) {
+          const cplx<T> Sm = cadd(Fm, cconj(F)), Dm = csub(Fm, cconj(F));
+          cplx<T> Gm = cadd(cmul(Sm, K0m), cmul(Dm, Knm));
+          Gm = {T(0.5) * Gm.x, T(0.5) * Gm.y};
+          buf[iz] = cconj(Gm);
+        }
+        buf[iy] = cconj(G);
+      }
+      lds_barrier();
+    }
+    lds_fft_range<T, NT, EMAX, LOGNF, 0, 0, DL>(buf, twc);
+    stage_last_out<T, NT, LOGNF>(buf, twc + OFFL, a.out[set] + col_off);
+    lds_barrier();  // the next set's first stage overwrites buf
+  }
+}
+
 // PSF column pass: full 2n-point transform of each of the n+1 columns,
 // scaled by 1/(2n)^2 (the inverse-transform normalisation, folded into K).
 template <typename T, int NT>
@@ -941,8 +1139,10 @@ static int launch_col(const FftPlan<T>& p, const cplx<T>* const* in, cplx<T>* co
   constexpr bool F32 = sizeof(T) == 4;
   const size_t shm_t = shm + sizeof(cplx<T>) * (size_t)stage_table_len(a.logn + 1);
   if (p.n == 1024) {
-    MUFFIN_ALLOW_BIG_LDS((col_pass<T, 256, F32, 10>));
-    col_pass<T, 256, F32, 10><<<grid, 256, F32 ? shm_t : shm, s>>>(a);
+    // one column per block: the pruned form
+    if (a.B != 1) return -2; /* E_SHAPE */
+    MUFFIN_ALLOW_BIG_LDS((col_pass_pruned<T, 256, F32, 10>));
+    col_pass_pruned<T, 256, F32, 10><<<grid, 256, F32 ? shm_t : shm, s>>>(a);
   } else if (2 * p.n <= 2048) {
     MUFFIN_ALLOW_BIG_LDS((col_pass<T, 256, F32, 0>));
     col_pass<T, 256, F32, 0><<<grid, 256, F32 ? shm_t : shm, s>>>(a);

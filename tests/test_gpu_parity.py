@@ -421,3 +421,51 @@ def test_adapt_reduced_precision_forms(form):
     assert abs(rep["mu"] - ref.mu) <= 1e-3 * abs(ref.mu)
     assert abs(rep["gamma"] - ref.gamma) <= 1e-3 * abs(ref.gamma)
     h.close()
+
+
+@pytest.fixture(scope="module")
+def full_side_adapt():
+    """ADA-PT on one 1024^2 band (the benchmark's side: every state set goes
+    through the n = 1024 convolution chain), two iterations, a theta update
+    after each; the oracle's run is shared by both precisions."""
+    n, L, seed = 1024, 1, 31
+    prob = _problem(n, L, seed)
+    alpha, beta = synth.random_weights(L, n, seed)
+    eps = 0.05 * prob.sigma_w
+    pb = om.make_problem(prob.dirty, prob.psf, P=8, J=3, alpha=alpha, beta=beta)
+    tau = safe_tau(prob.psf, 10.0, 2 * beta, 2 * alpha)
+    kw = dict(mu0=0.5, gamma0=0.4, iters=2, Delta=1, eps=eps, tau=tau)
+    ref = om.run_adapt(pb, kw["mu0"], kw["gamma0"], kw["iters"], prob.delta, eps,
+                       prob.sigma_w, Delta=1, eta_mu=2e-4, eta_gamma=2e-4, tau=tau)
+    return prob, alpha, beta, kw, ref
+
+
+@pytest.mark.timeout(900)  # the oracle's two 1024^2 iterations take about a minute
+@pytest.mark.parametrize("mode", ["f64", "f32"])
+def test_full_side_adapt_iterations(mode, full_side_adapt):
+    mm = _mm()
+    torch = _torch()
+    prob, alpha, beta, kw, ref = full_side_adapt
+    n, L = 1024, 1
+    m = mm.F64 if mode == "f64" else mm.F32
+    dt = torch.float64 if mode == "f64" else torch.float32
+    cfg = _config(mm, n, L, mode=m, mu=kw["mu0"], gamma=kw["gamma0"], tau=kw["tau"],
+                  pi_iters=0, sure=1, delta_period=kw["Delta"], eps_fd=kw["eps"],
+                  sigma_w=prob.sigma_w, eta_mu=2e-4, eta_gamma=2e-4)
+    h = mm.Muffin(cfg)
+    h.set_problem(dev(prob.dirty, dt), dev(prob.psf, dt), alpha, beta, dev(prob.delta, dt))
+    rep = h.run(kw["iters"])
+    assert rep["theta_updates"] == len(ref.history) == 2
+    if mode == "f64":
+        assert rel(host(h.sky()), ref.X) < 1e-10
+        for s, key in [(1, "Sb"), (2, "Dm"), (3, "Dg"), (4, "Dbm"), (5, "Dbg")]:
+            exp = getattr(ref.states[key], "X")
+            assert rel(host(h.get_state(0, s)), exp) < 1e-9 or np.abs(exp).max() == 0, key
+        for row, r in zip(h.history(), ref.history):
+            assert abs(row[1] - r["mu"]) <= 1e-12 * max(1.0, abs(r["mu"]))
+            assert abs(row[2] - r["gamma"]) <= 1e-12 * max(1.0, abs(r["gamma"]))
+    else:
+        assert rel(host(h.sky()), ref.X) < 1e-5
+        assert abs(rep["mu"] - ref.mu) <= 1e-3 * abs(ref.mu)
+        assert abs(rep["gamma"] - ref.gamma) <= 1e-3 * abs(ref.gamma)
+    h.close()
