@@ -420,6 +420,78 @@ __device__ __forceinline__ void tables_to_lds(cplx<T>* dst, const cplx<T>* src, 
   }
 }
 
+// Hermitian pre-pass of the real inverse: with A = X[k], B = conj X[n-k],
+// Z[k] = (A + B) + i exp(i pi k / n) (A - B); stores conj Z for the
+// inverse-by-forward FFT.  Pairs (k, n-k) are owned by one thread.
+template <typename T, int RB, int NT>
+__device__ __forceinline__ void herm_pre(cplx<T>* buf, int stride, const cplx<T>* __restrict__ tw,
+                                         int n) {
+  const int half = n >> 1;
+  for (int t = threadIdx.x; t < RB * (half + 1); t += NT) {
+    const int r = t / (half + 1), k = t - r * (half + 1);
+    cplx<T>* row = buf + r * stride;
+    if (k == 0) {
+      const cplx<T> sv = row[0];  // (X[0], X[n]) both real
+      const T a0 = sv.x, an = sv.y;
+      row[0] = {a0 + an, -(a0 - an)};  // conj((a0 + an) + i (a0 - an))
+    } else {
+      const cplx<T> w = cconj(tw[k]);  // exp(+i pi k / n)
+      const int ik = sw<T>(k), im = sw<T>(n - k);
+      const cplx<T> A = row[ik];
+      const cplx<T> B = cconj(row[im]);
+      const cplx<T> S = cadd(A, B), D = csub(A, B);
+      const cplx<T> wD = cmul(w, D);
+      const cplx<T> Zk = {S.x - wD.y, S.y + wD.x};
+      if (k == half) {
+        row[ik] = cconj(Zk);
+      } else {
+        // partner: A' = X[n-k], B' = conj X[k], w' = exp(i pi (n-k)/n) = -conj(w)
+        const cplx<T> S2 = cconj(S);     // A' + B' = conj(A + B)
+        const cplx<T> D2 = {-D.x, D.y};  // A' - B' = -conj(D)
+        const cplx<T> wD2 = cmul(cplx<T>{-w.x, w.y}, D2);
+        const cplx<T> Zm = {S2.x - wD2.y, S2.y + wD2.x};
+        row[ik] = cconj(Zk);
+        row[im] = cconj(Zm);
+      }
+    }
+  }
+}
+
+// Hermitian post-pass of the real forward transform:
+// X[k] = (Z[k] + conj Z[n-k]) / 2 - (i / 2) exp(-i pi k / n) (Z[k] - conj Z[n-k])
+template <typename T, int RB, int NT>
+__device__ __forceinline__ void herm_post(cplx<T>* buf, int stride, const cplx<T>* __restrict__ tw,
+                                          int n) {
+  const int half = n >> 1;
+  for (int t = threadIdx.x; t < RB * (half + 1); t += NT) {
+    const int r = t / (half + 1), k = t - r * (half + 1);
+    cplx<T>* row = buf + r * stride;
+    if (k == 0) {
+      const cplx<T> z = row[0];
+      row[0] = {z.x + z.y, z.x - z.y};  // (X[0], X[n]), both real
+    } else {
+      const cplx<T> w = tw[k];
+      const int ik = sw<T>(k), im = sw<T>(n - k);
+      const cplx<T> A = row[ik];
+      const cplx<T> B = cconj(row[im]);
+      const cplx<T> S = cadd(A, B), D = csub(A, B);
+      const cplx<T> wD = cmul(w, D);
+      // X = S/2 - (i/2) wD = (S.x + wD.y, S.y - wD.x) / 2
+      const cplx<T> Xk = {T(0.5) * (S.x + wD.y), T(0.5) * (S.y - wD.x)};
+      if (k == half) {
+        row[ik] = Xk;
+      } else {
+        // partner twiddle exp(-i pi (n-k)/n) = -conj(w)
+        const cplx<T> S2 = cconj(S);
+        const cplx<T> D2 = {-D.x, D.y};
+        const cplx<T> wD2 = cmul(cplx<T>{-w.x, w.y}, D2);
+        row[im] = {T(0.5) * (S2.x + wD2.y), T(0.5) * (S2.y - wD2.x)};
+        row[ik] = Xk;
+      }
+    }
+  }
+}
+
 // two 512-thread blocks per CU (the LDS limit): at most 128 VGPRs.
 // TWL: stage twiddles staged in LDS after the row buffer.  LOGN > 0: the row
 // length n = 2^LOGN is a compile-time constant (a.n must equal it).
@@ -521,37 +593,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
     lds_barrier();
 #endif
     if constexpr (IN == IN_SPEC) {
-      // Hermitian pre-pass of the real inverse: with A = X[k], B = conj X[n-k],
-      // Z[k] = (A + B) + i exp(i pi k / n) (A - B); store conj Z for the
-      // inverse-by-forward FFT.  Pairs (k, n-k) are owned by one thread.
-      for (int t = threadIdx.x; t < RB * (half + 1); t += NT) {
-        const int r = t / (half + 1), k = t - r * (half + 1);
-        cplx<T>* row = buf + r * stride;
-        if (k == 0) {
-          const cplx<T> sv = row[0];  // (X[0], X[n]) both real
-          const T a0 = sv.x, an = sv.y;
-          row[0] = {a0 + an, -(a0 - an)};  // conj((a0 + an) + i (a0 - an))
-        } else {
-          const cplx<T> w = cconj(a.tw[k]);  // exp(+i pi k / n)
-          const int ik = sw<T>(k), im = sw<T>(n - k);
-          const cplx<T> A = row[ik];
-          const cplx<T> B = cconj(row[im]);
-          const cplx<T> S = cadd(A, B), D = csub(A, B);
-          const cplx<T> wD = cmul(w, D);
-          const cplx<T> Zk = {S.x - wD.y, S.y + wD.x};
-          if (k == half) {
-            row[ik] = cconj(Zk);
-          } else {
-            // partner: A' = X[n-k], B' = conj X[k], w' = exp(i pi (n-k)/n) = -conj(w)
-            const cplx<T> S2 = cconj(S);     // A' + B' = conj(A + B)
-            const cplx<T> D2 = {-D.x, D.y};  // A' - B' = -conj(D)
-            const cplx<T> wD2 = cmul(cplx<T>{-w.x, w.y}, D2);
-            const cplx<T> Zm = {S2.x - wD2.y, S2.y + wD2.x};
-            row[ik] = cconj(Zk);
-            row[im] = cconj(Zm);
-          }
-        }
-      }
+      herm_pre<T, RB, NT>(buf, stride, a.tw, n);
       lds_barrier();
       lds_fft_any<T, NT, EMAX, LOGN>(buf, logn, RB, stride, twr);
       // z = conj(buf): x[2m] = z.x, x[2m+1] = z.y for m < n/2 (image window)
@@ -595,35 +637,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
 
     if constexpr (OUT == OUT_SPEC || OUT == OUT_PSFTMP) {
       lds_fft_any<T, NT, EMAX, LOGN>(buf, logn, RB, stride, twr);
-      // Hermitian post-pass of the real forward transform:
-      // X[k] = (Z[k] + conj Z[n-k]) / 2 - (i / 2) exp(-i pi k / n) (Z[k] - conj Z[n-k])
-      for (int t = threadIdx.x; t < RB * (half + 1); t += NT) {
-        const int r = t / (half + 1), k = t - r * (half + 1);
-        cplx<T>* row = buf + r * stride;
-        if (k == 0) {
-          const cplx<T> z = row[0];
-          row[0] = {z.x + z.y, z.x - z.y};  // (X[0], X[n]), both real
-        } else {
-          const cplx<T> w = a.tw[k];
-          const int ik = sw<T>(k), im = sw<T>(n - k);
-          const cplx<T> A = row[ik];
-          const cplx<T> B = cconj(row[im]);
-          const cplx<T> S = cadd(A, B), D = csub(A, B);
-          const cplx<T> wD = cmul(w, D);
-          // X = S/2 - (i/2) wD = (S.x + wD.y, S.y - wD.x) / 2
-          const cplx<T> Xk = {T(0.5) * (S.x + wD.y), T(0.5) * (S.y - wD.x)};
-          if (k == half) {
-            row[ik] = Xk;
-          } else {
-            // partner twiddle exp(-i pi (n-k)/n) = -conj(w)
-            const cplx<T> S2 = cconj(S);
-            const cplx<T> D2 = {-D.x, D.y};
-            const cplx<T> wD2 = cmul(cplx<T>{-w.x, w.y}, D2);
-            row[im] = {T(0.5) * (S2.x + wD2.y), T(0.5) * (S2.y - wD2.x)};
-            row[ik] = Xk;
-          }
-        }
-      }
+      herm_post<T, RB, NT>(buf, stride, a.tw, n);
       lds_barrier();
       if constexpr (OUT == OUT_SPEC) {
         cplx<T>* sp = a.out_spec[set] + (size_t)band * n * n + i0;
@@ -798,14 +812,15 @@ constexpr int stage_table_off(int lognf, int upto) {
   return off;
 }
 
-// Stages DONE .. STOP-1 of a length-2^LOGNF transform of one sequence.
+// Stages DONE .. STOP-1 of `batch` length-2^LOGNF transforms.
 template <typename T, int NT, int EMAX, int LOGNF, int DONE, int OFF, int STOP>
-__device__ __forceinline__ void lds_fft_range(cplx<T>* buf, const cplx<T>* __restrict__ twtab) {
+__device__ __forceinline__ void lds_fft_range(cplx<T>* buf, int batch, int stride,
+                                              const cplx<T>* __restrict__ twtab) {
   if constexpr (DONE < STOP) {
     constexpr int LR = radix_log_c(LOGNF - DONE);
-    fft_stage_ct<T, (1 << LR), NT, EMAX, LOGNF, DONE>(buf, 1, 0, twtab + OFF);
+    fft_stage_ct<T, (1 << LR), NT, EMAX, LOGNF, DONE>(buf, batch, stride, twtab + OFF);
     constexpr int NOFF = DONE > 0 ? OFF + (1 << DONE) * ((1 << LR) - 1) : OFF;
-    lds_fft_range<T, NT, EMAX, LOGNF, DONE + LR, NOFF, STOP>(buf, twtab);
+    lds_fft_range<T, NT, EMAX, LOGNF, DONE + LR, NOFF, STOP>(buf, batch, stride, twtab);
   }
 }
 
@@ -824,23 +839,32 @@ __device__ __forceinline__ void stage_first_half(cplx<T>* buf, const cplx<T>* x)
   for (int r = 0; r < R; ++r) buf[sw<T>(base + r)] = v[r];
 }
 
-// Loads and twiddles of the last stage: butterfly j = threadIdx.x + q NT
-// takes elements j + r Ns.
-template <typename T, int NT, int LOGNF, int MAXQ, int R>
-__device__ __forceinline__ void stage_last_load(const cplx<T>* buf, const cplx<T>* __restrict__ tws,
-                                                cplx<T> (&v)[MAXQ][R]) {
+// Loads and twiddles of the last stage: butterfly t = threadIdx.x + q NT
+// is butterfly j = t mod Ns of sequence t / Ns and takes its elements
+// j + r Ns; lst_slot gives the LDS slot of element j + r Ns of sequence b.
+template <typename T, int LOGNF, int R>
+__device__ __forceinline__ int lst_slot(int b, int j, int r, int stride) {
   constexpr int NS = 1 << last_stage_done(LOGNF);
   constexpr int S = sw_shift<T>();
   static_assert((NS & ((1 << S) - 1)) == 0, "last-stage stride is a swizzle multiple");
+  return b * stride + sw<T>(j) + r * NS + ((r * NS) >> S);
+}
+
+template <typename T, int NT, int LOGNF, int MAXQ, int R>
+__device__ __forceinline__ void stage_last_load(const cplx<T>* buf, int stride,
+                                                const cplx<T>* __restrict__ tws,
+                                                cplx<T> (&v)[MAXQ][R]) {
+  constexpr int DL = last_stage_done(LOGNF);
+  constexpr int NS = 1 << DL;
   cplx<T> w[MAXQ][R - 1];
 #pragma unroll
   for (int q = 0; q < MAXQ; ++q) {
-    const int j = threadIdx.x + q * NT;
+    const int t = threadIdx.x + q * NT;
+    const int b = t >> DL, j = t & (NS - 1);
 #pragma unroll
     for (int r = 1; r < R; ++r) w[q][r - 1] = tws[j * (R - 1) + r - 1];
-    const int sj = sw<T>(j);
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[q][r] = buf[sj + r * NS + ((r * NS) >> S)];
+    for (int r = 0; r < R; ++r) v[q][r] = buf[lst_slot<T, LOGNF, R>(b, j, r, stride)];
   }
 #pragma unroll
   for (int q = 0; q < MAXQ; ++q) {
@@ -857,19 +881,17 @@ __device__ __forceinline__ void stage_last_fwd(cplx<T>* buf, const cplx<T>* __re
                                                const cplx<T>* Ks, bool mul) {
   constexpr int DL = last_stage_done(LOGNF);
   constexpr int R = 1 << (LOGNF - DL), NS = 1 << DL, MAXQ = NS / NT;
-  constexpr int S = sw_shift<T>();
   static_assert(NS % NT == 0, "whole last-stage butterflies per thread");
   cplx<T> v[MAXQ][R];
-  stage_last_load<T, NT, LOGNF, MAXQ, R>(buf, tws, v);
+  stage_last_load<T, NT, LOGNF, MAXQ, R>(buf, 0, tws, v);
 #pragma unroll
   for (int q = 0; q < MAXQ; ++q) {
     const int j = threadIdx.x + q * NT;
-    const int sj = sw<T>(j);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       cplx<T> x = v[q][r];
       if (mul) x = cconj(cmul(x, Ks[j + r * NS]));
-      buf[sj + r * NS + ((r * NS) >> S)] = x;
+      buf[lst_slot<T, LOGNF, R>(0, j, r, 0)] = x;
     }
   }
   lds_barrier();
@@ -883,7 +905,7 @@ __device__ __forceinline__ void stage_last_out(const cplx<T>* buf, const cplx<T>
   constexpr int DL = last_stage_done(LOGNF);
   constexpr int R = 1 << (LOGNF - DL), NS = 1 << DL, MAXQ = NS / NT;
   cplx<T> v[MAXQ][R];
-  stage_last_load<T, NT, LOGNF, MAXQ, R>(buf, tws, v);
+  stage_last_load<T, NT, LOGNF, MAXQ, R>(buf, 0, tws, v);
 #pragma unroll
   for (int q = 0; q < MAXQ; ++q) {
     const int j = threadIdx.x + q * NT;
@@ -937,7 +959,7 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 4) col_pass_pruned(Co
       for (int q = 0; q < IPT; ++q) pre[q] = a.in[set + 1][col_off + threadIdx.x + q * NT];
     }
     lds_barrier();
-    lds_fft_range<T, NT, EMAX, LOGNF, radix_log_c(LOGNF), 0, DL>(buf, twc);
+    lds_fft_range<T, NT, EMAX, LOGNF, radix_log_c(LOGNF), 0, DL>(buf, 1, 0, twc);
     stage_last_fwd<T, NT, LOGNF>(buf, twc + OFFL, Ks, !slot0);
     if (slot0) {
       for (int ky = threadIdx.x; ky <= N; ky += NT) {
@@ -963,9 +985,158 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 4) col_pass_pruned(Co
       }
       lds_barrier();
     }
-    lds_fft_range<T, NT, EMAX, LOGNF, 0, 0, DL>(buf, twc);
+    lds_fft_range<T, NT, EMAX, LOGNF, 0, 0, DL>(buf, 1, 0, twc);
     stage_last_out<T, NT, LOGNF>(buf, twc + OFFL, a.out[set] + col_off);
     lds_barrier();  // the next set's first stage overwrites buf
+  }
+}
+
+// ---- row passes with pruned end stages (n = 2^LOGN at compile time) ----
+// IN_REAL: the first stage is computed from the loaded image pairs (the
+// padded upper half of every row is zero), with no staging of the input in
+// LDS.  IN_SPEC -> OUT_REAL: the last inverse stage produces only the image
+// window (m < n/2) and stores it straight to global memory.  IN_SPEC ->
+// OUT_SPEC (inverse, crop, forward): the last inverse stage writes the
+// window back in place (conjugated; the residual of set 0 accumulated from
+// it), and the forward transform's first stage reads only that half.
+template <typename T, int RB, int NT, int IN, int OUT, bool TWL, int LOGN>
+__global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass_pruned(RowArgs<T> a) {
+  static_assert(IN != IN_PSF && OUT != OUT_PSFTMP && LOGN > 0, "image rows of a fixed length");
+  constexpr int N = 1 << LOGN, HALF = N / 2;
+  constexpr int EMAX = RB * N;
+  constexpr int LR0 = radix_log_c(LOGN), R0 = 1 << LR0, NB0 = N / R0;  // first stage
+  constexpr int Q0 = RB * NB0 / NT;
+  static_assert(RB * NB0 % NT == 0, "whole first-stage butterflies per thread");
+  constexpr int DL = last_stage_done(LOGN), RL = 1 << (LOGN - DL), NSL = 1 << DL;
+  constexpr int QL = RB * NSL / NT;
+  static_assert(RB * NSL % NT == 0, "whole last-stage butterflies per thread");
+  constexpr int OFFL = stage_table_off(LOGN, DL);
+  constexpr int stride = sw_stride<T>(N);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  __shared__ double red[NT / 64];
+  const int lb = xcd_remap(blockIdx.x, a.nblocks);
+  if (lb >= a.nblocks) return;
+  constexpr int rblocks = N / RB;
+  const int band = lb / rblocks;
+  const int i0 = (lb - band * rblocks) * RB;
+  const cplx<T>* twr;
+  if constexpr (TWL) {
+    cplx<T>* twl = buf + RB * stride;
+    tables_to_lds<T, NT>(twl, a.twr, stage_table_len(LOGN));
+    twr = twl;  // made visible by the first barrier
+  } else {
+    twr = a.twr;
+  }
+  // first forward stage from v[q][r] = element j + r NB0 (r < R0/2) of row b
+  auto first_store = [&](cplx<T> (&v)[Q0][R0]) {
+#pragma unroll
+    for (int q = 0; q < Q0; ++q) {
+      const int t = threadIdx.x + q * NT;
+      const int b = t / NB0, j = t - b * NB0;
+#pragma unroll
+      for (int r = R0 / 2; r < R0; ++r) v[q][r] = cplx<T>{T(0), T(0)};
+      dft_small<T, R0>(v[q]);
+#pragma unroll
+      for (int r = 0; r < R0; ++r) buf[b * stride + sw<T>(j * R0 + r)] = v[q][r];
+    }
+  };
+  for (int set = 0; set < a.nsets; ++set) {
+    if constexpr (IN == IN_REAL) {
+      cplx<T> v[Q0][R0];
+#pragma unroll
+      for (int q = 0; q < Q0; ++q) {
+        const int t = threadIdx.x + q * NT;
+        const int b = t / NB0, j = t - b * NB0;
+        const T* row = a.in[set] + ((size_t)band * N + i0 + b) * N;
+#pragma unroll
+        for (int r = 0; r < R0 / 2; ++r)
+          v[q][r] = *reinterpret_cast<const cplx<T>*>(row + 2 * (j + r * NB0));
+      }
+      first_store(v);
+      lds_barrier();
+      lds_fft_range<T, NT, EMAX, LOGN, LR0, 0, LOGN>(buf, RB, stride, twr);
+    } else {
+      constexpr int U = 4;
+      for (int t0 = threadIdx.x; t0 < EMAX; t0 += U * NT) {
+        cplx<T> v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          v[u] = row_input<T, RB, NT, IN>(a, set, band, i0, min(t0 + u * NT, EMAX - 1), N, LOGN);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int t = t0 + u * NT;
+          if (t < EMAX) buf[row_slot<T, RB, IN>(t, N, LOGN, stride)] = v[u];
+        }
+      }
+      lds_barrier();
+      herm_pre<T, RB, NT>(buf, stride, a.tw, N);
+      lds_barrier();
+      lds_fft_range<T, NT, EMAX, LOGN, 0, 0, DL>(buf, RB, stride, twr);
+      cplx<T> v[QL][RL];
+      stage_last_load<T, NT, LOGN, QL, RL>(buf, stride, twr + OFFL, v);
+      if constexpr (OUT == OUT_REAL) {
+        // z = conj(inverse): x[2m] = z.x, x[2m+1] = z.y for m < n/2
+#pragma unroll
+        for (int q = 0; q < QL; ++q) {
+          const int t = threadIdx.x + q * NT;
+          const int b = t >> DL, j = t & (NSL - 1);
+          T* o = a.out[set] + ((size_t)band * N + i0 + b) * N;
+#pragma unroll
+          for (int r = 0; r < RL / 2; ++r) {
+            const cplx<T> z = v[q][r];
+            *reinterpret_cast<cplx<T>*>(o + 2 * (j + r * NSL)) = cplx<T>{z.x, -z.y};
+          }
+        }
+        lds_barrier();
+      } else {
+        double acc = 0.0;
+        const T* y = (a.y != nullptr && set == 0) ? a.y + ((size_t)band * N + i0) * N : nullptr;
+#pragma unroll
+        for (int q = 0; q < QL; ++q) {
+          const int t = threadIdx.x + q * NT;
+          const int b = t >> DL, j = t & (NSL - 1);
+#pragma unroll
+          for (int r = 0; r < RL / 2; ++r) {
+            const cplx<T> z = cconj(v[q][r]);
+            if (y != nullptr) {
+              const T* yq = y + (size_t)b * N + 2 * (j + r * NSL);
+              const double e0 = double(z.x) - double(yq[0]);
+              const double e1 = double(z.y) - double(yq[1]);
+              acc += e0 * e0 + e1 * e1;
+            }
+            buf[lst_slot<T, LOGN, RL>(b, j, r, stride)] = z;
+          }
+        }
+        if (a.partials != nullptr && set == 0) {
+          const double sum = block_sum<NT>(acc, red);
+          if (threadIdx.x == 0) a.partials[lb] = sum;
+        }
+        lds_barrier();
+        cplx<T> u[Q0][R0];
+#pragma unroll
+        for (int q = 0; q < Q0; ++q) {
+          const int t = threadIdx.x + q * NT;
+          const int b = t / NB0, j = t - b * NB0;
+#pragma unroll
+          for (int r = 0; r < R0 / 2; ++r) u[q][r] = buf[b * stride + sw<T>(j + r * NB0)];
+        }
+        lds_barrier();
+        first_store(u);
+        lds_barrier();
+        lds_fft_range<T, NT, EMAX, LOGN, LR0, 0, LOGN>(buf, RB, stride, twr);
+      }
+    }
+    if constexpr (OUT == OUT_SPEC) {
+      herm_post<T, RB, NT>(buf, stride, a.tw, N);
+      lds_barrier();
+      cplx<T>* sp = a.out_spec[set] + (size_t)band * N * N + i0;
+      for (int t = threadIdx.x; t < EMAX; t += NT) {
+        const int kx = t / RB, r = t - kx * RB;
+        sp[(size_t)kx * N + r] = buf[r * stride + sw<T>(kx)];
+      }
+      lds_barrier();
+    }
   }
 }
 
@@ -1078,8 +1249,8 @@ static int launch_row_rb(RowArgs<T>& a, int nsets, hipStream_t s) {
   // (row blocks at n = 1024: 8 rows in FP32, 4 in FP64)
   if constexpr (IN != IN_PSF && RB == (F32 ? 8 : 4)) {
     if (n == 1024) {
-      MUFFIN_ALLOW_BIG_LDS((row_pass<T, RB, kRowNT, IN, OUT, F32, 10>));
-      row_pass<T, RB, kRowNT, IN, OUT, F32, 10><<<grid, kRowNT, F32 ? shm_t : shm, s>>>(a);
+      MUFFIN_ALLOW_BIG_LDS((row_pass_pruned<T, RB, kRowNT, IN, OUT, F32, 10>));
+      row_pass_pruned<T, RB, kRowNT, IN, OUT, F32, 10><<<grid, kRowNT, F32 ? shm_t : shm, s>>>(a);
       MUFFIN_HIP_CHECK(hipGetLastError());
       return 0;
     }
