@@ -221,9 +221,13 @@ __device__ __forceinline__ int sw_plus(int x, int swx) {
     return sw<T>(x + C);
 }
 
-template <typename T, int R, int NT, int EMAX, int LOGNF, int LOGNS>
+// RTW: the twiddles come from wreg[r - 1] (registers): k = j mod Ns is then
+// the same for all of a thread's butterflies (Ns divides NT).
+template <typename T, int R, int NT, int EMAX, int LOGNF, int LOGNS, bool RTW = false>
 __device__ __forceinline__ void fft_stage_ct(cplx<T>* buf, int batch, int stride,
-                                             const cplx<T>* __restrict__ tws) {
+                                             const cplx<T>* __restrict__ tws,
+                                             const cplx<T>* wreg = nullptr) {
+  static_assert(!RTW || NT % (1 << LOGNS) == 0, "register twiddles need Ns | NT");
   constexpr int MAXQ = (EMAX / R + NT - 1) / NT;
   constexpr int LOGR = R == 2 ? 1 : (R == 4 ? 2 : 3);
   constexpr int LOGNBF = LOGNF - LOGR;
@@ -238,7 +242,7 @@ __device__ __forceinline__ void fft_stage_ct(cplx<T>* buf, int batch, int stride
     const int t = threadIdx.x + q * NT;
     if (t < total) {
       const int b = t >> LOGNBF, j = t & (NBF - 1);
-      if constexpr (HOIST && LOGNS > 0) {
+      if constexpr (HOIST && LOGNS > 0 && !RTW) {
         const cplx<T>* tw = tws + (j & (NS - 1)) * (R - 1);
 #pragma unroll
         for (int r = 1; r < R; ++r) w[q][r - 1] = tw[r - 1];
@@ -267,7 +271,10 @@ __device__ __forceinline__ void fft_stage_ct(cplx<T>* buf, int batch, int stride
       const int b = t >> LOGNBF, j = t & (NBF - 1);
       const int k = j & (NS - 1);
       if constexpr (LOGNS > 0) {
-        if constexpr (HOIST) {
+        if constexpr (RTW) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], wreg[r - 1]);
+        } else if constexpr (HOIST) {
 #pragma unroll
           for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[q][r - 1]);
         } else {
@@ -850,19 +857,24 @@ __device__ __forceinline__ int lst_slot(int b, int j, int r, int stride) {
   return b * stride + sw<T>(j) + r * NS + ((r * NS) >> S);
 }
 
-template <typename T, int NT, int LOGNF, int MAXQ, int R>
+// RTW: twiddles from wreg[(q mod QW) (R - 1) + r - 1], QW = max(1, Ns / NT)
+// (the distinct butterflies of a thread; see last_tw_regs).
+template <typename T, int NT, int LOGNF, int MAXQ, int R, bool RTW = false>
 __device__ __forceinline__ void stage_last_load(const cplx<T>* buf, int stride,
                                                 const cplx<T>* __restrict__ tws,
-                                                cplx<T> (&v)[MAXQ][R]) {
+                                                cplx<T> (&v)[MAXQ][R],
+                                                const cplx<T>* wreg = nullptr) {
   constexpr int DL = last_stage_done(LOGNF);
   constexpr int NS = 1 << DL;
+  constexpr int QW = NS > NT ? NS / NT : 1;
   cplx<T> w[MAXQ][R - 1];
 #pragma unroll
   for (int q = 0; q < MAXQ; ++q) {
     const int t = threadIdx.x + q * NT;
     const int b = t >> DL, j = t & (NS - 1);
 #pragma unroll
-    for (int r = 1; r < R; ++r) w[q][r - 1] = tws[j * (R - 1) + r - 1];
+    for (int r = 1; r < R; ++r)
+      w[q][r - 1] = RTW ? wreg[(q % QW) * (R - 1) + r - 1] : tws[j * (R - 1) + r - 1];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[q][r] = buf[lst_slot<T, LOGNF, R>(b, j, r, stride)];
   }
@@ -991,6 +1003,45 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 4) col_pass_pruned(Co
   }
 }
 
+// Twiddles of a thread's butterflies in the stage with Ns = 2^LOGNS when
+// they are the same for all of them (Ns | NT), and of the last stage (QW
+// distinct butterflies), read once from the stage tables into registers.
+template <typename T, int R, int NT, int LOGNS>
+__device__ __forceinline__ void stage_tw_regs(const cplx<T>* __restrict__ tws, cplx<T> (&w)[R - 1]) {
+  static_assert(NT % (1 << LOGNS) == 0, "register twiddles need Ns | NT");
+  const int k = threadIdx.x & ((1 << LOGNS) - 1);
+#pragma unroll
+  for (int r = 1; r < R; ++r) w[r - 1] = tws[k * (R - 1) + r - 1];
+}
+template <typename T, int NT, int LOGNF, int QW, int R>
+__device__ __forceinline__ void last_tw_regs(const cplx<T>* __restrict__ tws, cplx<T> (&w)[QW * (R - 1)]) {
+  constexpr int NS = 1 << last_stage_done(LOGNF);
+#pragma unroll
+  for (int q = 0; q < QW; ++q) {
+    const int j = (threadIdx.x + q * NT) & (NS - 1);
+#pragma unroll
+    for (int r = 1; r < R; ++r) w[q * (R - 1) + r - 1] = tws[j * (R - 1) + r - 1];
+  }
+}
+
+// The schedule of a length-2^LOGNF transform as first stage, two middle
+// stages and the last stage (the lengths 1024 and 2048 of the image side
+// 1024); Dk is the log2 of Ns of stage k, Rk its radix, OFFk the offset of
+// its twiddles in the stage tables.
+template <int LOGNF>
+struct Sched4 {
+  static constexpr int D1 = radix_log_c(LOGNF);
+  static constexpr int R0 = 1 << D1;
+  static constexpr int R1 = 1 << radix_log_c(LOGNF - D1);
+  static constexpr int D2 = D1 + radix_log_c(LOGNF - D1);
+  static constexpr int R2 = 1 << radix_log_c(LOGNF - D2);
+  static constexpr int DL = D2 + radix_log_c(LOGNF - D2);
+  static constexpr int RL = 1 << (LOGNF - DL);
+  static constexpr int OFF2 = stage_table_off(LOGNF, D2);
+  static constexpr int OFFL = stage_table_off(LOGNF, DL);
+  static_assert(DL == last_stage_done(LOGNF), "four stages");
+};
+
 // ---- row passes with pruned end stages (n = 2^LOGN at compile time) ----
 // IN_REAL: the first stage is computed from the loaded image pairs (the
 // padded upper half of every row is zero), with no staging of the input in
@@ -998,7 +1049,10 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 4) col_pass_pruned(Co
 // window (m < n/2) and stores it straight to global memory.  IN_SPEC ->
 // OUT_SPEC (inverse, crop, forward): the last inverse stage writes the
 // window back in place (conjugated; the residual of set 0 accumulated from
-// it), and the forward transform's first stage reads only that half.
+// it), and the forward transform's first stage reads only that half.  RT
+// (FP32 passes with one transform): every twiddle of a thread stays in
+// registers (Ns divides NT in every stage after the first) and no tables
+// are read per set; the middle pass, with two transforms, would spill them.
 template <typename T, int RB, int NT, int IN, int OUT, bool TWL, int LOGN>
 __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass_pruned(RowArgs<T> a) {
   static_assert(IN != IN_PSF && OUT != OUT_PSFTMP && LOGN > 0, "image rows of a fixed length");
@@ -1028,6 +1082,33 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass_pruned(RowArgs<T> a
   } else {
     twr = a.twr;
   }
+  constexpr bool RT = sizeof(T) == 4 && !(IN == IN_SPEC && OUT == OUT_SPEC);
+  using S4 = Sched4<LOGN>;
+  cplx<T> w1[S4::R1 - 1], w2[S4::R2 - 1], wl[RL - 1];
+  if constexpr (RT) {
+    stage_tw_regs<T, S4::R1, NT, S4::D1>(a.twr, w1);
+    stage_tw_regs<T, S4::R2, NT, S4::D2>(a.twr + S4::OFF2, w2);
+    stage_tw_regs<T, RL, NT, DL>(a.twr + OFFL, wl);
+  }
+  // stages after the first, and the stages before the last
+  auto fwd_rest = [&]() {
+    if constexpr (RT) {
+      fft_stage_ct<T, S4::R1, NT, EMAX, LOGN, S4::D1, true>(buf, RB, stride, nullptr, w1);
+      fft_stage_ct<T, S4::R2, NT, EMAX, LOGN, S4::D2, true>(buf, RB, stride, nullptr, w2);
+      fft_stage_ct<T, RL, NT, EMAX, LOGN, DL, true>(buf, RB, stride, nullptr, wl);
+    } else {
+      lds_fft_range<T, NT, EMAX, LOGN, LR0, 0, LOGN>(buf, RB, stride, twr);
+    }
+  };
+  auto inv_head = [&]() {
+    if constexpr (RT) {
+      fft_stage_ct<T, S4::R0, NT, EMAX, LOGN, 0>(buf, RB, stride, nullptr);
+      fft_stage_ct<T, S4::R1, NT, EMAX, LOGN, S4::D1, true>(buf, RB, stride, nullptr, w1);
+      fft_stage_ct<T, S4::R2, NT, EMAX, LOGN, S4::D2, true>(buf, RB, stride, nullptr, w2);
+    } else {
+      lds_fft_range<T, NT, EMAX, LOGN, 0, 0, DL>(buf, RB, stride, twr);
+    }
+  };
   // first forward stage from v[q][r] = element j + r NB0 (r < R0/2) of row b
   auto first_store = [&](cplx<T> (&v)[Q0][R0]) {
 #pragma unroll
@@ -1055,7 +1136,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass_pruned(RowArgs<T> a
       }
       first_store(v);
       lds_barrier();
-      lds_fft_range<T, NT, EMAX, LOGN, LR0, 0, LOGN>(buf, RB, stride, twr);
+      fwd_rest();
     } else {
       constexpr int U = 4;
       for (int t0 = threadIdx.x; t0 < EMAX; t0 += U * NT) {
@@ -1072,9 +1153,9 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass_pruned(RowArgs<T> a
       lds_barrier();
       herm_pre<T, RB, NT>(buf, stride, a.tw, N);
       lds_barrier();
-      lds_fft_range<T, NT, EMAX, LOGN, 0, 0, DL>(buf, RB, stride, twr);
+      inv_head();
       cplx<T> v[QL][RL];
-      stage_last_load<T, NT, LOGN, QL, RL>(buf, stride, twr + OFFL, v);
+      stage_last_load<T, NT, LOGN, QL, RL, RT>(buf, stride, twr + OFFL, v, wl);
       if constexpr (OUT == OUT_REAL) {
         // z = conj(inverse): x[2m] = z.x, x[2m+1] = z.y for m < n/2
 #pragma unroll
@@ -1124,7 +1205,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass_pruned(RowArgs<T> a
         lds_barrier();
         first_store(u);
         lds_barrier();
-        lds_fft_range<T, NT, EMAX, LOGN, LR0, 0, LOGN>(buf, RB, stride, twr);
+        fwd_rest();
       }
     }
     if constexpr (OUT == OUT_SPEC) {
@@ -1137,6 +1218,111 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass_pruned(RowArgs<T> a
       }
       lds_barrier();
     }
+  }
+}
+
+// Pruned column pass with every twiddle and the block's column of K (or
+// conj K) in registers: per state set the only LDS traffic is the
+// transform's own exchanges (no twiddle or K reads), and the block keeps no
+// tables in LDS.
+template <typename T, int NT, int LOGN>
+__global__ void __launch_bounds__(NT, 4) col_pass_rt(ColArgs<T> a) {
+  constexpr int LOGNF = LOGN + 1, N = 1 << LOGN, M2 = 2 * N;
+  using S4 = Sched4<LOGNF>;
+  constexpr int IPT = S4::R0 / 2;  // inputs per thread
+  static_assert(N == IPT * NT, "the first stage's inputs are the loaded values");
+  constexpr int EMAX = M2;
+  constexpr int DL = S4::DL, RL = S4::RL, NS = 1 << DL;
+  constexpr int QL = NS / NT;  // last-stage butterflies per thread (distinct)
+  static_assert(NS % NT == 0, "whole last-stage butterflies per thread");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int lb = xcd_remap(blockIdx.x, a.nblocks);
+  if (lb >= a.nblocks) return;
+  const int band = lb >> LOGN;
+  const int kx0 = lb - (band << LOGN);
+  const cplx<T>* Kb = a.Kh + (size_t)band * (N + 1) * M2;
+  const cplx<T>* Kc = Kb + (size_t)kx0 * M2;
+  const size_t col_off = ((size_t)band * N + kx0) * N;
+  cplx<T> pre[IPT];
+#pragma unroll
+  for (int q = 0; q < IPT; ++q) pre[q] = a.in[0][col_off + threadIdx.x + q * NT];
+  cplx<T> w1[S4::R1 - 1], w2[S4::R2 - 1], wl[QL * (RL - 1)];
+  stage_tw_regs<T, S4::R1, NT, S4::D1>(a.twc, w1);
+  stage_tw_regs<T, S4::R2, NT, S4::D2>(a.twc + S4::OFF2, w2);
+  last_tw_regs<T, NT, LOGNF, QL, RL>(a.twc + S4::OFFL, wl);
+  // slot 0 packs the two real columns kx = 0 and kx = n (see col_pass)
+  const bool slot0 = kx0 == 0;
+  cplx<T> kr[QL][RL];
+#pragma unroll
+  for (int q = 0; q < QL; ++q)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const cplx<T> k = Kc[threadIdx.x + q * NT + r * NS];
+      kr[q][r] = a.conj ? cconj(k) : k;
+    }
+  for (int set = 0; set < a.nsets; ++set) {
+    stage_first_half<T, NT, LOGNF>(buf, pre);
+    if (set + 1 < a.nsets) {
+#pragma unroll
+      for (int q = 0; q < IPT; ++q) pre[q] = a.in[set + 1][col_off + threadIdx.x + q * NT];
+    }
+    lds_barrier();
+    fft_stage_ct<T, S4::R1, NT, EMAX, LOGNF, S4::D1, true>(buf, 1, 0, nullptr, w1);
+    fft_stage_ct<T, S4::R2, NT, EMAX, LOGNF, S4::D2, true>(buf, 1, 0, nullptr, w2);
+    {
+      cplx<T> v[QL][RL];
+      stage_last_load<T, NT, LOGNF, QL, RL, true>(buf, 0, nullptr, v, wl);
+#pragma unroll
+      for (int q = 0; q < QL; ++q) {
+        const int j = threadIdx.x + q * NT;
+#pragma unroll
+        for (int r = 0; r < RL; ++r)
+          buf[lst_slot<T, LOGNF, RL>(0, j, r, 0)] = slot0 ? v[q][r] : cconj(cmul(v[q][r], kr[q][r]));
+      }
+      lds_barrier();
+    }
+    if (slot0) {
+      for (int ky = threadIdx.x; ky <= N; ky += NT) {
+        const int kz = (M2 - ky) & (M2 - 1);
+        const int iy = sw<T>(ky), iz = sw<T>(kz);
+        const cplx<T> F = buf[iy], Fm = buf[iz];
+        cplx<T> K0 = Kc[ky], K0m = Kc[kz];
+        cplx<T> Kn = Kb[(size_t)N * M2 + ky], Knm = Kb[(size_t)N * M2 + kz];
+        if (a.conj) {
+          K0 = cconj(K0);
+          K0m = cconj(K0m);
+          Kn = cconj(Kn);
+          Knm = cconj(Knm);
+        }
+        const cplx<T> Sp = cadd(F, cconj(Fm)), Dp = csub(F, cconj(Fm));
+        cplx<T> G = cadd(cmul(Sp, K0), cmul(Dp, Kn));
+        G = {T(0.5) * G.x, T(0.5) * G.y};
+        if (kz != ky) {
+          const cplx<T> Sm = cadd(Fm, cconj(F)), Dm = csub(Fm, cconj(F));
+          cplx<T> Gm = cadd(cmul(Sm, K0m), cmul(Dm, Knm));
+          Gm = {T(0.5) * Gm.x, T(0.5) * Gm.y};
+          buf[iz] = cconj(Gm);
+        }
+        buf[iy] = cconj(G);
+      }
+      lds_barrier();
+    }
+    fft_stage_ct<T, S4::R0, NT, EMAX, LOGNF, 0>(buf, 1, 0, nullptr);
+    fft_stage_ct<T, S4::R1, NT, EMAX, LOGNF, S4::D1, true>(buf, 1, 0, nullptr, w1);
+    fft_stage_ct<T, S4::R2, NT, EMAX, LOGNF, S4::D2, true>(buf, 1, 0, nullptr, w2);
+    {
+      cplx<T> v[QL][RL];
+      stage_last_load<T, NT, LOGNF, QL, RL, true>(buf, 0, nullptr, v, wl);
+      cplx<T>* dst = a.out[set] + col_off;
+#pragma unroll
+      for (int q = 0; q < QL; ++q) {
+        const int j = threadIdx.x + q * NT;
+#pragma unroll
+        for (int r = 0; r < RL / 2; ++r) dst[j + r * NS] = cconj(v[q][r]);
+      }
+    }
+    lds_barrier();  // the next set's first stage overwrites buf
   }
 }
 
@@ -1249,8 +1435,11 @@ static int launch_row_rb(RowArgs<T>& a, int nsets, hipStream_t s) {
   // (row blocks at n = 1024: 8 rows in FP32, 4 in FP64)
   if constexpr (IN != IN_PSF && RB == (F32 ? 8 : 4)) {
     if (n == 1024) {
-      MUFFIN_ALLOW_BIG_LDS((row_pass_pruned<T, RB, kRowNT, IN, OUT, F32, 10>));
-      row_pass_pruned<T, RB, kRowNT, IN, OUT, F32, 10><<<grid, kRowNT, F32 ? shm_t : shm, s>>>(a);
+      // tables in LDS only for the FP32 middle pass (the others keep their
+      // twiddles in registers, FP64 reads them from global memory)
+      constexpr bool TW = F32 && IN == IN_SPEC && OUT == OUT_SPEC;
+      MUFFIN_ALLOW_BIG_LDS((row_pass_pruned<T, RB, kRowNT, IN, OUT, TW, 10>));
+      row_pass_pruned<T, RB, kRowNT, IN, OUT, TW, 10><<<grid, kRowNT, TW ? shm_t : shm, s>>>(a);
       MUFFIN_HIP_CHECK(hipGetLastError());
       return 0;
     }
@@ -1312,8 +1501,14 @@ static int launch_col(const FftPlan<T>& p, const cplx<T>* const* in, cplx<T>* co
   if (p.n == 1024) {
     // one column per block: the pruned form
     if (a.B != 1) return -2; /* E_SHAPE */
-    MUFFIN_ALLOW_BIG_LDS((col_pass_pruned<T, 256, F32, 10>));
-    col_pass_pruned<T, 256, F32, 10><<<grid, 256, F32 ? shm_t : shm, s>>>(a);
+    if constexpr (F32) {
+      // twiddles and K in registers: only the transform buffer in LDS
+      const size_t shr = sizeof(cplx<T>) * (size_t)sw_stride<T>(2 * p.n);
+      col_pass_rt<T, 256, 10><<<grid, 256, shr, s>>>(a);
+    } else {
+      MUFFIN_ALLOW_BIG_LDS((col_pass_pruned<T, 256, F32, 10>));
+      col_pass_pruned<T, 256, F32, 10><<<grid, 256, F32 ? shm_t : shm, s>>>(a);
+    }
   } else if (2 * p.n <= 2048) {
     MUFFIN_ALLOW_BIG_LDS((col_pass<T, 256, F32, 0>));
     col_pass<T, 256, F32, 0><<<grid, 256, F32 ? shm_t : shm, s>>>(a);

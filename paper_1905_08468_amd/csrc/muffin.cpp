@@ -31,7 +31,7 @@
 #include <numeric>
 #include <vector>
 
-#include "../../include/muffin.h"
+#include "muffin.h"
 #include "internal.hpp"
 
 using namespace muffin;
