@@ -10,7 +10,7 @@
 // the product C (L x L) times Z (L x pixels): no transpose is needed.
 //
 // A block owns 64 (FP32) or 32 (FP64) pixels and all bands, staged in LDS;
-// its 4 waves split the output rows and run the two products on MFMA
+// its 8 waves split the output rows and run the two products on MFMA
 // 16x16x4 tiles (FP64 or FP32) with the v update in registers between them.
 // The DCT matrix is stored in MFMA fragment order so every operand load is one
 // coalesced 64-lane read.
@@ -72,7 +72,10 @@ struct DctArgs {
   int role, pure;
 };
 
-constexpr int kDctWaves = 4;
+#ifndef MUFFIN_DCT_WAVES
+#define MUFFIN_DCT_WAVES 8
+#endif
+constexpr int kDctWaves = MUFFIN_DCT_WAVES;  // waves per block of the FP32/FP64 kernel
 constexpr int kDctMaxKt = 16;  // Lp <= 256
 constexpr int kDctKtPerWave = kDctMaxKt / kDctWaves;
 
@@ -90,9 +93,13 @@ __device__ __forceinline__ int out_row(int lk, int r) {
   return sizeof(T) == 8 ? lk + 4 * r : 4 * lk + r;
 }
 
-// Block = 4 waves x (16 * G) pixels.  Wave w owns the output row tiles
-// w, w + 4, w + 8, w + 12 for every pixel group, so each A fragment (read
-// coalesced from the fragment-ordered matrix) feeds G MFMAs.
+// Block = kDctWaves waves x (16 * G) pixels.  Wave w owns the output row
+// tiles w, w + kDctWaves, ... for every pixel group, so each A fragment
+// (read coalesced from the fragment-ordered matrix) feeds G MFMAs.  Eight
+// waves (two output tiles each) rather than four: the block's 64 KB of LDS
+// allows two blocks per CU, and the per-wave accumulators then fit in 128
+// VGPRs, so a SIMD holds four waves instead of two to cover the latency of
+// the operand loads.
 template <typename T>
 __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_kernel(DctArgs<T> a) {
   typedef typename Acc4<T>::type acc_t;
@@ -339,13 +346,19 @@ struct DctBfArgs {
 
 constexpr int kBfPix = 64;   // pixels per block (4 groups of 16)
 constexpr int kBfG = 4;
+// waves per block; each takes kDctMaxKt / kBfWaves of the 16-band output tiles
+#ifndef MUFFIN_BF_WAVES
+#define MUFFIN_BF_WAVES 8
+#endif
+constexpr int kBfWaves = MUFFIN_BF_WAVES;
+constexpr int kBfKtPerWave = kDctMaxKt / kBfWaves;
 
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   hi = (__bf16)x;
   lo = (__bf16)(x - (float)hi);
 }
 
-__global__ void __launch_bounds__(64 * kDctWaves, 2) dct_bf16_kernel(DctBfArgs a) {
+__global__ void __launch_bounds__(64 * kBfWaves, 2) dct_bf16_kernel(DctBfArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int L = a.L, Lp = a.Lp, N = a.N;
   const int LpS = Lp + 8;  // padded band stride of the [pixel][band] tile
@@ -369,7 +382,7 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_bf16_kernel(DctBfArgs a
     // as one 16-byte hi and one 16-byte lo vector; the operands of the 8
     // bands are loaded unconditionally (clamped indices) before any is used
     const int total = (Lp / 8) * kBfPix;
-    for (int t = threadIdx.x; t < total; t += 64 * kDctWaves) {
+    for (int t = threadIdx.x; t < total; t += 64 * kBfWaves) {
       const int lg = t / kBfPix, j = t - lg * kBfPix;
       const int pix = pix0 + j;
       const int pc = min(pix, N - 1);
@@ -407,9 +420,9 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_bf16_kernel(DctBfArgs a
     }
   }
   lds_barrier();
-  flt4 acc[kDctKtPerWave][kBfG];
+  flt4 acc[kBfKtPerWave][kBfG];
 #pragma unroll
-  for (int i = 0; i < kDctKtPerWave; ++i)
+  for (int i = 0; i < kBfKtPerWave; ++i)
 #pragma unroll
     for (int g = 0; g < kBfG; ++g) acc[i][g] = flt4{0, 0, 0, 0};
   const bf16x8* Ah = a.pure == 2 ? a.Ah2 : a.Ah1;
@@ -423,8 +436,8 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_bf16_kernel(DctBfArgs a
       bl[g] = *reinterpret_cast<const bf16x8*>(Zl + o);
     }
 #pragma unroll
-    for (int i = 0; i < kDctKtPerWave; ++i) {
-      const int kt = wave + kDctWaves * i;
+    for (int i = 0; i < kBfKtPerWave; ++i) {
+      const int kt = wave + kBfWaves * i;
       if (kt < nkt) {
         const size_t f = ((size_t)kt * nks + ks) * 64 + lane;
         const bf16x8 ah = Ah[f], al = Al[f];
@@ -440,8 +453,8 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_bf16_kernel(DctBfArgs a
   if (a.pure) {
     float* out = a.V[set];
 #pragma unroll
-    for (int i = 0; i < kDctKtPerWave; ++i) {
-      const int kt = wave + kDctWaves * i;
+    for (int i = 0; i < kBfKtPerWave; ++i) {
+      const int kt = wave + kBfWaves * i;
       if (kt < nkt) {
 #pragma unroll
         for (int g = 0; g < kBfG; ++g) {
@@ -472,8 +485,8 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_bf16_kernel(DctBfArgs a
     al[g] = a.alpha ? (pix < N ? float(a.alpha[pix]) : 0.f) : 1.f;
   }
 #pragma unroll
-  for (int i = 0; i < kDctKtPerWave; ++i) {
-    const int kt = wave + kDctWaves * i;
+  for (int i = 0; i < kBfKtPerWave; ++i) {
+    const int kt = wave + kBfWaves * i;
     if (kt < nkt) {
       // phase 1: every operand of this k-tile in flight at once
       float vold[kBfG][4], vbv[kBfG][4];
@@ -525,7 +538,7 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_bf16_kernel(DctBfArgs a
   }
   lds_barrier();
 #pragma unroll
-  for (int i = 0; i < kDctKtPerWave; ++i)
+  for (int i = 0; i < kBfKtPerWave; ++i)
 #pragma unroll
     for (int g = 0; g < kBfG; ++g) acc[i][g] = flt4{0, 0, 0, 0};
   for (int ks = 0; ks < nks; ++ks) {
@@ -537,8 +550,8 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_bf16_kernel(DctBfArgs a
       bl[g] = *reinterpret_cast<const bf16x8*>(Zl + o);
     }
 #pragma unroll
-    for (int i = 0; i < kDctKtPerWave; ++i) {
-      const int lt = wave + kDctWaves * i;
+    for (int i = 0; i < kBfKtPerWave; ++i) {
+      const int lt = wave + kBfWaves * i;
       if (lt < nkt) {
         const size_t f = ((size_t)lt * nks + ks) * 64 + lane;
         const bf16x8 ah = a.Ah2[f], al2 = a.Al2[f];
@@ -553,8 +566,8 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_bf16_kernel(DctBfArgs a
   }
   float* To = a.Tout[set];
 #pragma unroll
-  for (int i = 0; i < kDctKtPerWave; ++i) {
-    const int lt = wave + kDctWaves * i;
+  for (int i = 0; i < kBfKtPerWave; ++i) {
+    const int lt = wave + kBfWaves * i;
     if (lt < nkt) {
 #pragma unroll
       for (int g = 0; g < kBfG; ++g) {
@@ -680,7 +693,7 @@ static int dct_update_bf16(const DctPlan<float>& p, const DctIO<float>& io, cons
   const size_t shm = 2 * sizeof(__bf16) * (size_t)kBfPix * (p.Lp + 8);
   dim3 grid((p.N + kBfPix - 1) / kBfPix, io.nsets);
   MUFFIN_ALLOW_BIG_LDS(dct_bf16_kernel);
-  dct_bf16_kernel<<<grid, 64 * kDctWaves, shm, s>>>(a);
+  dct_bf16_kernel<<<grid, 64 * kBfWaves, shm, s>>>(a);
   MUFFIN_HIP_CHECK(hipGetLastError());
   return 0;
 }
