@@ -231,6 +231,11 @@ struct AnArgs {
   double pure_scale;
 };
 
+// Row pitch of the row-filtered tile: odd, so the row filter's stores (four
+// rows of eight lanes, four values apart, per 32 lanes) hit distinct banks.
+template <int TO>
+constexpr int an_pitch() { return 2 * TO + 1; }
+
 // Row filter of basis p over the staged input: rowbuf[r][k] = low, [TO+k] = high.
 template <typename T, int TO, int NT, int PB>
 __device__ __forceinline__ void an_rows(const T* in, T* rowbuf, int IN) {
@@ -258,8 +263,8 @@ __device__ __forceinline__ void an_rows(const T* in, T* rowbuf, int IN) {
         lo += h[m] * w[2 * k + m];
         hi += g[m] * w[2 * k + m];
       }
-      rowbuf[r * (2 * TO) + k0 + k] = lo;
-      rowbuf[r * (2 * TO) + TO + k0 + k] = hi;
+      rowbuf[r * an_pitch<TO>() + k0 + k] = lo;
+      rowbuf[r * an_pitch<TO>() + TO + k0 + k] = hi;
     }
   }
 }
@@ -313,10 +318,10 @@ __device__ __forceinline__ void an_cols(const AnArgs<T>& a, const T* rowbuf, con
     g[k] = filt_g<T>(PB - 1, k);
   }
   const int q = threadIdx.x % (2 * TO), kp = threadIdx.x / (2 * TO);
-  const T* col = rowbuf + (4 * kp) * (2 * TO) + q;
+  const T* col = rowbuf + (4 * kp) * an_pitch<TO>() + q;
   T w[TAPS + 2];
 #pragma unroll
-  for (int i = 0; i < TAPS + 2; ++i) w[i] = col[i * (2 * TO)];
+  for (int i = 0; i < TAPS + 2; ++i) w[i] = col[i * an_pitch<TO>()];
   auto update = [&](int i, T c) {
     const uint32_t bo = ln.uoff[i] * (uint32_t)sizeof(T);
     if (a.pure) {
@@ -358,7 +363,7 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_an(AnArgs<T> a) {
   static_assert((TO / 2) * (2 * TO) == NT, "one thread per column-filter output quad");
   constexpr int IN = 2 * TO + kHalo;
   __shared__ T s_in[IN * IN];
-  __shared__ T s_row[IN * 2 * TO];
+  __shared__ T s_row[IN * an_pitch<TO>()];
   const int lb = xcd_remap_d(blockIdx.x, a.nblocks);
   if (lb >= a.nblocks) return;
   const int tiles2 = a.tiles * a.tiles;
@@ -517,6 +522,9 @@ struct SyArgs {
 template <int TC, int NT, int APT_, int BPT_>
 struct SyLanes {
   static constexpr int W = TC + kSHal;
+  // row pitch of rbuf: odd, so the row pass's reads (8 rows x 8 lanes per
+  // wave, 4 values apart within a row) spread over all banks
+  static constexpr int RP = 2 * W + 1;
   static constexpr int APT = APT_;
   static constexpr int BPT = BPT_;
   static constexpr int NA = TC / APT;
@@ -534,14 +542,14 @@ struct SyLanes {
     const int cc = hf ? col - W : col;
     ql = (hf ? 2 : 0) * W * W + a0 * W + cc;
     qh = ql + W * W;
-    rout = (2 * a0) * (2 * W) + col;
+    rout = (2 * a0) * RP + col;
     const int ri = t / (TC / BPT), b0 = (t % (TC / BPT)) * BPT;
-    rc = ri * (2 * W) + b0;
+    rc = ri * RP + b0;
   }
 };
 
 // Column synthesis of basis PB: from the four quadrants (low/high rows of the
-// c and d column halves) into rbuf[2TC][2 (TC + HAL)].  Each thread slides
+// c and d column halves) into rbuf[2TC][2 (TC + HAL) + 1].  Each thread slides
 // over APT consecutive coefficient rows, so every LDS value it loads feeds
 // several outputs.  Window entry i holds coefficient row a0 + HAL + 1 - PB + i
 // (output a - a0 uses entries a - a0 - e + PB - 1, e < PB), so every LDS
@@ -584,8 +592,8 @@ __device__ __forceinline__ void sy_cols(const T* q, T* rbuf, const Lanes& ln) {
         od = fma(ho[e], l, od);
         od = fma(go[e], hh, od);
       }
-      out[(2 * a) * (2 * W)] = ev;
-      out[(2 * a + 1) * (2 * W)] = od;
+      out[(2 * a) * Lanes::RP] = ev;
+      out[(2 * a + 1) * Lanes::RP] = od;
     }
   }
 }
@@ -783,7 +791,7 @@ template <typename T, int TC, int NT, int APT, int BPT, bool DEEP, int PN>
 __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_sy(SyArgs<T> a) {
   constexpr int W = TC + kSHal;
   __shared__ T s_q[4 * W * W];
-  __shared__ T s_r[2 * TC * 2 * W];
+  __shared__ T s_r[2 * TC * (2 * W + 1)];
   const int lb = xcd_remap_d(blockIdx.x, a.nblocks);
   if (lb >= a.nblocks) return;
   sy_block<T, TC, NT, APT, BPT, DEEP, PN>(a, lb, s_q, s_r);
