@@ -84,12 +84,23 @@ __device__ __forceinline__ void dft_small(cplx<T>* v) {
   }
 }
 
-// LDS index swizzle: one padding element every 16 (FP32) or 8 (FP64)
-// complex values, which removes the bank conflicts of the strided Stockham
-// writes (checked with a bank model for every stage of 1024/2048 points).
+// LDS index swizzle: one padding element every 32 (FP32) or 8 (FP64)
+// complex values, which spreads the strided Stockham accesses over the
+// banks (periods of 8, 16, 32 and 64 FP32 values measured: 32 is the
+// fastest, 16 and 64 within 2 %, 8 far slower; FP64 8 and 16 alike).
+#ifndef MUFFIN_SW_SHIFT32
+#define MUFFIN_SW_SHIFT32 5
+#endif
+#ifndef MUFFIN_SW_SHIFT64
+#define MUFFIN_SW_SHIFT64 3
+#endif
+template <typename T>
+__host__ __device__ constexpr int sw_shift() {
+  return sizeof(T) == 8 ? MUFFIN_SW_SHIFT64 : MUFFIN_SW_SHIFT32;
+}
 template <typename T>
 __device__ __forceinline__ int sw(int x) {
-  return x + (x >> (sizeof(T) == 8 ? 3 : 4));
+  return x + (x >> sw_shift<T>());
 }
 template <typename T>
 __host__ __device__ constexpr int sw_stride(int nf) {
@@ -97,7 +108,7 @@ __host__ __device__ constexpr int sw_stride(int nf) {
   // 16 (FP64) complex values: the transposed accesses of the row passes
   // (consecutive threads walk across sequences, then along them) then hit
   // distinct banks
-  const int need = nf + ((nf - 1) >> (sizeof(T) == 8 ? 3 : 4));
+  const int need = nf + ((nf - 1) >> sw_shift<T>());
   const int mod = sizeof(T) == 8 ? 16 : 32, want = sizeof(T) == 8 ? 4 : 8;
   return need + ((want - need % mod) + mod) % mod;
 }
@@ -208,8 +219,6 @@ __device__ __forceinline__ void lds_fft(cplx<T>* buf, int lognf, int batch, int 
 // offsets of the LDS instructions.
 constexpr int radix_log_c(int rem) { return rem == 1 ? 1 : ((rem == 2 || rem == 4) ? 2 : 3); }
 
-template <typename T>
-constexpr int sw_shift() { return sizeof(T) == 8 ? 3 : 4; }
 
 template <typename T, int C>
 __device__ __forceinline__ int sw_plus(int x, int swx) {
