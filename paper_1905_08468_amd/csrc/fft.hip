@@ -1033,22 +1033,24 @@ __device__ __forceinline__ void last_tw_regs(const cplx<T>* __restrict__ tws, cp
   }
 }
 
-// The schedule of a length-2^LOGNF transform as first stage, two middle
-// stages and the last stage (the lengths 1024 and 2048 of the image side
-// 1024); Dk is the log2 of Ns of stage k, Rk its radix, OFFk the offset of
-// its twiddles in the stage tables.
+// The schedule of a length-2^LOGNF transform (256 ... 2048 points) as first
+// stage, one or two middle stages (NMID) and the last stage; Dk is the log2
+// of Ns of stage k, Rk its radix, OFFk the offset of its twiddles in the
+// stage tables (R2 and OFF2 unused with one middle stage).
 template <int LOGNF>
-struct Sched4 {
+struct Sched {
   static constexpr int D1 = radix_log_c(LOGNF);
   static constexpr int R0 = 1 << D1;
+  static constexpr int DL = last_stage_done(LOGNF);
+  static constexpr int RL = 1 << (LOGNF - DL);
   static constexpr int R1 = 1 << radix_log_c(LOGNF - D1);
   static constexpr int D2 = D1 + radix_log_c(LOGNF - D1);
-  static constexpr int R2 = 1 << radix_log_c(LOGNF - D2);
-  static constexpr int DL = D2 + radix_log_c(LOGNF - D2);
-  static constexpr int RL = 1 << (LOGNF - DL);
-  static constexpr int OFF2 = stage_table_off(LOGNF, D2);
+  static constexpr int NMID = D2 < DL ? 2 : 1;
+  static constexpr int R2 = NMID == 2 ? 1 << radix_log_c(LOGNF - D2) : 2;
+  static constexpr int OFF2 = NMID == 2 ? stage_table_off(LOGNF, D2) : 0;
   static constexpr int OFFL = stage_table_off(LOGNF, DL);
-  static_assert(DL == last_stage_done(LOGNF), "four stages");
+  static_assert(D1 < DL, "at least three stages");
+  static_assert(NMID == 1 ? D2 == DL : D2 + radix_log_c(LOGNF - D2) == DL, "three or four stages");
 };
 
 // ---- row passes with pruned end stages (n = 2^LOGN at compile time) ----
@@ -1058,10 +1060,12 @@ struct Sched4 {
 // window (m < n/2) and stores it straight to global memory.  IN_SPEC ->
 // OUT_SPEC (inverse, crop, forward): the last inverse stage writes the
 // window back in place (conjugated; the residual of set 0 accumulated from
-// it), and the forward transform's first stage reads only that half.  RT
-// (FP32 passes with one transform): every twiddle of a thread stays in
-// registers (Ns divides NT in every stage after the first) and no tables
-// are read per set; the middle pass, with two transforms, would spill them.
+// it), and the forward transform's first stage reads only that half.  In
+// FP32 a thread's twiddles stay in registers (Ns divides NT in every stage
+// after the first) and no tables are read per set: all of them in the
+// passes with one transform (RTL); in the middle pass, with two, those of
+// the middle stages when there is one (n < 1024; two would spill), the
+// others from tables in LDS.
 template <typename T, int RB, int NT, int IN, int OUT, bool TWL, int LOGN>
 __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass_pruned(RowArgs<T> a) {
   static_assert(IN != IN_PSF && OUT != OUT_PSFTMP && LOGN > 0, "image rows of a fixed length");
@@ -1091,29 +1095,36 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass_pruned(RowArgs<T> a
   } else {
     twr = a.twr;
   }
-  constexpr bool RT = sizeof(T) == 4 && !(IN == IN_SPEC && OUT == OUT_SPEC);
-  using S4 = Sched4<LOGN>;
-  cplx<T> w1[S4::R1 - 1], w2[S4::R2 - 1], wl[RL - 1];
+  using S = Sched<LOGN>;
+  constexpr bool MIDP = IN == IN_SPEC && OUT == OUT_SPEC;
+  constexpr bool RT = sizeof(T) == 4 && (!MIDP || S::NMID == 1);
+  constexpr bool RTL = sizeof(T) == 4 && !MIDP;
+  cplx<T> w1[S::R1 - 1], w2[S::R2 - 1], wl[RL - 1];
   if constexpr (RT) {
-    stage_tw_regs<T, S4::R1, NT, S4::D1>(a.twr, w1);
-    stage_tw_regs<T, S4::R2, NT, S4::D2>(a.twr + S4::OFF2, w2);
-    stage_tw_regs<T, RL, NT, DL>(a.twr + OFFL, wl);
+    stage_tw_regs<T, S::R1, NT, S::D1>(a.twr, w1);
+    if constexpr (S::NMID == 2) stage_tw_regs<T, S::R2, NT, S::D2>(a.twr + S::OFF2, w2);
   }
+  if constexpr (RTL) stage_tw_regs<T, RL, NT, DL>(a.twr + OFFL, wl);
   // stages after the first, and the stages before the last
   auto fwd_rest = [&]() {
     if constexpr (RT) {
-      fft_stage_ct<T, S4::R1, NT, EMAX, LOGN, S4::D1, true>(buf, RB, stride, nullptr, w1);
-      fft_stage_ct<T, S4::R2, NT, EMAX, LOGN, S4::D2, true>(buf, RB, stride, nullptr, w2);
-      fft_stage_ct<T, RL, NT, EMAX, LOGN, DL, true>(buf, RB, stride, nullptr, wl);
+      fft_stage_ct<T, S::R1, NT, EMAX, LOGN, S::D1, true>(buf, RB, stride, nullptr, w1);
+      if constexpr (S::NMID == 2)
+        fft_stage_ct<T, S::R2, NT, EMAX, LOGN, S::D2, true>(buf, RB, stride, nullptr, w2);
+      if constexpr (RTL)
+        fft_stage_ct<T, RL, NT, EMAX, LOGN, DL, true>(buf, RB, stride, nullptr, wl);
+      else
+        fft_stage_ct<T, RL, NT, EMAX, LOGN, DL>(buf, RB, stride, twr + OFFL);
     } else {
       lds_fft_range<T, NT, EMAX, LOGN, LR0, 0, LOGN>(buf, RB, stride, twr);
     }
   };
   auto inv_head = [&]() {
     if constexpr (RT) {
-      fft_stage_ct<T, S4::R0, NT, EMAX, LOGN, 0>(buf, RB, stride, nullptr);
-      fft_stage_ct<T, S4::R1, NT, EMAX, LOGN, S4::D1, true>(buf, RB, stride, nullptr, w1);
-      fft_stage_ct<T, S4::R2, NT, EMAX, LOGN, S4::D2, true>(buf, RB, stride, nullptr, w2);
+      fft_stage_ct<T, S::R0, NT, EMAX, LOGN, 0>(buf, RB, stride, nullptr);
+      fft_stage_ct<T, S::R1, NT, EMAX, LOGN, S::D1, true>(buf, RB, stride, nullptr, w1);
+      if constexpr (S::NMID == 2)
+        fft_stage_ct<T, S::R2, NT, EMAX, LOGN, S::D2, true>(buf, RB, stride, nullptr, w2);
     } else {
       lds_fft_range<T, NT, EMAX, LOGN, 0, 0, DL>(buf, RB, stride, twr);
     }
@@ -1164,7 +1175,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass_pruned(RowArgs<T> a
       lds_barrier();
       inv_head();
       cplx<T> v[QL][RL];
-      stage_last_load<T, NT, LOGN, QL, RL, RT>(buf, stride, twr + OFFL, v, wl);
+      stage_last_load<T, NT, LOGN, QL, RL, RTL>(buf, stride, twr + OFFL, v, wl);
       if constexpr (OUT == OUT_REAL) {
         // z = conj(inverse): x[2m] = z.x, x[2m+1] = z.y for m < n/2
 #pragma unroll
@@ -1237,11 +1248,11 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass_pruned(RowArgs<T> a
 template <typename T, int NT, int LOGN>
 __global__ void __launch_bounds__(NT, 4) col_pass_rt(ColArgs<T> a) {
   constexpr int LOGNF = LOGN + 1, N = 1 << LOGN, M2 = 2 * N;
-  using S4 = Sched4<LOGNF>;
-  constexpr int IPT = S4::R0 / 2;  // inputs per thread
+  using SC = Sched<LOGNF>;
+  constexpr int IPT = SC::R0 / 2;  // inputs per thread
   static_assert(N == IPT * NT, "the first stage's inputs are the loaded values");
   constexpr int EMAX = M2;
-  constexpr int DL = S4::DL, RL = S4::RL, NS = 1 << DL;
+  constexpr int DL = SC::DL, RL = SC::RL, NS = 1 << DL;
   constexpr int QL = NS / NT;  // last-stage butterflies per thread (distinct)
   static_assert(NS % NT == 0, "whole last-stage butterflies per thread");
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1256,10 +1267,10 @@ __global__ void __launch_bounds__(NT, 4) col_pass_rt(ColArgs<T> a) {
   cplx<T> pre[IPT];
 #pragma unroll
   for (int q = 0; q < IPT; ++q) pre[q] = a.in[0][col_off + threadIdx.x + q * NT];
-  cplx<T> w1[S4::R1 - 1], w2[S4::R2 - 1], wl[QL * (RL - 1)];
-  stage_tw_regs<T, S4::R1, NT, S4::D1>(a.twc, w1);
-  stage_tw_regs<T, S4::R2, NT, S4::D2>(a.twc + S4::OFF2, w2);
-  last_tw_regs<T, NT, LOGNF, QL, RL>(a.twc + S4::OFFL, wl);
+  cplx<T> w1[SC::R1 - 1], w2[SC::R2 - 1], wl[QL * (RL - 1)];
+  stage_tw_regs<T, SC::R1, NT, SC::D1>(a.twc, w1);
+  if constexpr (SC::NMID == 2) stage_tw_regs<T, SC::R2, NT, SC::D2>(a.twc + SC::OFF2, w2);
+  last_tw_regs<T, NT, LOGNF, QL, RL>(a.twc + SC::OFFL, wl);
   // slot 0 packs the two real columns kx = 0 and kx = n (see col_pass)
   const bool slot0 = kx0 == 0;
   cplx<T> kr[QL][RL];
@@ -1277,8 +1288,9 @@ __global__ void __launch_bounds__(NT, 4) col_pass_rt(ColArgs<T> a) {
       for (int q = 0; q < IPT; ++q) pre[q] = a.in[set + 1][col_off + threadIdx.x + q * NT];
     }
     lds_barrier();
-    fft_stage_ct<T, S4::R1, NT, EMAX, LOGNF, S4::D1, true>(buf, 1, 0, nullptr, w1);
-    fft_stage_ct<T, S4::R2, NT, EMAX, LOGNF, S4::D2, true>(buf, 1, 0, nullptr, w2);
+    fft_stage_ct<T, SC::R1, NT, EMAX, LOGNF, SC::D1, true>(buf, 1, 0, nullptr, w1);
+    if constexpr (SC::NMID == 2)
+      fft_stage_ct<T, SC::R2, NT, EMAX, LOGNF, SC::D2, true>(buf, 1, 0, nullptr, w2);
     {
       cplx<T> v[QL][RL];
       stage_last_load<T, NT, LOGNF, QL, RL, true>(buf, 0, nullptr, v, wl);
@@ -1317,9 +1329,10 @@ __global__ void __launch_bounds__(NT, 4) col_pass_rt(ColArgs<T> a) {
       }
       lds_barrier();
     }
-    fft_stage_ct<T, S4::R0, NT, EMAX, LOGNF, 0>(buf, 1, 0, nullptr);
-    fft_stage_ct<T, S4::R1, NT, EMAX, LOGNF, S4::D1, true>(buf, 1, 0, nullptr, w1);
-    fft_stage_ct<T, S4::R2, NT, EMAX, LOGNF, S4::D2, true>(buf, 1, 0, nullptr, w2);
+    fft_stage_ct<T, SC::R0, NT, EMAX, LOGNF, 0>(buf, 1, 0, nullptr);
+    fft_stage_ct<T, SC::R1, NT, EMAX, LOGNF, SC::D1, true>(buf, 1, 0, nullptr, w1);
+    if constexpr (SC::NMID == 2)
+      fft_stage_ct<T, SC::R2, NT, EMAX, LOGNF, SC::D2, true>(buf, 1, 0, nullptr, w2);
     {
       cplx<T> v[QL][RL];
       stage_last_load<T, NT, LOGNF, QL, RL, true>(buf, 0, nullptr, v, wl);
@@ -1441,18 +1454,6 @@ static int launch_row_rb(RowArgs<T>& a, int nsets, hipStream_t s) {
   // n = 1024 (the benchmark size) runs the compile-time form
   constexpr bool F32 = sizeof(T) == 4;
   const size_t shm_t = shm + sizeof(cplx<T>) * (size_t)stage_table_len(31 - __builtin_clz(n));
-  // (row blocks at n = 1024: 8 rows in FP32, 4 in FP64)
-  if constexpr (IN != IN_PSF && RB == (F32 ? 8 : 4)) {
-    if (n == 1024) {
-      // tables in LDS only for the FP32 middle pass (the others keep their
-      // twiddles in registers, FP64 reads them from global memory)
-      constexpr bool TW = F32 && IN == IN_SPEC && OUT == OUT_SPEC;
-      MUFFIN_ALLOW_BIG_LDS((row_pass_pruned<T, RB, kRowNT, IN, OUT, TW, 10>));
-      row_pass_pruned<T, RB, kRowNT, IN, OUT, TW, 10><<<grid, kRowNT, TW ? shm_t : shm, s>>>(a);
-      MUFFIN_HIP_CHECK(hipGetLastError());
-      return 0;
-    }
-  }
   if (F32 && n <= 1024) {
     MUFFIN_ALLOW_BIG_LDS((row_pass<T, RB, kRowNT, IN, OUT, F32, 0>));
     row_pass<T, RB, kRowNT, IN, OUT, F32, 0><<<grid, kRowNT, shm_t, s>>>(a);
@@ -1464,8 +1465,47 @@ static int launch_row_rb(RowArgs<T>& a, int nsets, hipStream_t s) {
   return 0;
 }
 
+// Rows per block of the pruned row passes (n = 256, 512, 1024), or 0 where
+// the generic pass runs: every thread then owns whole butterflies of the
+// first and the last stage.
+static int pruned_rb(int n, int elem_bytes) {
+  switch (n) {
+    case 256: return 16;
+    case 512: return 8;
+    case 1024: return elem_bytes == 8 ? 4 : 8;
+    default: return 0;
+  }
+}
+
+template <typename T, int IN, int OUT, int LOGN>
+static int launch_row_pruned(RowArgs<T>& a, int nsets, hipStream_t s) {
+  constexpr bool F32 = sizeof(T) == 4;
+  constexpr int RB = LOGN == 8 ? 16 : (LOGN == 9 ? 8 : (F32 ? 8 : 4));
+  if (a.n != (1 << LOGN) || pruned_rb(a.n, sizeof(T)) != RB) return -2; /* E_SHAPE */
+  a.nblocks = a.L * (a.rows / RB);
+  a.nsets = nsets;
+  const size_t shm = sizeof(cplx<T>) * (size_t)RB * sw_stride<T>(1 << LOGN);
+  const size_t shm_t = shm + sizeof(cplx<T>) * (size_t)stage_table_len(LOGN);
+  dim3 grid(xcd_grid(a.nblocks), 1);
+  // tables in LDS only for the FP32 middle pass (the others keep their
+  // twiddles in registers, FP64 reads them from global memory)
+  constexpr bool TW = F32 && IN == IN_SPEC && OUT == OUT_SPEC;
+  MUFFIN_ALLOW_BIG_LDS((row_pass_pruned<T, RB, kRowNT, IN, OUT, TW, LOGN>));
+  row_pass_pruned<T, RB, kRowNT, IN, OUT, TW, LOGN><<<grid, kRowNT, TW ? shm_t : shm, s>>>(a);
+  MUFFIN_HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
 template <typename T, int IN, int OUT>
 static int launch_row(RowArgs<T>& a, int nsets, hipStream_t s) {
+  if constexpr (IN != IN_PSF) {
+    switch (a.n) {
+      case 256: return launch_row_pruned<T, IN, OUT, 8>(a, nsets, s);
+      case 512: return launch_row_pruned<T, IN, OUT, 9>(a, nsets, s);
+      case 1024: return launch_row_pruned<T, IN, OUT, 10>(a, nsets, s);
+      default: break;
+    }
+  }
   switch (row_rb<T>(a.n)) {
     case 8: return launch_row_rb<T, 8, IN, OUT>(a, nsets, s);
     case 4: return launch_row_rb<T, 4, IN, OUT>(a, nsets, s);
@@ -1475,11 +1515,32 @@ static int launch_row(RowArgs<T>& a, int nsets, hipStream_t s) {
 }
 
 int fft_res_blocks(int n, int L, int elem_bytes) {
+  // (the middle row pass writes one residual partial per block)
+  if (const int prb = pruned_rb(n, elem_bytes)) return L * (n / prb);
   const int emax = (elem_bytes == 8 ? 16 : 32) * 256;
   int rb = elem_bytes == 8 ? 4 : 8;
   while (rb > 1 && rb * n > emax) rb >>= 1;
   if (rb > n) rb = n;
   return L * (n / rb);
+}
+
+// Pruned column pass for n = 2^LOGN (one column per block, n / 4 threads):
+// FP32 keeps twiddles and K in registers (only the transform buffer in
+// LDS), FP64 stages the column of K in LDS and reads the tables.
+template <typename T, int LOGN>
+static int launch_col_pruned(const ColArgs<T>& a, dim3 grid, hipStream_t s) {
+  constexpr int NT = (1 << LOGN) / 4;
+  if (a.B != 1 || a.n != (1 << LOGN)) return -2; /* E_SHAPE */
+  const size_t buf = sizeof(cplx<T>) * (size_t)sw_stride<T>(2 << LOGN);
+  if constexpr (sizeof(T) == 4) {
+    col_pass_rt<T, NT, LOGN><<<grid, NT, buf, s>>>(a);
+  } else {
+    const size_t shm = buf + sizeof(cplx<T>) * (size_t)(2 << LOGN);
+    MUFFIN_ALLOW_BIG_LDS((col_pass_pruned<T, NT, false, LOGN>));
+    col_pass_pruned<T, NT, false, LOGN><<<grid, NT, shm, s>>>(a);
+  }
+  MUFFIN_HIP_CHECK(hipGetLastError());
+  return 0;
 }
 
 template <typename T>
@@ -1495,7 +1556,9 @@ static int launch_col(const FftPlan<T>& p, const cplx<T>* const* in, cplx<T>* co
   a.n = p.n;
   a.logn = 31 - __builtin_clz(p.n);
   a.L = p.L;
-  a.B = std::max(1, 2048 / (2 * p.n));
+  // n = 256, 512, 1024: the pruned passes, one column per block
+  const bool pruned = p.n == 256 || p.n == 512 || p.n == 1024;
+  a.B = pruned ? 1 : std::max(1, 2048 / (2 * p.n));
   if (a.B > p.n) a.B = p.n;
   a.conj = conj;
   a.nblocks = p.L * (p.n / a.B);
@@ -1507,16 +1570,11 @@ static int launch_col(const FftPlan<T>& p, const cplx<T>* const* in, cplx<T>* co
   // n = 1024 (the benchmark size) runs the compile-time form
   constexpr bool F32 = sizeof(T) == 4;
   const size_t shm_t = shm + sizeof(cplx<T>) * (size_t)stage_table_len(a.logn + 1);
-  if (p.n == 1024) {
-    // one column per block: the pruned form
-    if (a.B != 1) return -2; /* E_SHAPE */
-    if constexpr (F32) {
-      // twiddles and K in registers: only the transform buffer in LDS
-      const size_t shr = sizeof(cplx<T>) * (size_t)sw_stride<T>(2 * p.n);
-      col_pass_rt<T, 256, 10><<<grid, 256, shr, s>>>(a);
-    } else {
-      MUFFIN_ALLOW_BIG_LDS((col_pass_pruned<T, 256, F32, 10>));
-      col_pass_pruned<T, 256, F32, 10><<<grid, 256, F32 ? shm_t : shm, s>>>(a);
+  if (pruned) {
+    switch (p.n) {
+      case 256: return launch_col_pruned<T, 8>(a, grid, s);
+      case 512: return launch_col_pruned<T, 9>(a, grid, s);
+      default: return launch_col_pruned<T, 10>(a, grid, s);
     }
   } else if (2 * p.n <= 2048) {
     MUFFIN_ALLOW_BIG_LDS((col_pass<T, 256, F32, 0>));
