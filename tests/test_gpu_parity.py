@@ -354,6 +354,53 @@ def test_max_side_operators(mode):
     hs.close()
 
 
+@pytest.mark.parametrize("n", [256, 512])
+@pytest.mark.parametrize("mode", ["f64", "f32"])
+def test_pruned_fft_sides(n, mode):
+    """The other sides with pruned FFT passes (n = 256: three-stage
+    transforms, 16 rows per block; n = 512: 1024-point columns), H^T H on two
+    bands, element by element against the oracle."""
+    mm = _mm()
+    torch = _torch()
+    L = 2
+    m = mm.F64 if mode == "f64" else mm.F32
+    dt = torch.float64 if mode == "f64" else torch.float32
+    tol = 1e-12 if mode == "f64" else 3e-6
+    rng = np.random.default_rng(n)
+    prob = synth.make_problem(n, L, n_src=200, n_blob=10, n_base=4000, seed=n)
+    x = np.abs(rng.standard_normal((L, n, n)))
+    h = mm.Muffin(mm.default_config(n, L, mode=m, tau=1.0, pi_iters=0))
+    h.set_problem(dev(prob.dirty, dt), dev(prob.psf, dt), np.ones(n * n), np.ones(L))
+    xd = dev(x, dt)
+    K = op.psf_spectrum(host(dev(prob.psf, dt)))
+    assert rel(host(h.op("HTH", xd)), op.HT(op.H(host(xd), K), K)) < tol
+    h.close()
+
+
+@pytest.mark.parametrize("mode", ["f64", "f32"])
+def test_adapt_pruned_side_256(mode):
+    """ADA-PT at n = 256 (all six state sets through the pruned chain, the
+    residual partials of its middle row pass), three iterations with a theta
+    update after each, against the oracle."""
+    mm = _mm()
+    m = mm.F64 if mode == "f64" else mm.F32
+    h, rep, ref = _adapt_case(mm, m, n=256, L=2, iters=3, Delta=1, seed=41)
+    assert rep["theta_updates"] == len(ref.history) == 3
+    if mode == "f64":
+        assert rel(host(h.sky()), ref.X) < 1e-10
+        for s, key in [(1, "Sb"), (2, "Dm"), (3, "Dg"), (4, "Dbm"), (5, "Dbg")]:
+            exp = getattr(ref.states[key], "X")
+            assert rel(host(h.get_state(0, s)), exp) < 1e-9 or np.abs(exp).max() == 0, key
+        for row, r in zip(h.history(), ref.history):
+            assert abs(row[6] - r["psure"]) <= 1e-9 * max(1.0, abs(r["psure"]))
+            assert abs(row[1] - r["mu"]) <= 1e-12 * max(1.0, abs(r["mu"]))
+    else:
+        assert rel(host(h.sky()), ref.X) < 1e-5
+        assert abs(rep["mu"] - ref.mu) <= 1e-3 * abs(ref.mu)
+        assert abs(rep["gamma"] - ref.gamma) <= 1e-3 * abs(ref.gamma)
+    h.close()
+
+
 def test_full_cube_dct_sampled_f32():
     """1024^2 pixels x 256 bands (the benchmark's DCT configuration); sampled
     pixel spectra against the oracle's DCT."""
