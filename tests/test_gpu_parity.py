@@ -422,6 +422,35 @@ def test_full_cube_dct_sampled_f32():
     h.close()
 
 
+@pytest.mark.timeout(600)
+def test_full_cube_operators_sampled_f32():
+    """1024^2 pixels x 256 bands (the benchmark's FFT and wavelet launch
+    configuration): H^T H, W_s and W_s^T over the whole cube, three sampled
+    bands against the oracle."""
+    mm = _mm()
+    torch = _torch()
+    n, L = 1024, 256
+    prob = synth.make_config("c2", seed=3, device="cuda:0")
+    h = mm.Muffin(mm.default_config(n, L, mode=mm.F32, tau=1.0, pi_iters=0))
+    h.set_problem(dev(prob.dirty, torch.float32), dev(prob.psf, torch.float32),
+                  np.ones(n * n), np.ones(L))
+    g = torch.Generator(device="cuda:0").manual_seed(9)
+    x = torch.rand((L, n, n), generator=g, device="cuda:0", dtype=torch.float32)
+    y = h.op("HTH", x)
+    u = h.op("Ws", x)
+    w = h.op("WsT", u)
+    W = op.SpatialDictionary(8, 3)
+    for b in (0, 131, 255):
+        xb = x[b:b + 1].double().cpu().numpy()
+        psf32 = prob.psf[b:b + 1].astype(np.float32).astype(np.float64)
+        K = op.psf_spectrum(psf32)
+        assert rel(host(y[b:b + 1]), op.HT(op.H(xb, K), K)) < 3e-6, b
+        ub = host(u[b:b + 1])
+        assert rel(ub, W.forward(xb)) < 3e-6, b
+        assert rel(host(w[b:b + 1]), W.adjoint(ub)) < 3e-6, b
+    h.close()
+
+
 # --------------------------------------------------------- precision forms --
 
 @pytest.mark.parametrize("L", [1, 7, 32, 40, 256])
