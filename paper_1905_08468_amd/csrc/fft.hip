@@ -27,11 +27,6 @@
 #include <cmath>
 #include <vector>
 
-// Row passes fetch the next state set's rows into registers while the
-// current set is transformed (1) or load each set when it is reached (0).
-#ifndef MUFFIN_ROW_PREFETCH
-#define MUFFIN_ROW_PREFETCH 0
-#endif
 
 namespace muffin {
 
@@ -313,29 +308,6 @@ __device__ __forceinline__ void fft_stage_ct(cplx<T>* buf, int batch, int stride
   lds_barrier();
 }
 
-// Forward FFT of `batch` sequences of length 2^LOGNF (as lds_fft).
-template <typename T, int NT, int EMAX, int LOGNF, int DONE = 0, int OFF = 0>
-__device__ __forceinline__ void lds_fft_ct(cplx<T>* buf, int batch, int stride,
-                                           const cplx<T>* __restrict__ twtab) {
-  if constexpr (DONE < LOGNF) {
-    constexpr int LR = radix_log_c(LOGNF - DONE);
-    fft_stage_ct<T, (1 << LR), NT, EMAX, LOGNF, DONE>(buf, batch, stride, twtab + OFF);
-    constexpr int NOFF = DONE > 0 ? OFF + (1 << DONE) * ((1 << LR) - 1) : OFF;
-    lds_fft_ct<T, NT, EMAX, LOGNF, DONE + LR, NOFF>(buf, batch, stride, twtab);
-  }
-}
-
-// Length-2^lognf FFT; LOGNF > 0 selects the compile-time form (lognf must
-// then equal it).
-template <typename T, int NT, int EMAX, int LOGNF>
-__device__ __forceinline__ void lds_fft_any(cplx<T>* buf, int lognf, int batch, int stride,
-                                            const cplx<T>* __restrict__ twtab) {
-  if constexpr (LOGNF > 0)
-    lds_fft_ct<T, NT, EMAX, LOGNF>(buf, batch, stride, twtab);
-  else
-    lds_fft<T, NT, EMAX>(buf, lognf, batch, stride, twtab);
-}
-
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 
 // Blocks are handed to the 8 XCDs round-robin; remap so that each XCD gets a
@@ -508,15 +480,15 @@ __device__ __forceinline__ void herm_post(cplx<T>* buf, int stride, const cplx<T
   }
 }
 
-// two 512-thread blocks per CU (the LDS limit): at most 128 VGPRs.
-// TWL: stage twiddles staged in LDS after the row buffer.  LOGN > 0: the row
-// length n = 2^LOGN is a compile-time constant (a.n must equal it).
-template <typename T, int RB, int NT, int IN, int OUT, bool TWL, int LOGN>
+// Generic row pass (any power-of-two n; the pruned passes cover 256 ... 1024
+// for the image rows).  Two 512-thread blocks per CU (the LDS limit): at
+// most 128 VGPRs.  TWL: stage twiddles staged in LDS after the row buffer.
+template <typename T, int RB, int NT, int IN, int OUT, bool TWL>
 __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   __shared__ double red[NT / 64];
-  const int logn = LOGN > 0 ? LOGN : a.logn;
+  const int logn = a.logn;
   const int n = 1 << logn;
   const int stride = sw_stride<T>(n);
   const int lb = xcd_remap(blockIdx.x, a.nblocks);
@@ -526,7 +498,6 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
   const int i0 = (lb - band * rblocks) * RB;
   const int half = n >> 1;
   constexpr int EMAX = (sizeof(T) == 8 ? 16 : 32) * 256;
-  constexpr int EPT = (EMAX + NT - 1) / NT;  // staged input values per thread
   const int nel = RB * n;
   const cplx<T>* twr;
   if constexpr (TWL) {
@@ -536,32 +507,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
   } else {
     twr = a.twr;
   }
-  // the first set's input, then each set's input is fetched while the
-  // previous set is transformed
-#if MUFFIN_ROW_PREFETCH
-  cplx<T> pre[EPT];
-#pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int t = threadIdx.x + q * NT;
-    if (t < nel) pre[q] = row_input<T, RB, NT, IN>(a, 0, band, i0, t, n, logn);
-  }
-#endif
   for (int set = 0; set < a.nsets; ++set) {
-#if MUFFIN_ROW_PREFETCH
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int t = threadIdx.x + q * NT;
-      if (t < nel) buf[row_slot<T, RB, IN>(t, n, logn, stride)] = pre[q];
-    }
-    lds_barrier();
-    if (set + 1 < a.nsets) {
-#pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        const int t = threadIdx.x + q * NT;
-        if (t < nel) pre[q] = row_input<T, RB, NT, IN>(a, set + 1, band, i0, t, n, logn);
-      }
-    }
-#else
     if constexpr (IN == IN_REAL) {
       // image rows: (x[2m], x[2m+1]) pairs for m < n/2, zeros above (the
       // padding); the loads of several pairs are issued before any is stored
@@ -607,11 +553,10 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
         buf[row_slot<T, RB, IN>(t, n, logn, stride)] = row_input<T, RB, NT, IN>(a, set, band, i0, t, n, logn);
     }
     lds_barrier();
-#endif
     if constexpr (IN == IN_SPEC) {
       herm_pre<T, RB, NT>(buf, stride, a.tw, n);
       lds_barrier();
-      lds_fft_any<T, NT, EMAX, LOGN>(buf, logn, RB, stride, twr);
+      lds_fft<T, NT, EMAX>(buf, logn, RB, stride, twr);
       // z = conj(buf): x[2m] = z.x, x[2m+1] = z.y for m < n/2 (image window)
       if constexpr (OUT == OUT_REAL) {
         T* o = a.out[set] + ((size_t)band * n + i0) * n;
@@ -652,7 +597,7 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass(RowArgs<T> a) {
     }
 
     if constexpr (OUT == OUT_SPEC || OUT == OUT_PSFTMP) {
-      lds_fft_any<T, NT, EMAX, LOGN>(buf, logn, RB, stride, twr);
+      lds_fft<T, NT, EMAX>(buf, logn, RB, stride, twr);
       herm_post<T, RB, NT>(buf, stride, a.tw, n);
       lds_barrier();
       if constexpr (OUT == OUT_SPEC) {
@@ -695,15 +640,14 @@ struct ColArgs {
   int nsets;           // state sets, processed in turn with the same K
 };
 
+// Generic column pass (sides other than 256 ... 1024, B columns per block).
 // TWL: stage twiddles staged in LDS after the transfer-function columns.
-// LOGN > 0: n = 2^LOGN at compile time (a.n and a.B must match).
-template <typename T, int NT, bool TWL, int LOGN>
+template <typename T, int NT, bool TWL>
 __global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 4) col_pass(ColArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
-  constexpr int BC = LOGN > 0 ? ((2048 >> (LOGN + 1)) > 1 ? (2048 >> (LOGN + 1)) : 1) : 0;
-  const int logn = LOGN > 0 ? LOGN : a.logn;
-  const int n = 1 << logn, m2 = 2 * n, B = LOGN > 0 ? BC : a.B;
+  const int logn = a.logn;
+  const int n = 1 << logn, m2 = 2 * n, B = a.B;
   const int stride = sw_stride<T>(m2);
   const int lb = xcd_remap(blockIdx.x, a.nblocks);
   if (lb >= a.nblocks) return;
@@ -758,7 +702,7 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 4) col_pass(ColArgs<T
         if (t < nin) pre[q] = a.in[set + 1][((size_t)band * n + kx0) * n + t];
       }
     }
-    lds_fft_any<T, NT, EMAX, (LOGN > 0 ? LOGN + 1 : 0)>(buf, logn + 1, B, stride, twc);
+    lds_fft<T, NT, EMAX>(buf, logn + 1, B, stride, twc);
     for (int t = threadIdx.x; t < B * m2; t += NT) {
       const int b = t / m2, ky = t - b * m2;
       const int kx = kx0 + b;
@@ -791,7 +735,7 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 4) col_pass(ColArgs<T
       }
     }
     lds_barrier();
-    lds_fft_any<T, NT, EMAX, (LOGN > 0 ? LOGN + 1 : 0)>(buf, logn + 1, B, stride, twc);
+    lds_fft<T, NT, EMAX>(buf, logn + 1, B, stride, twc);
     cplx<T>* dst = a.out[set] + ((size_t)band * n + kx0) * n;
     for (int t = threadIdx.x; t < nin; t += NT) {
       const int b = t / n, i = t - b * n;
@@ -1455,11 +1399,11 @@ static int launch_row_rb(RowArgs<T>& a, int nsets, hipStream_t s) {
   constexpr bool F32 = sizeof(T) == 4;
   const size_t shm_t = shm + sizeof(cplx<T>) * (size_t)stage_table_len(31 - __builtin_clz(n));
   if (F32 && n <= 1024) {
-    MUFFIN_ALLOW_BIG_LDS((row_pass<T, RB, kRowNT, IN, OUT, F32, 0>));
-    row_pass<T, RB, kRowNT, IN, OUT, F32, 0><<<grid, kRowNT, shm_t, s>>>(a);
+    MUFFIN_ALLOW_BIG_LDS((row_pass<T, RB, kRowNT, IN, OUT, F32>));
+    row_pass<T, RB, kRowNT, IN, OUT, F32><<<grid, kRowNT, shm_t, s>>>(a);
   } else {
-    MUFFIN_ALLOW_BIG_LDS((row_pass<T, RB, kRowNT, IN, OUT, false, 0>));
-    row_pass<T, RB, kRowNT, IN, OUT, false, 0><<<grid, kRowNT, shm, s>>>(a);
+    MUFFIN_ALLOW_BIG_LDS((row_pass<T, RB, kRowNT, IN, OUT, false>));
+    row_pass<T, RB, kRowNT, IN, OUT, false><<<grid, kRowNT, shm, s>>>(a);
   }
   MUFFIN_HIP_CHECK(hipGetLastError());
   return 0;
@@ -1577,11 +1521,11 @@ static int launch_col(const FftPlan<T>& p, const cplx<T>* const* in, cplx<T>* co
       default: return launch_col_pruned<T, 10>(a, grid, s);
     }
   } else if (2 * p.n <= 2048) {
-    MUFFIN_ALLOW_BIG_LDS((col_pass<T, 256, F32, 0>));
-    col_pass<T, 256, F32, 0><<<grid, 256, F32 ? shm_t : shm, s>>>(a);
+    MUFFIN_ALLOW_BIG_LDS((col_pass<T, 256, F32>));
+    col_pass<T, 256, F32><<<grid, 256, F32 ? shm_t : shm, s>>>(a);
   } else {
-    MUFFIN_ALLOW_BIG_LDS((col_pass<T, 512, false, 0>));
-    col_pass<T, 512, false, 0><<<grid, 512, shm, s>>>(a);
+    MUFFIN_ALLOW_BIG_LDS((col_pass<T, 512, false>));
+    col_pass<T, 512, false><<<grid, 512, shm, s>>>(a);
   }
   MUFFIN_HIP_CHECK(hipGetLastError());
   return 0;
