@@ -33,9 +33,12 @@ MFMA_BF16_PEAK, MFMA_F32_PEAK, MFMA_F64_PEAK = 2500.0, 157.3, 78.6   # TFLOP/s, 
 #   synthesis_l1: per set the 6 level-1 detail coefficients of the 8 bases
 #     (8 x 3/4) + the 2 coarse values (8 x 1/4) in, S out.  6 sets: 6*9.
 #   analysis_l1_primal: per set x~, x in; 6 detail coefficients read and
-#     written; 2 low-pass values out; 6 mask bytes out.  2 sets.
-#   analysis_l1_deriv: as above with the mask read; the d/dmu sets read the
-#     primal's x~, x too.  4 sets: 2*(4+12+2) + 2*(2+12+2), 24 mask bytes.
+#     written; 2 low-pass values out; the masks of the 8 bases' outputs as
+#     bits, one 32-bit word per thread of a 64 x 64 tile (1 byte per
+#     voxel) out.  2 sets.
+#   analysis_l1_deriv: as above with the mask words read; the d/dmu sets
+#     read the primal's x~, x too.  4 sets: 2*(4+12+2) + 2*(2+12+2), 4 mask
+#     bytes.
 #   dct_primal: x~, x, V in; V, T out; 1 mask byte.  2 sets.
 #   dct_deriv: d/dmu: x~', x', V' in, V', T' out; d/dgamma also x~, x, and
 #     the new primal V.  4 sets: 2*5 + 2*8, 4 mask bytes.
@@ -43,8 +46,8 @@ MFMA_BF16_PEAK, MFMA_F32_PEAK, MFMA_F64_PEAK = 2500.0, 157.3, 78.6   # TFLOP/s, 
 #     derivative x', G', S', T' in, x~' out.  2 trajectories: 2*(6+5+5).
 STAGE_TRAFFIC = {
     "synthesis_l1": (54, 0),
-    "analysis_l1_primal": (32, 12),
-    "analysis_l1_deriv": (68, 24),
+    "analysis_l1_primal": (32, 2),
+    "analysis_l1_deriv": (68, 4),
     "dct_primal": (10, 2),
     "dct_deriv": (26, 4),
     "primal_step": (32, 0),

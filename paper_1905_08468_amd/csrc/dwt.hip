@@ -218,7 +218,7 @@ struct AnArgs {
   const T* x_b[kMaxSets];
   int c1_sel[kMaxSets], c2_sel[kMaxSets];
   T* U[kMaxSets];
-  uint8_t* mask[kMaxSets];
+  uint8_t* mask[kMaxSets];   // this level's mask words (uint32 per block thread) or null
   const T* llin[kMaxSets];   // level >= 2: [L][P][Ms*Ms]
   T* llout[kMaxSets];        // [L][P][(Ms/2)^2] (not at the last level)
   const double* beta;
@@ -301,15 +301,17 @@ struct AnLanes {
 };
 
 // Column filter of basis PB and the dual update (or low-pass output) of this
-// thread's four outputs; u/m hold the prefetched dual values and masks.
-// rU, rM, rL: the band's planes of U, of the masks and of the next level;
-// sU, sM, sL: byte offsets of this basis' plane in them.
+// thread's four outputs; u holds the prefetched dual values.  The masks
+// 1[|p| <= 1] of a thread's outputs are bits 4 (PB - 1) + i of one 32-bit
+// word per thread and block (mw): set by the primal role, read by the
+// derivative role, whose launch has the same blocks and threads.
+// rU, rL: the band's planes of U and of the next level; sU, sL: byte
+// offsets of this basis' plane in them.
 template <typename T, int TO, int NT, int PB>
 __device__ __forceinline__ void an_cols(const AnArgs<T>& a, const T* rowbuf, const AnLanes& ln,
-                                        __amdgpu_buffer_rsrc_t rU, __amdgpu_buffer_rsrc_t rM,
-                                        __amdgpu_buffer_rsrc_t rL, uint32_t sU, uint32_t sM,
-                                        uint32_t sL, bool mask_out, bool mask_in, T scale,
-                                        const T (&u)[4], const uint8_t (&m)[4]) {
+                                        __amdgpu_buffer_rsrc_t rU, __amdgpu_buffer_rsrc_t rL,
+                                        uint32_t sU, uint32_t sL, bool mask_out, bool mask_in,
+                                        T scale, const T (&u)[4], uint32_t& mw) {
   constexpr int TAPS = 2 * PB;
   T h[TAPS], g[TAPS];
 #pragma unroll
@@ -331,11 +333,9 @@ __device__ __forceinline__ void an_cols(const AnArgs<T>& a, const T* rowbuf, con
     const T pv = u[i] + scale * c;
     if (a.role == ROLE_PRIMAL) {
       buf_st<T>(rU, bo, pv < T(-1) ? T(-1) : (pv > T(1) ? T(1) : pv), sU);
-      if (mask_out)
-        __builtin_amdgcn_raw_buffer_store_b8((pv >= T(-1) && pv <= T(1)) ? 1 : 0, rM, ln.uoff[i],
-                                             sM, 0);
+      if (mask_out && pv >= T(-1) && pv <= T(1)) mw |= 1u << (4 * (PB - 1) + i);
     } else {
-      buf_st<T>(rU, bo, (mask_in && m[i]) ? pv : T(0), sU);
+      buf_st<T>(rU, bo, (mask_in && ((mw >> (4 * (PB - 1) + i)) & 1u)) ? pv : T(0), sU);
     }
   };
 #pragma unroll
@@ -394,24 +394,21 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_an(AnArgs<T> a) {
   const size_t bpl = (size_t)band * a.P;
   const size_t hh = (size_t)half * half;
   const auto rU = plane_rsrc(a.U[set] + bpl * plane, (size_t)a.P * plane);
-  const auto rM = plane_rsrc(a.mask[set] ? a.mask[set] + bpl * plane
-                                         : reinterpret_cast<uint8_t*>(a.U[set]),
-                             (size_t)a.P * plane);
   const auto rL = plane_rsrc(a.last ? a.U[set] : a.llout[set] + bpl * hh,
                              a.last ? plane : (size_t)a.P * hh);
   T u[2][4];
-  uint8_t m[2][4];
-  auto fetch_um = [&](int pidx, T (&uo)[4], uint8_t (&mo)[4]) {
+  // mask word of this thread (see an_cols); the derivative role reads it once
+  uint32_t* mwp = a.mask[set] ? reinterpret_cast<uint32_t*>(a.mask[set]) + (size_t)lb * NT +
+                                    threadIdx.x
+                              : nullptr;
+  uint32_t mw = has_m ? *mwp : 0u;
+  auto fetch_um = [&](int pidx, T (&uo)[4]) {
     const uint32_t sp = (uint32_t)((pidx < a.P ? pidx : a.P - 1) * plane);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
       uo[i] = buf_ld<T>(rU, ln.uoff[i] * (uint32_t)sizeof(T), sp * (uint32_t)sizeof(T));
-    if (has_m) {  // uniform; mo is only read when has_m
-#pragma unroll
-      for (int i = 0; i < 4; ++i) mo[i] = __builtin_amdgcn_raw_buffer_load_b8(rM, ln.uoff[i], sp, 0);
-    }
   };
-  fetch_um(0, u[0], m[0]);
+  fetch_um(0, u[0]);
   // ---- this thread's tile offsets (bytes) in a plane of side Ms ----
   // (wrapped into the plane, so every offset is valid, also for t >= IN^2)
   constexpr int NI = (IN * IN + NT - 1) / NT;
@@ -468,20 +465,20 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_an(AnArgs<T> a) {
   lds_barrier();
   const double beta = a.beta ? a.beta[band] : 1.0;
   const T scale = T(a.dp ? a.dp->sigma * beta / sqrt((double)a.P) : 0.0);
-  auto cols = [&](auto pb, const T (&uu)[4], const uint8_t (&mm)[4]) {
+  auto cols = [&](auto pb, const T (&uu)[4]) {
     constexpr int PB = decltype(pb)::value;
     const uint32_t sp = (uint32_t)((PB - 1) * plane);
-    an_cols<T, TO, NT, PB>(a, s_row, ln, rU, rM, rL, sp * (uint32_t)sizeof(T), sp,
-                           (uint32_t)((PB - 1) * hh * sizeof(T)), mask_out, has_m, scale, uu, mm);
+    an_cols<T, TO, NT, PB>(a, s_row, ln, rU, rL, sp * (uint32_t)sizeof(T),
+                           (uint32_t)((PB - 1) * hh * sizeof(T)), mask_out, has_m, scale, uu, mw);
   };
 #define MUFFIN_AN_STEP(PB)                                                      \
   if (PB - 1 >= p0 && PB - 1 < p1) {                                            \
     const bool more = DEEP && PB < p1;                                          \
     if (more) fetch_ll(PB);                                                     \
-    if (PB < p1) fetch_um(PB, u[PB & 1], m[PB & 1]);                            \
+    if (PB < p1) fetch_um(PB, u[PB & 1]);                                       \
     an_rows<T, TO, NT, PB>(s_in, s_row, IN);                                    \
     lds_barrier();                                                            \
-    cols(std::integral_constant<int, PB>{}, u[(PB - 1) & 1], m[(PB - 1) & 1]);  \
+    cols(std::integral_constant<int, PB>{}, u[(PB - 1) & 1]);                   \
     if (more) {                                                                 \
       _Pragma("unroll") for (int i = 0; i < NI; ++i) {                          \
         const int t = threadIdx.x + i * NT;                                     \
@@ -499,6 +496,7 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_an(AnArgs<T> a) {
   MUFFIN_AN_STEP(7)
   MUFFIN_AN_STEP(8)
 #undef MUFFIN_AN_STEP
+  if (mask_out) *mwp = mw;
 }
 
 // ---------------------------------------------------------------------------
@@ -812,7 +810,31 @@ int dwt_analysis(const DwtPlan<T>& p, const AnalysisIO<T>& io, const DevParams* 
                  hipStream_t s, int lev_lo, int lev_hi) {
   if (lev_lo <= 0) lev_lo = 1;
   if (lev_hi <= 0 || lev_hi > p.J) lev_hi = p.J;
+  // launch shape of a level: FP32 with the paper's 8 bases, subbands of side
+  // >= 64: 32 x 32 output tiles per subband (input halo re-reads
+  // (64 + 14)^2 / 64^2 = 1.49x instead of (32 + 14)^2 / 32^2 = 2.07x)
+  constexpr bool big = sizeof(T) == 4;
+  auto shape = [&](int lev, bool& wide, int& tiles, int& nblocks, int& nt) {
+    const int half = (p.n >> (lev - 1)) >> 1;
+    wide = big && p.P == 8 && (lev == 1 && p.an_tile1 ? p.an_tile1 == kAnTO1 : half >= 64);
+    const int to = wide ? kAnTO1 : kTO;
+    tiles = (half + to - 1) / to;
+    nblocks = tiles * tiles * p.L;
+    nt = wide ? kAnNT1 : kNT;
+  };
+  // mask words of the levels one after another (the primal and derivative
+  // roles of a level have the same launch shape)
+  size_t woff = 0;
+  for (int lev = 1; lev < lev_lo; ++lev) {
+    bool w;
+    int t, nb, nt;
+    shape(lev, w, t, nb, nt);
+    woff += (size_t)nb * nt;
+  }
   for (int lev = lev_lo; lev <= lev_hi; ++lev) {
+    bool wide;
+    int tiles, nblocks, nt;
+    shape(lev, wide, tiles, nblocks, nt);
     AnArgs<T> a{};
     for (int i = 0; i < io.nsets; ++i) {
       a.xt_a[i] = io.xt_a[i];
@@ -822,11 +844,14 @@ int dwt_analysis(const DwtPlan<T>& p, const AnalysisIO<T>& io, const DevParams* 
       a.c1_sel[i] = io.c1_sel[i];
       a.c2_sel[i] = io.c2_sel[i];
       a.U[i] = io.U[i];
-      a.mask[i] = io.mask[i];
+      a.mask[i] = io.mask[i] ? reinterpret_cast<uint8_t*>(reinterpret_cast<uint32_t*>(io.mask[i]) +
+                                                          woff)
+                             : nullptr;
       // LL_j lives in tmp0 for odd j, tmp1 for even j
       a.llin[i] = lev >= 2 ? ((lev - 1) % 2 == 1 ? io.tmp0[i] : io.tmp1[i]) : nullptr;
       a.llout[i] = lev % 2 == 1 ? io.tmp0[i] : io.tmp1[i];
     }
+    woff += (size_t)nblocks * nt;
     a.beta = io.beta;
     a.dp = dp;
     a.n = p.n;
@@ -835,16 +860,8 @@ int dwt_analysis(const DwtPlan<T>& p, const AnalysisIO<T>& io, const DevParams* 
     a.level = lev;
     a.last = lev == p.J;
     a.Ms = p.n >> (lev - 1);
-    const int half = a.Ms >> 1;
-    // FP32 with the paper's 8 bases, subbands of side >= 64: 32 x 32 output
-    // tiles per subband (input halo re-reads (64 + 14)^2 / 64^2 = 1.49x
-    // instead of (32 + 14)^2 / 32^2 = 2.07x)
-    constexpr bool big = sizeof(T) == 4;
-    const bool wide = big && p.P == 8 &&
-                      (lev == 1 && p.an_tile1 ? p.an_tile1 == kAnTO1 : half >= 64);
-    const int to = wide ? kAnTO1 : kTO;
-    a.tiles = (half + to - 1) / to;
-    a.nblocks = a.tiles * a.tiles * p.L;
+    a.tiles = tiles;
+    a.nblocks = nblocks;
     a.role = io.role;
     a.pure = io.pure;
     a.pure_scale = io.pure_scale;
@@ -916,6 +933,17 @@ int dwt_synthesis(const DwtPlan<T>& p, const SynthesisIO<T>& io, const DevParams
     MUFFIN_HIP_CHECK(hipGetLastError());
   }
   return 0;
+}
+size_t dwt_mask_words(int n, int L, int J, int P, int elem_bytes) {
+  size_t words = 0;
+  for (int lev = 1; lev <= J; ++lev) {
+    const int half = (n >> (lev - 1)) >> 1;
+    const size_t t16 = (size_t)((half + kTO - 1) / kTO), t32 = (size_t)((half + kAnTO1 - 1) / kAnTO1);
+    size_t w = t16 * t16 * kNT;
+    if (elem_bytes == 4 && P == 8) w = std::max(w, t32 * t32 * (size_t)kAnNT1);
+    words += w * (size_t)L;
+  }
+  return words;
 }
 template int dwt_analysis<double>(const DwtPlan<double>&, const AnalysisIO<double>&,
                                   const DevParams*, hipStream_t, int, int);

@@ -147,6 +147,10 @@ struct SynthesisIO {
 // Coefficient selectors: the factor is read from DevParams at run time.
 enum CoefSel { SEL_ZERO = 0, SEL_ONE = 1, SEL_MU = 2, SEL_GAMMA = 3 };
 
+// 32-bit mask words the analysis of an n x n x L cube with J levels writes
+// per state set (one per thread and block of every level; the largest of
+// the launch shapes it may use).
+size_t dwt_mask_words(int n, int L, int J, int P, int elem_bytes);
 // Levels lev_lo..lev_hi (1-based; analysis runs them in increasing order,
 // synthesis in decreasing order).  0, 0 = all levels.
 template <typename T>

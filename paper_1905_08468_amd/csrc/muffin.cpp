@@ -215,7 +215,11 @@ size_t workspace_bytes_of(const muffin_config* c) {
   const size_t per_set = (6 + P + 4) * LN * es;
   size_t shared = LN * es * (c->sure ? 5 : 2);                  // Y, Ybar, HTy, HTybar, HTd
   shared += L * (n + 1) * 2 * n * 2 * es;                        // transfer functions
-  shared += c->sure ? 2 * (P + 1) * LN : 0;                      // masks (bytes)
+  // masks: U (bytes per coefficient for the starlet, bit words per analysis
+  // thread for the Daubechies union) and V (bytes)
+  const size_t mu_bytes = std::max(P * LN, 4 * dwt_mask_words((int)n, (int)L, c->levels,
+                                                                (int)P, (int)es));
+  shared += c->sure ? 2 * (mu_bytes + LN) : 0;
   shared += (N + L) * 8 + 4096 * 8 + 64 * 1024;                  // weights, partials, params
   if (c->stop_rel > 0) shared += (P + 1) * LN * es;              // U, V snapshots (stop rule)
   return nsets * per_set + shared;
@@ -323,7 +327,7 @@ struct Impl final : ImplBase {
       HTybar = dev.alloc<T>(LN);
       HTd = dev.alloc<T>(LN);
       for (int t = 0; t < 2; ++t) {
-        maskU[t] = dev.alloc<uint8_t>(LN * P);
+        maskU[t] = dev.alloc<uint8_t>(std::max(LN * P, 4 * dwt_mask_words(n, L, J, P, sizeof(T))));
         maskV[t] = dev.alloc<uint8_t>(LN);
       }
     }
