@@ -39,17 +39,19 @@ MFMA_BF16_PEAK, MFMA_F32_PEAK, MFMA_F64_PEAK = 2500.0, 157.3, 78.6   # TFLOP/s, 
 #   analysis_l1_deriv: as above with the mask words read; the d/dmu sets
 #     read the primal's x~, x too.  4 sets: 2*(4+12+2) + 2*(2+12+2), 4 mask
 #     bytes.
-#   dct_primal: x~, x, V in; V, T out; 1 mask byte.  2 sets.
+#   dct_primal: x~, x, V in; V, T out; the masks as bits, one 32-bit word
+#     per thread of a 64-pixel x 256-band block (1/8 byte per voxel).
+#     2 sets.
 #   dct_deriv: d/dmu: x~', x', V' in, V', T' out; d/dgamma also x~, x, and
-#     the new primal V.  4 sets: 2*5 + 2*8, 4 mask bytes.
+#     the new primal V.  4 sets: 2*5 + 2*8, 1/2 mask byte.
 #   primal_step: per trajectory x, G, H^T y, S, T in, x~ out; each
 #     derivative x', G', S', T' in, x~' out.  2 trajectories: 2*(6+5+5).
 STAGE_TRAFFIC = {
     "synthesis_l1": (54, 0),
     "analysis_l1_primal": (32, 2),
     "analysis_l1_deriv": (68, 4),
-    "dct_primal": (10, 2),
-    "dct_deriv": (26, 4),
+    "dct_primal": (10, 0.25),
+    "dct_deriv": (26, 0.5),
     "primal_step": (32, 0),
 }
 

@@ -16,6 +16,7 @@
 // coalesced 64-lane read.
 #include "internal.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -78,6 +79,7 @@ struct DctArgs {
 constexpr int kDctWaves = MUFFIN_DCT_WAVES;  // waves per block of the FP32/FP64 kernel
 constexpr int kDctMaxKt = 16;  // Lp <= 256
 constexpr int kDctKtPerWave = kDctMaxKt / kDctWaves;
+static_assert(4 * 4 * kDctKtPerWave <= 32, "a thread's DCT mask bits fit one word");
 
 // Column groups (16 pixels each) per block: the LDS tile Lp x pixels is
 // 64 KB at L = 256 in both precisions.
@@ -215,9 +217,15 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_kernel(DctArgs<T> a) {
   const T d2 = T(dct_coef(a.d2_sel[set], dp));
   T* __restrict__ V = a.V[set];
   const T* __restrict__ Vb = a.Vb[set];
-  uint8_t* __restrict__ M = a.mask[set];
+  // masks 1[|v~| <= 1] as bits of one 32-bit word per thread and block (bit
+  // 4 (G i + g) + r), written by the primal role, read by the derivative
+  // role (same launch shape)
+  uint32_t* __restrict__ MW =
+      a.mask[set] ? reinterpret_cast<uint32_t*>(a.mask[set]) + (size_t)blockIdx.x * blockDim.x +
+                        threadIdx.x
+                  : nullptr;
   const bool has_vb = Vb != nullptr;
-  const bool has_mk = a.role != ROLE_PRIMAL;  // the derivative roles read the mask
+  uint32_t mw = (a.role != ROLE_PRIMAL && MW) ? *MW : 0u;
   T al[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) {
@@ -231,7 +239,6 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_kernel(DctArgs<T> a) {
       // every operand of this k-tile in flight at once: clamped,
       // unconditional loads (values outside the cube are not used)
       T vold[G][4], vbv[G][4];
-      uint8_t mk[G][4];
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         const int pix = min(pix0 + 16 * g + lr, N - 1);
@@ -241,7 +248,6 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_kernel(DctArgs<T> a) {
           const size_t idx = (size_t)k * N + pix;
           vold[g][r] = V[idx];
           if (has_vb) vbv[g][r] = Vb[idx];
-          if (has_mk) mk[g][r] = M[idx];
         }
       }
 #pragma unroll
@@ -255,11 +261,12 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_kernel(DctArgs<T> a) {
             const size_t idx = (size_t)k * N + pix;
             const T vt = vold[g][r] + sg * al[g] * acc[i][g][r];
             T vn;
+            const uint32_t bit = 1u << (4 * (G * i + g) + r);
             if (a.role == ROLE_PRIMAL) {
               vn = vt < T(-1) ? T(-1) : (vt > T(1) ? T(1) : vt);
-              if (M) M[idx] = (vt >= T(-1) && vt <= T(1)) ? 1 : 0;
+              if (vt >= T(-1) && vt <= T(1)) mw |= bit;
             } else {
-              vn = mk[g][r] ? vt : T(0);
+              vn = (mw & bit) ? vt : T(0);
             }
             V[idx] = vn;
             bv = d1 * vn;
@@ -270,6 +277,7 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_kernel(DctArgs<T> a) {
       }
     }
   }
+  if (a.role == ROLE_PRIMAL && MW) *MW = mw;
   lds_barrier();
 
   // ---- product 2: t = alpha C^T b ----
@@ -352,6 +360,7 @@ constexpr int kBfG = 4;
 #endif
 constexpr int kBfWaves = MUFFIN_BF_WAVES;
 constexpr int kBfKtPerWave = kDctMaxKt / kBfWaves;
+static_assert(4 * 4 * kBfKtPerWave <= 32, "a thread's DCT mask bits fit one word");
 
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   hi = (__bf16)x;
@@ -475,9 +484,13 @@ __global__ void __launch_bounds__(64 * kBfWaves, 2) dct_bf16_kernel(DctBfArgs a)
   const float d2 = float(dct_coef(a.d2_sel[set], dp));
   float* __restrict__ V = a.V[set];
   const float* __restrict__ Vb = a.Vb[set];
-  uint8_t* __restrict__ M = a.mask[set];
+  // mask bits as in dct_kernel: bit 4 (kBfG i + g) + r of the thread's word
+  uint32_t* __restrict__ MW =
+      a.mask[set] ? reinterpret_cast<uint32_t*>(a.mask[set]) + (size_t)blockIdx.x * blockDim.x +
+                        threadIdx.x
+                  : nullptr;
   const bool has_vb = Vb != nullptr;
-  const bool has_mk = a.role != ROLE_PRIMAL;  // the derivative roles read the mask
+  uint32_t mw = (a.role != ROLE_PRIMAL && MW) ? *MW : 0u;
   float al[kBfG];
 #pragma unroll
   for (int g = 0; g < kBfG; ++g) {
@@ -490,7 +503,6 @@ __global__ void __launch_bounds__(64 * kBfWaves, 2) dct_bf16_kernel(DctBfArgs a)
     if (kt < nkt) {
       // phase 1: every operand of this k-tile in flight at once
       float vold[kBfG][4], vbv[kBfG][4];
-      uint8_t mk[kBfG][4];
 #pragma unroll
       for (int g = 0; g < kBfG; ++g) {
         const int pix = min(pix0 + 16 * g + lr, N - 1);
@@ -500,7 +512,6 @@ __global__ void __launch_bounds__(64 * kBfWaves, 2) dct_bf16_kernel(DctBfArgs a)
           const size_t idx = (size_t)k * N + pix;
           vold[g][r] = V[idx];
           if (has_vb) vbv[g][r] = Vb[idx];
-          if (has_mk) mk[g][r] = M[idx];
         }
       }
 #pragma unroll
@@ -515,11 +526,12 @@ __global__ void __launch_bounds__(64 * kBfWaves, 2) dct_bf16_kernel(DctBfArgs a)
             const size_t idx = (size_t)k * N + pix;
             const float vt = vold[g][r] + sg * al[g] * acc[i][g][r];
             float vn;
+            const uint32_t bit = 1u << (4 * (kBfG * i + g) + r);
             if (a.role == ROLE_PRIMAL) {
               vn = vt < -1.f ? -1.f : (vt > 1.f ? 1.f : vt);
-              if (M) M[idx] = (vt >= -1.f && vt <= 1.f) ? 1 : 0;
+              if (vt >= -1.f && vt <= 1.f) mw |= bit;
             } else {
-              vn = mk[g][r] ? vt : 0.f;
+              vn = (mw & bit) ? vt : 0.f;
             }
             V[idx] = vn;
             bv = d1 * vn;
@@ -536,6 +548,7 @@ __global__ void __launch_bounds__(64 * kBfWaves, 2) dct_bf16_kernel(DctBfArgs a)
       }
     }
   }
+  if (a.role == ROLE_PRIMAL && MW) *MW = mw;
   lds_barrier();
 #pragma unroll
   for (int i = 0; i < kBfKtPerWave; ++i)
@@ -580,6 +593,12 @@ __global__ void __launch_bounds__(64 * kBfWaves, 2) dct_bf16_kernel(DctBfArgs a)
       }
     }
   }
+}
+
+size_t dct_mask_words(int N) {
+  // blocks of 32 (FP64) or 64 pixels; 64 threads per wave
+  const size_t threads = 64 * (size_t)std::max(kDctWaves, kBfWaves);
+  return (size_t)((N + 31) / 32) * threads;
 }
 
 // host: round-to-nearest-even float -> bf16 bits

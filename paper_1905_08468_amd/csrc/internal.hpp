@@ -207,6 +207,9 @@ struct DctIO {
   int pure;                  // 1: out = C in (debug), 2: out = C^T in (debug)
 };
 
+// 32-bit mask words the spectral update writes per state set over N pixels
+// (one per thread and block; the largest of its launch shapes).
+size_t dct_mask_words(int N);
 template <typename T>
 int dct_make_plan(DctPlan<T>& p, int L, int N, int kind);
 template <typename T>

@@ -216,10 +216,11 @@ size_t workspace_bytes_of(const muffin_config* c) {
   size_t shared = LN * es * (c->sure ? 5 : 2);                  // Y, Ybar, HTy, HTybar, HTd
   shared += L * (n + 1) * 2 * n * 2 * es;                        // transfer functions
   // masks: U (bytes per coefficient for the starlet, bit words per analysis
-  // thread for the Daubechies union) and V (bytes)
+  // thread for the Daubechies union) and V (bit words per spectral thread)
   const size_t mu_bytes = std::max(P * LN, 4 * dwt_mask_words((int)n, (int)L, c->levels,
                                                                 (int)P, (int)es));
-  shared += c->sure ? 2 * (mu_bytes + LN) : 0;
+  const size_t mv_bytes = std::max(LN, 4 * dct_mask_words((int)N));
+  shared += c->sure ? 2 * (mu_bytes + mv_bytes) : 0;
   shared += (N + L) * 8 + 4096 * 8 + 64 * 1024;                  // weights, partials, params
   if (c->stop_rel > 0) shared += (P + 1) * LN * es;              // U, V snapshots (stop rule)
   return nsets * per_set + shared;
@@ -328,7 +329,7 @@ struct Impl final : ImplBase {
       HTd = dev.alloc<T>(LN);
       for (int t = 0; t < 2; ++t) {
         maskU[t] = dev.alloc<uint8_t>(std::max(LN * P, 4 * dwt_mask_words(n, L, J, P, sizeof(T))));
-        maskV[t] = dev.alloc<uint8_t>(LN);
+        maskV[t] = dev.alloc<uint8_t>(std::max(LN, 4 * dct_mask_words(N)));
       }
     }
     alpha = dev.alloc<double>(N);
