@@ -32,27 +32,27 @@ MFMA_BF16_PEAK, MFMA_F32_PEAK, MFMA_F64_PEAK = 2500.0, 157.3, 78.6   # TFLOP/s, 
 # values, mask bytes).  Each input and output array is counted once.
 #   synthesis_l1: per set the 6 level-1 detail coefficients of the 8 bases
 #     (8 x 3/4) + the 2 coarse values (8 x 1/4) in, S out.  6 sets: 6*9.
-#   analysis_l1_primal: per set x~, x in; 6 detail coefficients read and
+#   primal_step: per trajectory x, G, H^T y, S, T in, x~ and z = 2 x~ - x
+#     out; each derivative x', G', S', T' in, x~', z' out.  2 trajectories:
+#     2*(7+6+6).
+#   analysis_l1_primal: per set z in; 6 detail coefficients read and
 #     written; 2 low-pass values out; the masks of the 8 bases' outputs as
 #     bits, one 32-bit word per thread of a 64 x 64 tile (1 byte per
-#     voxel) out.  2 sets.
+#     voxel) out.  2 sets: 2*(1+12+2).
 #   analysis_l1_deriv: as above with the mask words read; the d/dmu sets
-#     read the primal's x~, x too.  4 sets: 2*(4+12+2) + 2*(2+12+2), 4 mask
+#     read the primal's z too.  4 sets: 2*(2+12+2) + 2*(1+12+2), 4 mask
 #     bytes.
-#   dct_primal: x~, x, V in; V, T out; the masks as bits, one 32-bit word
-#     per thread of a 64-pixel x 256-band block (1/8 byte per voxel).
-#     2 sets.
-#   dct_deriv: d/dmu: x~', x', V' in, V', T' out; d/dgamma also x~, x, and
-#     the new primal V.  4 sets: 2*5 + 2*8, 1/2 mask byte.
-#   primal_step: per trajectory x, G, H^T y, S, T in, x~ out; each
-#     derivative x', G', S', T' in, x~' out.  2 trajectories: 2*(6+5+5).
+#   dct_primal: z, V in; V, T out; the masks as bits, one 32-bit word per
+#     thread of a 64-pixel x 256-band block (1/8 byte per voxel).  2 sets.
+#   dct_deriv: d/dmu: z', V' in, V', T' out; d/dgamma also z and the new
+#     primal V.  4 sets: 2*4 + 2*6, 1/2 mask byte.
 STAGE_TRAFFIC = {
     "synthesis_l1": (54, 0),
-    "analysis_l1_primal": (32, 2),
-    "analysis_l1_deriv": (68, 4),
-    "dct_primal": (10, 0.25),
-    "dct_deriv": (26, 0.5),
-    "primal_step": (32, 0),
+    "analysis_l1_primal": (30, 2),
+    "analysis_l1_deriv": (62, 4),
+    "dct_primal": (8, 0.25),
+    "dct_deriv": (20, 0.5),
+    "primal_step": (38, 0),
 }
 
 

@@ -55,10 +55,8 @@ __device__ __forceinline__ double dct_coef(int sel, const DevParams* dp) {
 
 template <typename T>
 struct DctArgs {
-  const T* xt_a[kMaxSets];
-  const T* x_a[kMaxSets];
-  const T* xt_b[kMaxSets];
-  const T* x_b[kMaxSets];
+  const T* z_a[kMaxSets];    // input z = c1 z_a + c2 z_b
+  const T* z_b[kMaxSets];
   int c1_sel[kMaxSets], c2_sel[kMaxSets];
   T* V[kMaxSets];
   const T* Vb[kMaxSets];
@@ -117,34 +115,28 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_kernel(DctArgs<T> a) {
   const int lr = lane & 15, lk = lane >> 4;
   const DevParams* dp = a.dp;
 
-  // ---- stage z = c1 (2 xt_a - x_a) + c2 (2 xt_b - x_b), zero padded ----
+  // ---- stage z = c1 z_a + c2 z_b (the operand itself for pure), zero padded ----
   {
     const double c1 = a.pure ? 1.0 : dct_coef(a.c1_sel[set], dp);
     const double c2 = a.pure ? 0.0 : dct_coef(a.c2_sel[set], dp);
     // Operands of U items are loaded unconditionally (indices clamped into
     // the cube; out-of-range items are zeroed afterwards) before any is
     // used, so they are all in flight together.
-    const T* xa = a.x_a[set];
-    const T* ta = a.pure ? xa : a.xt_a[set];
-    const bool has_b = !a.pure && a.x_b[set] != nullptr;
-    const T* xb = has_b ? a.x_b[set] : xa;
-    const T* tb = has_b ? a.xt_b[set] : xa;
+    const T* za = a.z_a[set];
+    const bool has_b = !a.pure && a.z_b[set] != nullptr;
+    const T* zb = has_b ? a.z_b[set] : za;
     constexpr int U = 8;
     constexpr int NT = 64 * kDctWaves;
     const int total = Lp * PIX;
     for (int t0 = threadIdx.x; t0 < total; t0 += U * NT) {
-      T v0[U], v1[U], v2[U], v3[U];
+      T va[U], vb[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int t = min(t0 + u * NT, total - 1);
         const int l = t / PIX, j = t - l * PIX;
         const size_t idx = (size_t)min(l, L - 1) * N + min(pix0 + j, N - 1);
-        v0[u] = ta[idx];
-        v1[u] = xa[idx];
-        if (has_b) {
-          v2[u] = tb[idx];
-          v3[u] = xb[idx];
-        }
+        va[u] = za[idx];
+        if (has_b) vb[u] = zb[idx];
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -153,12 +145,8 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_kernel(DctArgs<T> a) {
           const int l = t / PIX, j = t - l * PIX;
           T z = T(0);
           if (l < L && pix0 + j < N) {
-            if (a.pure) {
-              z = v1[u];
-            } else {
-              z = T(c1) * (T(2) * v0[u] - v1[u]);
-              if (has_b) z += T(c2) * (T(2) * v2[u] - v3[u]);
-            }
+            z = T(c1) * va[u];
+            if (has_b) z += T(c2) * vb[u];
           }
           Z[t] = z;
         }
@@ -332,10 +320,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 struct DctBfArgs {
-  const float* xt_a[kMaxSets];
-  const float* x_a[kMaxSets];
-  const float* xt_b[kMaxSets];
-  const float* x_b[kMaxSets];
+  const float* z_a[kMaxSets];  // input z = c1 z_a + c2 z_b
+  const float* z_b[kMaxSets];
   int c1_sel[kMaxSets], c2_sel[kMaxSets];
   float* V[kMaxSets];
   const float* Vb[kMaxSets];
@@ -382,11 +368,9 @@ __global__ void __launch_bounds__(64 * kBfWaves, 2) dct_bf16_kernel(DctBfArgs a)
   {
     const double c1 = a.pure ? 1.0 : dct_coef(a.c1_sel[set], dp);
     const double c2 = a.pure ? 0.0 : dct_coef(a.c2_sel[set], dp);
-    const float* xa = a.x_a[set];
-    const float* ta = a.pure ? xa : a.xt_a[set];
-    const bool has_b = !a.pure && a.x_b[set] != nullptr;
-    const float* xb = has_b ? a.x_b[set] : xa;
-    const float* tb = has_b ? a.xt_b[set] : xa;
+    const float* za = a.z_a[set];
+    const bool has_b = !a.pure && a.z_b[set] != nullptr;
+    const float* zb = has_b ? a.z_b[set] : za;
     // each thread converts 8 consecutive bands of one pixel and stores them
     // as one 16-byte hi and one 16-byte lo vector; the operands of the 8
     // bands are loaded unconditionally (clamped indices) before any is used
@@ -395,16 +379,12 @@ __global__ void __launch_bounds__(64 * kBfWaves, 2) dct_bf16_kernel(DctBfArgs a)
       const int lg = t / kBfPix, j = t - lg * kBfPix;
       const int pix = pix0 + j;
       const int pc = min(pix, N - 1);
-      float v0[8], v1[8], v2[8], v3[8];
+      float va[8], vb[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const size_t idx = (size_t)min(8 * lg + e, L - 1) * N + pc;
-        v0[e] = ta[idx];
-        v1[e] = xa[idx];
-        if (has_b) {
-          v2[e] = tb[idx];
-          v3[e] = xb[idx];
-        }
+        va[e] = za[idx];
+        if (has_b) vb[e] = zb[idx];
       }
       bf16x8 vh, vl;
 #pragma unroll
@@ -412,12 +392,8 @@ __global__ void __launch_bounds__(64 * kBfWaves, 2) dct_bf16_kernel(DctBfArgs a)
         const int l = 8 * lg + e;
         float z = 0.f;
         if (l < L && pix < N) {
-          if (a.pure) {
-            z = v1[e];
-          } else {
-            z = float(c1) * (2.f * v0[e] - v1[e]);
-            if (has_b) z += float(c2) * (2.f * v2[e] - v3[e]);
-          }
+          z = float(c1) * va[e];
+          if (has_b) z += float(c2) * vb[e];
         }
         __bf16 h, lo;
         split_bf16(z, h, lo);
@@ -682,10 +658,8 @@ static int dct_update_bf16(const DctPlan<float>& p, const DctIO<float>& io, cons
                            hipStream_t s) {
   DctBfArgs a{};
   for (int i = 0; i < io.nsets; ++i) {
-    a.xt_a[i] = io.xt_a[i];
-    a.x_a[i] = io.x_a[i];
-    a.xt_b[i] = io.xt_b[i];
-    a.x_b[i] = io.x_b[i];
+    a.z_a[i] = io.z_a[i];
+    a.z_b[i] = io.z_b[i];
     a.c1_sel[i] = io.c1_sel[i];
     a.c2_sel[i] = io.c2_sel[i];
     a.V[i] = io.V[i];
@@ -724,10 +698,8 @@ int dct_update(const DctPlan<T>& p, const DctIO<T>& io, const DevParams* dp, hip
   }
   DctArgs<T> a{};
   for (int i = 0; i < io.nsets; ++i) {
-    a.xt_a[i] = io.xt_a[i];
-    a.x_a[i] = io.x_a[i];
-    a.xt_b[i] = io.xt_b[i];
-    a.x_b[i] = io.x_b[i];
+    a.z_a[i] = io.z_a[i];
+    a.z_b[i] = io.z_b[i];
     a.c1_sel[i] = io.c1_sel[i];
     a.c2_sel[i] = io.c2_sel[i];
     a.V[i] = io.V[i];

@@ -212,10 +212,8 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t boff, 
 
 template <typename T>
 struct AnArgs {
-  const T* xt_a[kMaxSets];
-  const T* x_a[kMaxSets];
-  const T* xt_b[kMaxSets];
-  const T* x_b[kMaxSets];
+  const T* z_a[kMaxSets];    // level-1 input z = c1 z_a + c2 z_b
+  const T* z_b[kMaxSets];
   int c1_sel[kMaxSets], c2_sel[kMaxSets];
   T* U[kMaxSets];
   uint8_t* mask[kMaxSets];   // this level's mask words (uint32 per block thread) or null
@@ -429,29 +427,24 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_an(AnArgs<T> a) {
   };
   // ---- stage the input tile (periodic wrap) ----
   if constexpr (!DEEP) {
-    // level 1: z = c1 (2 x~ - x) [+ c2 (2 x~b - xb)], all loads issued first
+    // level 1: z = c1 z_a [+ c2 z_b] (z = 2 x~ - x of a set), all loads
+    // issued first
     const double c1 = coef_of(a.c1_sel[set], a.dp), c2 = coef_of(a.c2_sel[set], a.dp);
-    const auto rxa = plane_rsrc(a.x_a[set] + (size_t)band * plane, plane);
-    const auto rta = plane_rsrc(a.xt_a[set] + (size_t)band * plane, plane);
-    const bool has_b = a.x_b[set] != nullptr;
-    const auto rxb = plane_rsrc((has_b ? a.x_b[set] : a.x_a[set]) + (size_t)band * plane, plane);
-    const auto rtb = plane_rsrc((has_b ? a.xt_b[set] : a.xt_a[set]) + (size_t)band * plane, plane);
-    T v0[NI], v1[NI], v2[NI], v3[NI];
+    const auto rza = plane_rsrc(a.z_a[set] + (size_t)band * plane, plane);
+    const bool has_b = a.z_b[set] != nullptr;
+    const auto rzb = plane_rsrc((has_b ? a.z_b[set] : a.z_a[set]) + (size_t)band * plane, plane);
+    T va[NI], vb[NI];
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-      v0[i] = buf_ld<T>(rta, ioff[i]);
-      v1[i] = buf_ld<T>(rxa, ioff[i]);
-      if (has_b) {
-        v2[i] = buf_ld<T>(rtb, ioff[i]);
-        v3[i] = buf_ld<T>(rxb, ioff[i]);
-      }
+      va[i] = buf_ld<T>(rza, ioff[i]);
+      if (has_b) vb[i] = buf_ld<T>(rzb, ioff[i]);
     }
     const T tc1 = T(c1), tc2 = T(c2);
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
       const int t = threadIdx.x + i * NT;
-      T z = tc1 * (T(2) * v0[i] - v1[i]);
-      if (has_b) z += tc2 * (T(2) * v2[i] - v3[i]);
+      T z = tc1 * va[i];
+      if (has_b) z += tc2 * vb[i];
       if (t < IN * IN) s_in[t] = z;
     }
   } else {
@@ -837,10 +830,8 @@ int dwt_analysis(const DwtPlan<T>& p, const AnalysisIO<T>& io, const DevParams* 
     shape(lev, wide, tiles, nblocks, nt);
     AnArgs<T> a{};
     for (int i = 0; i < io.nsets; ++i) {
-      a.xt_a[i] = io.xt_a[i];
-      a.x_a[i] = io.x_a[i];
-      a.xt_b[i] = io.xt_b[i];
-      a.x_b[i] = io.x_b[i];
+      a.z_a[i] = io.z_a[i];
+      a.z_b[i] = io.z_b[i];
       a.c1_sel[i] = io.c1_sel[i];
       a.c2_sel[i] = io.c2_sel[i];
       a.U[i] = io.U[i];

@@ -43,6 +43,7 @@ __global__ void __launch_bounds__(kEwNT) primal_kernel(PrimalIO<T> io, size_t co
   const T* __restrict__ s0 = io.s[tr][0];
   const T* __restrict__ t0 = io.t[tr][0];
   T* __restrict__ o0 = io.xt[tr][0];
+  T* __restrict__ z0 = io.z[tr][0];
   const int nd = io.nderiv;
   for (size_t i = blockIdx.x * (size_t)kEwNT + threadIdx.x; i < count;
        i += (size_t)gridDim.x * kEwNT) {
@@ -61,16 +62,21 @@ __global__ void __launch_bounds__(kEwNT) primal_kernel(PrimalIO<T> io, size_t co
     // term of the primal update is mu s, and its mu-derivative
     // s + mu s' (the primal's s is in registers already)
     const T sp = s0[i];
-    const T m = x0[i] - tau * ((g0[i] - hy[i]) + mu * sp + t0[i]);
+    const T xp = x0[i];
+    const T m = xp - tau * ((g0[i] - hy[i]) + mu * sp + t0[i]);
     const bool pos = m > T(0);
-    o0[i] = pos ? m : T(0);
+    const T op = pos ? m : T(0);
+    o0[i] = op;
+    z0[i] = T(2) * op - xp;
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
       if (d < nd) {
         T sterm = mu * sd[d];
         if (d == 0) sterm += sp;  // d/dmu set
         const T md = xd[d] - tau * (gd[d] + sterm + td[d]);
-        io.xt[tr][d + 1][i] = pos ? md : T(0);
+        const T od = pos ? md : T(0);
+        io.xt[tr][d + 1][i] = od;
+        io.z[tr][d + 1][i] = T(2) * od - xd[d];
       }
     }
   }

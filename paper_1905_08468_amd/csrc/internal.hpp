@@ -114,10 +114,10 @@ enum DualRole { ROLE_PRIMAL = 0, ROLE_DERIV = 1 };
 // followed by the dual update of U_s with scale sigma * beta_l / sqrt(P).
 template <typename T>
 struct AnalysisIO {
-  const T* xt_a[kMaxSets];
-  const T* x_a[kMaxSets];
-  const T* xt_b[kMaxSets];
-  const T* x_b[kMaxSets];
+  // level-1 input z = c1 z_a + c2 z_b, where z_a, z_b are 2 x~ - x of a set
+  // (made by the primal step), or the operand itself (set-up and debug ops)
+  const T* z_a[kMaxSets];
+  const T* z_b[kMaxSets];  // or null
   int c1_sel[kMaxSets];   // which theta factor multiplies the a-term
   int c2_sel[kMaxSets];   // and the b-term (see CoefSel)
   T* U[kMaxSets];         // [L][P][n][n] in/out
@@ -191,10 +191,8 @@ struct DctPlan {
 
 template <typename T>
 struct DctIO {
-  const T* xt_a[kMaxSets];
-  const T* x_a[kMaxSets];
-  const T* xt_b[kMaxSets];
-  const T* x_b[kMaxSets];
+  const T* z_a[kMaxSets];    // input z = c1 z_a + c2 z_b (as AnalysisIO)
+  const T* z_b[kMaxSets];    // or null
   int c1_sel[kMaxSets], c2_sel[kMaxSets];
   T* V[kMaxSets];
   const T* Vb[kMaxSets];     // second term of the adjoint input (new primal V)
@@ -227,6 +225,7 @@ struct PrimalIO {
   const T* s[2][3];      // beta_l / sqrt(P) W_s^T u of each set (no mu)
   const T* t[2][3];
   T* xt[2][3];
+  T* z[2][3];            // 2 x~ - x of each set, the analyses' input
   int ntraj, nderiv;
 };
 template <typename T>

@@ -309,6 +309,10 @@ struct Impl final : ImplBase {
   cplx<T>* specB(int s) { return reinterpret_cast<cplx<T>*>(scr[s] + 2 * LN); }
   T* tmp0(int s) { return scr[s]; }
   T* tmp1(int s) { return scr[s] + 2 * LN; }
+  // 2 x~ - x of set s: written by the primal step, read by the spatial and
+  // spectral analyses of the same iteration (the last quarter of the
+  // scratch, which the low-pass temporaries never reach)
+  T* zbuf(int s) { return scr[s] + 3 * LN; }
 
   int init() override {
     for (int s = 0; s < nsets; ++s) {
@@ -493,8 +497,7 @@ struct Impl final : ImplBase {
         // from the transform of the dirty cube (U of set 0 is zeroed below)
         AnalysisIO<T> io{};
         io.nsets = 1;
-        io.xt_a[0] = Y;
-        io.x_a[0] = Y;
+        io.z_a[0] = Y;
         io.c1_sel[0] = SEL_ONE;
         io.c2_sel[0] = SEL_ZERO;
         io.U[0] = U[0];
@@ -656,6 +659,7 @@ struct Impl final : ImplBase {
           io.s[t][d] = S[s];
           io.t[t][d] = Tt[s];
           io.xt[t][d] = Xt[s];
+          io.z[t][d] = zbuf(s);
         }
         io.hty[t] = t == 0 ? HTy : HTybar;
       }
@@ -670,8 +674,7 @@ struct Impl final : ImplBase {
       io.nsets = sure ? 2 : 1;
       io.beta = beta;
       for (int s = 0; s < io.nsets; ++s) {
-        io.xt_a[s] = Xt[s];
-        io.x_a[s] = X[s];
+        io.z_a[s] = zbuf(s);
         io.c1_sel[s] = SEL_MU;
         io.c2_sel[s] = SEL_ZERO;
         io.U[s] = U[s];
@@ -695,11 +698,9 @@ struct Impl final : ImplBase {
         for (int i = 0; i < 4; ++i) {
           const int s = 2 + i, prim = i < 2 ? 0 : 1;
           const bool is_mu = (i % 2) == 0;
-          d.xt_a[i] = Xt[s];
-          d.x_a[i] = X[s];
+          d.z_a[i] = zbuf(s);
           d.c1_sel[i] = SEL_MU;
-          d.xt_b[i] = is_mu ? Xt[prim] : nullptr;
-          d.x_b[i] = is_mu ? X[prim] : nullptr;
+          d.z_b[i] = is_mu ? zbuf(prim) : nullptr;
           d.c2_sel[i] = is_mu ? SEL_ONE : SEL_ZERO;
           d.U[i] = U[s];
           d.mask[i] = maskU[prim];
@@ -723,8 +724,7 @@ struct Impl final : ImplBase {
       io.nsets = sure ? 2 : 1;
       io.alpha = alpha;
       for (int s = 0; s < io.nsets; ++s) {
-        io.xt_a[s] = Xt[s];
-        io.x_a[s] = X[s];
+        io.z_a[s] = zbuf(s);
         io.c1_sel[s] = SEL_GAMMA;
         io.c2_sel[s] = SEL_ZERO;
         io.V[s] = V[s];
@@ -745,11 +745,9 @@ struct Impl final : ImplBase {
         for (int i = 0; i < 4; ++i) {
           const int s = 2 + i, prim = i < 2 ? 0 : 1;
           const bool is_ga = (i % 2) == 1;
-          d.xt_a[i] = Xt[s];
-          d.x_a[i] = X[s];
+          d.z_a[i] = zbuf(s);
           d.c1_sel[i] = SEL_GAMMA;
-          d.xt_b[i] = is_ga ? Xt[prim] : nullptr;
-          d.x_b[i] = is_ga ? X[prim] : nullptr;
+          d.z_b[i] = is_ga ? zbuf(prim) : nullptr;
           d.c2_sel[i] = is_ga ? SEL_ONE : SEL_ZERO;
           d.V[i] = V[s];
           d.Vb[i] = is_ga ? V[prim] : nullptr;
@@ -1107,8 +1105,7 @@ struct Impl final : ImplBase {
     io.nsets = sure ? 2 : 1;
     io.beta = beta;
     for (int s = 0; s < io.nsets; ++s) {
-      io.xt_a[s] = Xt[s];
-      io.x_a[s] = X[s];
+      io.z_a[s] = zbuf(s);
       io.c1_sel[s] = SEL_MU;
       io.c2_sel[s] = SEL_ZERO;
       io.U[s] = U[s];
@@ -1124,11 +1121,9 @@ struct Impl final : ImplBase {
     d.beta = beta;
     for (int i = 0; i < 4; ++i) {
       const int s = 2 + i, prim = i < 2 ? 0 : 1;
-      d.xt_a[i] = Xt[s];
-      d.x_a[i] = X[s];
+      d.z_a[i] = zbuf(s);
       d.c1_sel[i] = SEL_MU;
-      d.xt_b[i] = (i % 2) == 0 ? Xt[prim] : nullptr;
-      d.x_b[i] = (i % 2) == 0 ? X[prim] : nullptr;
+      d.z_b[i] = (i % 2) == 0 ? zbuf(prim) : nullptr;
       d.c2_sel[i] = (i % 2) == 0 ? SEL_ONE : SEL_ZERO;
       d.U[i] = U[s];
       d.mask[i] = maskU[prim];
@@ -1167,6 +1162,7 @@ struct Impl final : ImplBase {
       RC(fill_zero(X[s], LN, st));
       RC(fill_zero(Xt[s], LN, st));
       RC(fill_zero(U[s], LN * P, st));
+      RC(fill_zero(zbuf(s), LN, st));
     }
     RC(fill_zero(beta, (size_t)L, st));
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1260,8 +1256,7 @@ struct Impl final : ImplBase {
       case 3: {
         AnalysisIO<T> io{};
         io.nsets = 1;
-        io.xt_a[0] = x;
-        io.x_a[0] = x;
+        io.z_a[0] = x;
         io.c1_sel[0] = SEL_ONE;
         io.c2_sel[0] = SEL_ZERO;
         io.U[0] = y;
@@ -1285,7 +1280,7 @@ struct Impl final : ImplBase {
       case 6: {
         DctIO<T> io{};
         io.nsets = 1;
-        io.x_a[0] = x;
+        io.z_a[0] = x;
         io.V[0] = y;
         io.pure = kind == 5 ? 1 : 2;
         return dct_update(dct, io, nullptr, st);

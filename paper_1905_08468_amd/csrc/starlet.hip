@@ -44,11 +44,9 @@ __device__ __forceinline__ double st_coef(int sel, const DevParams* dp) {
 
 template <typename T>
 struct StArgs {
-  // analysis, scale 1: z = c1 (2 xt_a - x_a) + c2 (2 xt_b - x_b)
-  const T* xt_a[kMaxSets];
-  const T* x_a[kMaxSets];
-  const T* xt_b[kMaxSets];
-  const T* x_b[kMaxSets];
+  // analysis, scale 1: z = c1 z_a + c2 z_b (z = 2 x~ - x of a set)
+  const T* z_a[kMaxSets];
+  const T* z_b[kMaxSets];
   int c1_sel[kMaxSets], c2_sel[kMaxSets];
   // the scale's input plane: analysis c_(j-1) (scales >= 2), synthesis r_j,
   // at in[set] + (band * in_planes + in_plane) * N
@@ -105,16 +103,14 @@ __global__ void __launch_bounds__(kStNT) st_an(StArgs<T> a) {
   const size_t boff = (size_t)band * N;
   if (a.level == 1) {
     const double c1 = st_coef(a.c1_sel[set], a.dp), c2 = st_coef(a.c2_sel[set], a.dp);
-    const T* xa = a.x_a[set] + boff;
-    const T* ta = a.xt_a[set] + boff;
-    const bool has_b = a.x_b[set] != nullptr;
-    const T* xb = has_b ? a.x_b[set] + boff : xa;
-    const T* tb = has_b ? a.xt_b[set] + boff : ta;
+    const T* za = a.z_a[set] + boff;
+    const bool has_b = a.z_b[set] != nullptr;
+    const T* zb = has_b ? a.z_b[set] + boff : za;
     for (int t = threadIdx.x; t < W * W; t += kStNT) {
       const int r = t / W, c = t - r * W;
       const size_t g = (size_t)((i0 - R + r) & msk) * n + ((j0 - R + c) & msk);
-      T z = T(c1) * (T(2) * ta[g] - xa[g]);
-      if (has_b) z += T(c2) * (T(2) * tb[g] - xb[g]);
+      T z = T(c1) * za[g];
+      if (has_b) z += T(c2) * zb[g];
       s_in[t] = z;
     }
   } else {
@@ -253,10 +249,8 @@ int starlet_analysis(const StarletPlan& p, const AnalysisIO<T>& io, const DevPar
     StArgs<T> a{};
     st_prepare(a, p, lev);
     for (int i = 0; i < io.nsets; ++i) {
-      a.xt_a[i] = io.xt_a[i];
-      a.x_a[i] = io.x_a[i];
-      a.xt_b[i] = io.xt_b[i];
-      a.x_b[i] = io.x_b[i];
+      a.z_a[i] = io.z_a[i];
+      a.z_b[i] = io.z_b[i];
       a.c1_sel[i] = io.c1_sel[i];
       a.c2_sel[i] = io.c2_sel[i];
       a.U[i] = io.U[i];
