@@ -617,6 +617,13 @@ def main():
                     "value": round(k64 / f["elapsed"], 4), "unit": "iters/s",
                     "ms_per_step": round(1e3 * f["elapsed"] / k64, 2)}
             log(f"[bench] plain FP64: {fp64['value']} it/s")
+            # the same plain method in the default precision form, for the
+            # speedup of that form over the FP64 GPU method
+            fm = run_form(mm, torch, prob, mode, False, k64, 1)
+            mixed = k64 / fm["elapsed"]
+            fp64["same_method_in_this_form"] = {"value": round(mixed, 4), "unit": "iters/s",
+                                                "speedup_vs_fp64": round(mixed / fp64["value"], 3)}
+            log(f"[bench] plain {args.mode}: {mixed:.3f} it/s, x{mixed / fp64['value']:.2f} vs FP64")
         except Exception as e:  # report, do not hide
             fp64 = {"error": str(e)}
     if args.calib:
