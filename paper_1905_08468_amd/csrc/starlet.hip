@@ -86,6 +86,18 @@ __device__ __forceinline__ T st_col(const T* s_row, int r, int c, int R, int d) 
   return acc;
 }
 
+// Blocks are handed to the 8 XCDs round-robin; logical block b of XCD x is
+// (x * per + b), so neighbouring tiles (which share halo rows) share an L2.
+__device__ __forceinline__ int st_remap(int b, int nb) {
+  const int per = (nb + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+static inline int st_grid(int nb) { return ((nb + 7) >> 3) << 3; }
+
+// outputs per thread of a tile
+constexpr int kStOPT = kStTS * kStTS / kStNT;
+static_assert(kStOPT * kStNT == kStTS * kStTS, "whole outputs per thread");
+
 // analysis scale `level` with the fused dual update of planes level-1 (and J)
 template <typename T>
 __global__ void __launch_bounds__(kStNT) st_an(StArgs<T> a) {
@@ -93,7 +105,7 @@ __global__ void __launch_bounds__(kStNT) st_an(StArgs<T> a) {
   T* s_in = reinterpret_cast<T*>(st_smem);
   const int d = 1 << (a.level - 1), R = 2 * d, W = kStTS + 2 * R;
   T* s_row = s_in + W * W;
-  const int lb = blockIdx.x;
+  const int lb = st_remap(blockIdx.x, a.nblocks);
   if (lb >= a.nblocks) return;
   const int tiles2 = a.tiles * a.tiles;
   const int band = lb / tiles2, tile = lb - band * tiles2;
@@ -101,6 +113,34 @@ __global__ void __launch_bounds__(kStNT) st_an(StArgs<T> a) {
   const int set = blockIdx.y, n = a.n, msk = n - 1;
   const size_t N = (size_t)n * n;
   const size_t boff = (size_t)band * N;
+  // dual values (and masks) of this thread's outputs, fetched before the
+  // tile so their latency overlaps the staging and the filtering (indices
+  // of outputs outside the image are clamped to a valid element)
+  const bool last = a.level == a.J;
+  const bool mask_out = a.role == ROLE_PRIMAL && a.mask[set] != nullptr && !a.pure;
+  const bool mask_in = a.role == ROLE_DERIV && a.mask[set] != nullptr;
+  T* U = a.U[set];
+  uint8_t* M = a.mask[set];
+  const size_t pw = ((size_t)band * a.planes + (a.level - 1)) * N;  // plane of w_j
+  const size_t pc = ((size_t)band * a.planes + a.J) * N;            // plane of c_J
+  size_t opix[kStOPT];
+  T uw[kStOPT], uc[kStOPT];
+  uint8_t mw[kStOPT], mc[kStOPT];
+#pragma unroll
+  for (int k = 0; k < kStOPT; ++k) {
+    const int t = threadIdx.x + k * kStNT;
+    const int r = t / kStTS, c = t - r * kStTS;
+    const int gi = min(i0 + r, n - 1), gj = min(j0 + c, n - 1);
+    opix[k] = (size_t)gi * n + gj;
+    if (!a.pure) {
+      uw[k] = U[pw + opix[k]];
+      if (last) uc[k] = U[pc + opix[k]];
+      if (mask_in) {
+        mw[k] = M[pw + opix[k]];
+        if (last) mc[k] = M[pc + opix[k]];
+      }
+    }
+  }
   if (a.level == 1) {
     const double c1 = st_coef(a.c1_sel[set], a.dp), c2 = st_coef(a.c2_sel[set], a.dp);
     const T* za = a.z_a[set] + boff;
@@ -125,37 +165,32 @@ __global__ void __launch_bounds__(kStNT) st_an(StArgs<T> a) {
   lds_barrier();
   const double beta = a.beta ? a.beta[band] : 1.0;
   const T scale = T(a.dp ? a.dp->sigma * beta : 0.0);
-  const bool mask_out = a.role == ROLE_PRIMAL && a.mask[set] != nullptr && !a.pure;
-  const bool mask_in = a.role == ROLE_DERIV && a.mask[set] != nullptr;
-  T* U = a.U[set];
-  uint8_t* M = a.mask[set];
-  auto update = [&](int plane, size_t pix, T val) {
-    const size_t idx = ((size_t)band * a.planes + plane) * N + pix;
+  auto update = [&](size_t idx, T val, T uold, uint8_t mold) {
     if (a.pure) {
       U[idx] = T(a.pure_scale) * val;
       return;
     }
-    const T pv = U[idx] + scale * val;
+    const T pv = uold + scale * val;
     if (a.role == ROLE_PRIMAL) {
       U[idx] = pv < T(-1) ? T(-1) : (pv > T(1) ? T(1) : pv);
       if (mask_out) M[idx] = (pv >= T(-1) && pv <= T(1)) ? 1 : 0;
     } else {
-      U[idx] = (mask_in && M[idx]) ? pv : T(0);
+      U[idx] = (mask_in && mold) ? pv : T(0);
     }
   };
-  const bool last = a.level == a.J;
-  for (int t = threadIdx.x; t < kStTS * kStTS; t += kStNT) {
+#pragma unroll
+  for (int k = 0; k < kStOPT; ++k) {
+    const int t = threadIdx.x + k * kStNT;
     const int r = t / kStTS, c = t - r * kStTS;
-    const int gi = i0 + r, gj = j0 + c;
-    if (gi >= n || gj >= n) continue;
+    if (i0 + r >= n || j0 + c >= n) continue;
     const T cj = st_col(s_row, r, c, R, d);
     const T z0 = s_in[(r + R) * W + c + R];
-    const size_t pix = (size_t)gi * n + gj;
-    update(a.level - 1, pix, z0 - cj);  // w_j
+    const size_t pix = opix[k];
+    update(pw + pix, z0 - cj, uw[k], mw[k]);  // w_j
     if (last)
-      update(a.J, pix, cj);             // the coarse plane c_J
+      update(pc + pix, cj, uc[k], mc[k]);     // the coarse plane c_J
     else
-      a.out[set][boff + pix] = cj;      // c_j for the next scale
+      a.out[set][boff + pix] = cj;            // c_j for the next scale
   }
 }
 
@@ -166,7 +201,7 @@ __global__ void __launch_bounds__(kStNT) st_sy(StArgs<T> a) {
   T* s_in = reinterpret_cast<T*>(st_smem);
   const int d = 1 << (a.level - 1), R = 2 * d, W = kStTS + 2 * R;
   T* s_row = s_in + W * W;
-  const int lb = blockIdx.x;
+  const int lb = st_remap(blockIdx.x, a.nblocks);
   if (lb >= a.nblocks) return;
   const int tiles2 = a.tiles * a.tiles;
   const int band = lb / tiles2, tile = lb - band * tiles2;
@@ -175,6 +210,14 @@ __global__ void __launch_bounds__(kStNT) st_sy(StArgs<T> a) {
   const size_t N = (size_t)n * n;
   const T* rin = a.in[set] + ((size_t)band * a.in_planes + a.in_plane) * N;
   const T* u = a.U[set] + ((size_t)band * a.planes + (a.level - 1)) * N;
+  // u at this thread's outputs, fetched first (clamped indices)
+  T uo[kStOPT];
+#pragma unroll
+  for (int k = 0; k < kStOPT; ++k) {
+    const int t = threadIdx.x + k * kStNT;
+    const int r = t / kStTS, c = t - r * kStTS;
+    uo[k] = u[(size_t)min(i0 + r, n - 1) * n + min(j0 + c, n - 1)];
+  }
   for (int t = threadIdx.x; t < W * W; t += kStNT) {
     const int r = t / W, c = t - r * W;
     const size_t g = (size_t)((i0 - R + r) & msk) * n + ((j0 - R + c) & msk);
@@ -185,12 +228,13 @@ __global__ void __launch_bounds__(kStNT) st_sy(StArgs<T> a) {
   lds_barrier();
   const T sc = T(a.level == 1 && a.beta ? a.beta[band] : 1.0);
   T* out = a.out[set] + (size_t)band * N;
-  for (int t = threadIdx.x; t < kStTS * kStTS; t += kStNT) {
+#pragma unroll
+  for (int k = 0; k < kStOPT; ++k) {
+    const int t = threadIdx.x + k * kStNT;
     const int r = t / kStTS, c = t - r * kStTS;
     const int gi = i0 + r, gj = j0 + c;
     if (gi >= n || gj >= n) continue;
-    const size_t pix = (size_t)gi * n + gj;
-    out[pix] = sc * (u[pix] + st_col(s_row, r, c, R, d));
+    out[(size_t)gi * n + gj] = sc * (uo[k] + st_col(s_row, r, c, R, d));
   }
 }
 
@@ -268,7 +312,7 @@ int starlet_analysis(const StarletPlan& p, const AnalysisIO<T>& io, const DevPar
     a.pure_scale = io.pure_scale;
     const size_t shm = st_lds_bytes<T>(lev);
     MUFFIN_ALLOW_BIG_LDS((st_an<T>));
-    st_an<T><<<dim3(a.nblocks, io.nsets), kStNT, shm, s>>>(a);
+    st_an<T><<<dim3(st_grid(a.nblocks), io.nsets), kStNT, shm, s>>>(a);
     MUFFIN_HIP_CHECK(hipGetLastError());
   }
   return 0;
@@ -291,7 +335,7 @@ int starlet_synthesis(const StarletPlan& p, const SynthesisIO<T>& io, hipStream_
     a.beta = io.beta;
     const size_t shm = st_lds_bytes<T>(lev);
     MUFFIN_ALLOW_BIG_LDS((st_sy<T>));
-    st_sy<T><<<dim3(a.nblocks, io.nsets), kStNT, shm, s>>>(a);
+    st_sy<T><<<dim3(st_grid(a.nblocks), io.nsets), kStNT, shm, s>>>(a);
     MUFFIN_HIP_CHECK(hipGetLastError());
   }
   return 0;
