@@ -201,6 +201,7 @@ __device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t boff, uin
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, boff, soff, 0));
 }
 typedef unsigned int muffin_u32x2 __attribute__((__vector_size__(8)));
+typedef float muffin_f32x4 __attribute__((ext_vector_type(4)));
 template <typename T>
 __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t boff, T v,
                                        uint32_t soff = 0) {
@@ -509,10 +510,16 @@ struct SyArgs {
 // Per-thread LDS positions of the separable synthesis, the same for every
 // basis (computed once per block): the column pass slides over APT
 // coefficient rows of one column of a quadrant pair, the row pass produces
-// 2 BPT consecutive outputs of one row.
-template <int TC, int NT, int APT_, int BPT_>
+// 2 BPT consecutive outputs of one row.  V4: the staged tile's rows start
+// one column earlier (at a multiple of four) and have WC = W + 1 columns, so
+// that they are fetched as aligned 16-byte vectors; column CO of a staged
+// row is the first one the filters read.
+template <int TC, int NT, int APT_, int BPT_, bool V4 = false>
 struct SyLanes {
   static constexpr int W = TC + kSHal;
+  static constexpr int WC = V4 ? W + 1 : W;
+  static constexpr int CO = V4 ? 1 : 0;
+  static constexpr int QS = W * WC;  // values of one staged quadrant
   // row pitch of rbuf: odd, so the row pass's reads (8 rows x 8 lanes per
   // wave, 4 values apart within a row) spread over all banks
   static constexpr int RP = 2 * W + 1;
@@ -531,8 +538,8 @@ struct SyLanes {
     const int col = t % (2 * W), a0 = (t / (2 * W)) * APT;
     const int hf = col >= W;
     const int cc = hf ? col - W : col;
-    ql = (hf ? 2 : 0) * W * W + a0 * W + cc;
-    qh = ql + W * W;
+    ql = (hf ? 2 : 0) * QS + a0 * WC + cc + CO;
+    qh = ql + QS;
     rout = (2 * a0) * RP + col;
     const int ri = t / (TC / BPT), b0 = (t % (TC / BPT)) * BPT;
     rc = ri * RP + b0;
@@ -559,7 +566,7 @@ __device__ __forceinline__ void sy_cols(const T* q, T* rbuf, const Lanes& ln) {
     ge[e] = filt_g<T>(PB - 1, 2 * e);
     go[e] = filt_g<T>(PB - 1, 2 * e + 1);
   }
-  // q layout: [quad][W][W], quad 0 = low rows / c cols, 1 = high rows / c cols,
+  // q layout: [quad][W][WC], quad 0 = low rows / c cols, 1 = high rows / c cols,
   // 2 = low rows / d cols, 3 = high rows / d cols
   if (ln.col_on) {
     const T* ql = q + ln.ql;
@@ -567,8 +574,8 @@ __device__ __forceinline__ void sy_cols(const T* q, T* rbuf, const Lanes& ln) {
     T wl[NW], wh[NW];
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
-      wl[i] = ql[(R0 + i) * W];
-      wh[i] = qh[(R0 + i) * W];
+      wl[i] = ql[(R0 + i) * Lanes::WC];
+      wh[i] = qh[(R0 + i) * Lanes::WC];
     }
     T* out = rbuf + ln.rout;
 #pragma unroll
@@ -656,9 +663,15 @@ __device__ __forceinline__ void store_row(T* dst, const T (&acc)[BPT][2], T sc, 
 // PN: number of bases when known at compile time, or 0 (see dwt_an).
 template <typename T, int TC, int NT, int APT, int BPT, bool DEEP, int PN>
 __device__ __forceinline__ void sy_block(const SyArgs<T>& a, int lb, T* s_q, T* s_r) {
-  using Lanes = SyLanes<TC, NT, APT, BPT>;
+  // level 1 in FP32 stages its tile as 16-byte vectors (see SyLanes)
+  constexpr bool V4 = sizeof(T) == 4 && !DEEP;
+  using Lanes = SyLanes<TC, NT, APT, BPT, V4>;
+  using E = typename std::conditional<V4, muffin_f32x4, T>::type;  // staged element
+  constexpr int VW = V4 ? 4 : 1;                  // values per element
   constexpr int W = TC + kSHal;
-  constexpr int NQ = (4 * W * W + NT - 1) / NT;  // tile values per thread
+  constexpr int RE = Lanes::WC / VW;              // elements per staged row
+  constexpr int QE = W * RE;                      // elements per quadrant
+  constexpr int NQ = (4 * QE + NT - 1) / NT;      // elements per thread
   const int tiles2 = a.tiles * a.tiles;
   // (block-uniform; kept in scalar registers so plane addressing stays scalar)
   const int band = __builtin_amdgcn_readfirstlane(lb / tiles2);
@@ -691,18 +704,22 @@ __device__ __forceinline__ void sy_block(const SyArgs<T>& a, int lb, T* s_q, T* 
   // output (offset in a half x half plane, flagged by a negative value) when
   // there is one, the other quadrants read U.
   // Byte offsets of this thread's tile values inside their source plane
-  // (periodic wrap; also valid for the idle tail t >= 4 W^2).  Values of the
-  // low-low quadrant (t < W^2) come from the coarser level's output when
-  // there is one, the others from U.
-  constexpr int Q0 = W * W;
+  // (periodic wrap; the idle tail t >= 4 QE reads nothing in the vector
+  // form, a valid value otherwise).  Values of the low-low quadrant (t < QE)
+  // come from the coarser level's output when there is one, the others from
+  // U.  A vector never straddles the wrap (both are multiples of four).
+  constexpr int Q0 = QE;
+  constexpr uint32_t kNone = 0x7ffffff0u;  // past every plane: reads 0, no traffic
   uint32_t off[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const int t = threadIdx.x + i * NT;
-    const int quad = t / (W * W), rem = t - quad * W * W;
-    const int r = rem / W, c = rem - r * W;
-    const int kr = (kr0 - kSHal + r) & hm, kc = (kc0 - kSHal + c) & hm;
-    if (quad == 0 && has_ll) {
+    const int quad = t / QE, rem = t - quad * QE;
+    const int r = rem / RE, c = (rem - r * RE) * VW;
+    const int kr = (kr0 - kSHal + r) & hm, kc = (kc0 - kSHal - Lanes::CO + c) & hm;
+    if (V4 && t >= 4 * QE) {
+      off[i] = kNone;
+    } else if (quad == 0 && has_ll) {
       off[i] = (uint32_t)((kr * half + kc) * (int)sizeof(T));
     } else {
       const int roff = (quad & 1) ? half : 0, coff = (quad & 2) ? half : 0;
@@ -715,7 +732,13 @@ __device__ __forceinline__ void sy_block(const SyArgs<T>& a, int lb, T* s_q, T* 
   // planes, then selected).  The loads are unconditional (no branch between
   // a load and its use), so all of them stay in flight while the previous
   // basis is filtered.
-  T ra[NQ];
+  E ra[NQ];
+  auto ld = [&](__amdgpu_buffer_rsrc_t r, uint32_t o) -> E {
+    if constexpr (V4)
+      return __builtin_bit_cast(muffin_f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0));
+    else
+      return buf_ld<T>(r, o);
+  };
   auto fetch = [&](int pidx) {
     const auto ru = plane_rsrc(a.Ua[set] + ((size_t)band * a.P + pidx) * plane, plane);
     const auto rl = has_ll ? plane_rsrc(a.llin[set] + ((size_t)band * a.P + pidx) *
@@ -724,13 +747,13 @@ __device__ __forceinline__ void sy_block(const SyArgs<T>& a, int lb, T* s_q, T* 
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
       if ((i + 1) * NT <= Q0) {
-        ra[i] = buf_ld<T>(rl, off[i]);
+        ra[i] = ld(rl, off[i]);
       } else if (i * NT >= Q0) {
-        ra[i] = buf_ld<T>(ru, off[i]);
+        ra[i] = ld(ru, off[i]);
       } else {
         const bool q0 = has_ll && (int)threadIdx.x + i * NT < Q0;
-        const T vl = buf_ld<T>(rl, q0 ? off[i] : 0u);
-        const T vu = buf_ld<T>(ru, off[i]);
+        const E vl = ld(rl, q0 ? off[i] : (V4 ? kNone : 0u));
+        const E vu = ld(ru, V4 && q0 ? kNone : off[i]);
         ra[i] = q0 ? vl : vu;
       }
     }
@@ -739,7 +762,7 @@ __device__ __forceinline__ void sy_block(const SyArgs<T>& a, int lb, T* s_q, T* 
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
       const int t = threadIdx.x + i * NT;
-      if (t < 4 * W * W) s_q[t] = ra[i];
+      if (t < 4 * QE) reinterpret_cast<E*>(s_q)[t] = ra[i];
     }
   };
   const Lanes lanes;
@@ -781,7 +804,7 @@ __device__ __forceinline__ void sy_block(const SyArgs<T>& a, int lb, T* s_q, T* 
 template <typename T, int TC, int NT, int APT, int BPT, bool DEEP, int PN>
 __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_sy(SyArgs<T> a) {
   constexpr int W = TC + kSHal;
-  __shared__ T s_q[4 * W * W];
+  __shared__ __align__(16) T s_q[4 * SyLanes<TC, NT, APT, BPT, sizeof(T) == 4 && !DEEP>::QS];
   __shared__ T s_r[2 * TC * (2 * W + 1)];
   const int lb = xcd_remap_d(blockIdx.x, a.nblocks);
   if (lb >= a.nblocks) return;
