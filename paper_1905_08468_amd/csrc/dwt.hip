@@ -661,10 +661,11 @@ __device__ __forceinline__ void store_row(T* dst, const T (&acc)[BPT][2], T sc, 
 // DEEP = false: level 1 (the bases' syntheses summed into S); true: the
 // coarser levels (one output per basis).
 // PN: number of bases when known at compile time, or 0 (see dwt_an).
-template <typename T, int TC, int NT, int APT, int BPT, bool DEEP, int PN>
+// V4 (FP32, half-plane side a multiple of four): the tile is staged as
+// 16-byte vectors (see SyLanes).
+template <typename T, int TC, int NT, int APT, int BPT, bool DEEP, int PN, bool V4>
 __device__ __forceinline__ void sy_block(const SyArgs<T>& a, int lb, T* s_q, T* s_r) {
-  // level 1 in FP32 stages its tile as 16-byte vectors (see SyLanes)
-  constexpr bool V4 = sizeof(T) == 4 && !DEEP;
+  static_assert(!V4 || sizeof(T) == 4, "vector staging of FP32 tiles");
   using Lanes = SyLanes<TC, NT, APT, BPT, V4>;
   using E = typename std::conditional<V4, muffin_f32x4, T>::type;  // staged element
   constexpr int VW = V4 ? 4 : 1;                  // values per element
@@ -801,14 +802,14 @@ __device__ __forceinline__ void sy_block(const SyArgs<T>& a, int lb, T* s_q, T* 
 }
 
 // TC x TC coefficient tiles of every quadrant per block (2 TC x 2 TC outputs).
-template <typename T, int TC, int NT, int APT, int BPT, bool DEEP, int PN>
+template <typename T, int TC, int NT, int APT, int BPT, bool DEEP, int PN, bool V4>
 __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_sy(SyArgs<T> a) {
   constexpr int W = TC + kSHal;
-  __shared__ __align__(16) T s_q[4 * SyLanes<TC, NT, APT, BPT, sizeof(T) == 4 && !DEEP>::QS];
+  __shared__ __align__(16) T s_q[4 * SyLanes<TC, NT, APT, BPT, V4>::QS];
   __shared__ T s_r[2 * TC * (2 * W + 1)];
   const int lb = xcd_remap_d(blockIdx.x, a.nblocks);
   if (lb >= a.nblocks) return;
-  sy_block<T, TC, NT, APT, BPT, DEEP, PN>(a, lb, s_q, s_r);
+  sy_block<T, TC, NT, APT, BPT, DEEP, PN, V4>(a, lb, s_q, s_r);
 }
 
 // ---------------------------------------------------------------------------
@@ -937,12 +938,17 @@ int dwt_synthesis(const DwtPlan<T>& p, const SynthesisIO<T>& io, const DevParams
     dim3 grid(xcd_grid_h(a.nblocks), io.nsets);
     // (the basis count stays a run-time value here: compiled for P = 8 the
     // fully unrolled kernel needs 137 VGPRs and runs at half the occupancy)
+    // FP32 tiles are staged as aligned 16-byte vectors when the half-plane
+    // side is a multiple of four (no vector then straddles the wrap)
+    const bool v4 = big && half % 4 == 0;
     if (wide) {
-      if constexpr (big) dwt_sy<T, kSyTC1, kSyNT1, 8, 4, false, 0><<<grid, kSyNT1, 0, s>>>(a);
+      if constexpr (big) dwt_sy<T, kSyTC1, kSyNT1, 8, 4, false, 0, true><<<grid, kSyNT1, 0, s>>>(a);
     } else if (lev == 1) {
-      dwt_sy<T, kTO, kNT, 4, 2, false, 0><<<grid, kNT, 0, s>>>(a);
+      if (v4) dwt_sy<T, kTO, kNT, 4, 2, false, 0, big><<<grid, kNT, 0, s>>>(a);
+      else dwt_sy<T, kTO, kNT, 4, 2, false, 0, false><<<grid, kNT, 0, s>>>(a);
     } else {
-      dwt_sy<T, kTO, kNT, 4, 2, true, 0><<<grid, kNT, 0, s>>>(a);
+      if (v4) dwt_sy<T, kTO, kNT, 4, 2, true, 0, big><<<grid, kNT, 0, s>>>(a);
+      else dwt_sy<T, kTO, kNT, 4, 2, true, 0, false><<<grid, kNT, 0, s>>>(a);
     }
     MUFFIN_HIP_CHECK(hipGetLastError());
   }
