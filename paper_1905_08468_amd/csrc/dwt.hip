@@ -357,11 +357,17 @@ __device__ __forceinline__ void an_cols(const AnArgs<T>& a, const T* rowbuf, con
 // PN: number of bases when known at compile time (8, the paper's union of
 // db1..db8), or 0 to take it from the arguments; with it known, every basis
 // step and every prefetch is unconditional.
-template <typename T, int TO, int NT, bool DEEP, int PN>
+// V4 (FP32, input plane side a multiple of four): the input tile is fetched
+// as aligned 16-byte vectors (a row of IN values as ceil(IN / 4) of them; the
+// values past IN are dropped) and staged as 8-byte pairs, keeping the pitch
+// IN of the row filter's reads.
+template <typename T, int TO, int NT, bool DEEP, int PN, bool V4>
 __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_an(AnArgs<T> a) {
   static_assert((TO / 2) * (2 * TO) == NT, "one thread per column-filter output quad");
+  static_assert(!V4 || sizeof(T) == 4, "vector staging of FP32 tiles");
   constexpr int IN = 2 * TO + kHalo;
-  __shared__ T s_in[IN * IN];
+  static_assert(IN % 2 == 0, "8-byte aligned pairs in the staged rows");
+  __shared__ __align__(16) T s_in[IN * IN];
   __shared__ T s_row[IN * an_pitch<TO>()];
   const int lb = xcd_remap_d(blockIdx.x, a.nblocks);
   if (lb >= a.nblocks) return;
@@ -409,22 +415,50 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_an(AnArgs<T> a) {
   };
   fetch_um(0, u[0]);
   // ---- this thread's tile offsets (bytes) in a plane of side Ms ----
-  // (wrapped into the plane, so every offset is valid, also for t >= IN^2)
-  constexpr int NI = (IN * IN + NT - 1) / NT;
+  // (wrapped into the plane, so every offset is valid, also for t >= IN^2;
+  // in the vector form the idle tail reads nothing)
+  using E = typename std::conditional<V4, muffin_f32x4, T>::type;  // fetched element
+  constexpr int VW = V4 ? 4 : 1;               // values per element
+  constexpr int RE = (IN + VW - 1) / VW;       // elements per tile row
+  constexpr int NI = (IN * RE + NT - 1) / NT;  // elements per thread
+  constexpr uint32_t kNone = 0x7ffffff0u;      // past every plane: reads 0, no traffic
   uint32_t ioff[NI];
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
     const int t = threadIdx.x + i * NT;
-    const int r = t / IN, c = t - r * IN;
-    ioff[i] = (uint32_t)((((2 * kr0 + r) & msk) * Ms + ((2 * kc0 + c) & msk)) * (int)sizeof(T));
+    const int r = t / RE, c = (t - r * RE) * VW;
+    ioff[i] = V4 && t >= IN * RE
+                  ? kNone
+                  : (uint32_t)((((2 * kr0 + r) & msk) * Ms + ((2 * kc0 + c) & msk)) *
+                               (int)sizeof(T));
   }
-  T nxt[NI];
+  auto ld = [&](__amdgpu_buffer_rsrc_t r, uint32_t o, uint32_t so) -> E {
+    if constexpr (V4)
+      return __builtin_bit_cast(muffin_f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, o, so, 0));
+    else
+      return buf_ld<T>(r, o, so);
+  };
+  // element i of this thread into the staged tile
+  auto stage = [&](int i, const E& v) {
+    const int t = threadIdx.x + i * NT;
+    if constexpr (V4) {
+      const int r = t / RE, c = (t - r * RE) * VW;
+      if (t < IN * RE) {
+        T* d = s_in + r * IN + c;
+        *reinterpret_cast<float2*>(d) = make_float2(v.x, v.y);
+        if (c + 2 < IN) *reinterpret_cast<float2*>(d + 2) = make_float2(v.z, v.w);
+      }
+    } else {
+      if (t < IN * IN) s_in[t] = v;
+    }
+  };
+  E nxt[NI];
   const size_t mpl = (size_t)Ms * Ms;
   const auto rI = plane_rsrc(DEEP ? a.llin[set] + bpl * mpl : a.U[set], DEEP ? a.P * mpl : plane);
   auto fetch_ll = [&](int pidx) {
     const uint32_t sp = (uint32_t)(pidx * mpl * sizeof(T));
 #pragma unroll
-    for (int i = 0; i < NI; ++i) nxt[i] = buf_ld<T>(rI, ioff[i], sp);
+    for (int i = 0; i < NI; ++i) nxt[i] = ld(rI, ioff[i], sp);
   };
   // ---- stage the input tile (periodic wrap) ----
   if constexpr (!DEEP) {
@@ -434,27 +468,23 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_an(AnArgs<T> a) {
     const auto rza = plane_rsrc(a.z_a[set] + (size_t)band * plane, plane);
     const bool has_b = a.z_b[set] != nullptr;
     const auto rzb = plane_rsrc((has_b ? a.z_b[set] : a.z_a[set]) + (size_t)band * plane, plane);
-    T va[NI], vb[NI];
+    E va[NI], vb[NI];
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-      va[i] = buf_ld<T>(rza, ioff[i]);
-      if (has_b) vb[i] = buf_ld<T>(rzb, ioff[i]);
+      va[i] = ld(rza, ioff[i], 0u);
+      if (has_b) vb[i] = ld(rzb, ioff[i], 0u);
     }
     const T tc1 = T(c1), tc2 = T(c2);
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-      const int t = threadIdx.x + i * NT;
-      T z = tc1 * va[i];
+      E z = tc1 * va[i];
       if (has_b) z += tc2 * vb[i];
-      if (t < IN * IN) s_in[t] = z;
+      stage(i, z);
     }
   } else {
     fetch_ll(0);
 #pragma unroll
-    for (int i = 0; i < NI; ++i) {
-      const int t = threadIdx.x + i * NT;
-      if (t < IN * IN) s_in[t] = nxt[i];
-    }
+    for (int i = 0; i < NI; ++i) stage(i, nxt[i]);
   }
   lds_barrier();
   const double beta = a.beta ? a.beta[band] : 1.0;
@@ -474,10 +504,7 @@ __global__ void __launch_bounds__(NT, kDwtMinWaves) dwt_an(AnArgs<T> a) {
     lds_barrier();                                                            \
     cols(std::integral_constant<int, PB>{}, u[(PB - 1) & 1]);                   \
     if (more) {                                                                 \
-      _Pragma("unroll") for (int i = 0; i < NI; ++i) {                          \
-        const int t = threadIdx.x + i * NT;                                     \
-        if (t < IN * IN) s_in[t] = nxt[i];                                      \
-      }                                                                         \
+      _Pragma("unroll") for (int i = 0; i < NI; ++i) stage(i, nxt[i]);          \
     }                                                                           \
     lds_barrier();                                                            \
   }
@@ -881,23 +908,32 @@ int dwt_analysis(const DwtPlan<T>& p, const AnalysisIO<T>& io, const DevParams* 
     a.pure = io.pure;
     a.pure_scale = io.pure_scale;
     dim3 grid(xcd_grid_h(a.nblocks), io.nsets);
+    // FP32 input tiles are fetched as aligned 16-byte vectors when the
+    // input plane's side is a multiple of four (no vector straddles the wrap)
+    const bool v4 = big && a.Ms % 4 == 0;
     if (wide) {
       if constexpr (big) {
         if (lev == 1)
-          dwt_an<T, kAnTO1, kAnNT1, false, 8><<<grid, kAnNT1, 0, s>>>(a);
+          dwt_an<T, kAnTO1, kAnNT1, false, 8, true><<<grid, kAnNT1, 0, s>>>(a);
         else
-          dwt_an<T, kAnTO1, kAnNT1, true, 8><<<grid, kAnNT1, 0, s>>>(a);
+          dwt_an<T, kAnTO1, kAnNT1, true, 8, true><<<grid, kAnNT1, 0, s>>>(a);
       }
     } else if (p.P == 8) {
-      if (lev == 1)
-        dwt_an<T, kTO, kNT, false, 8><<<grid, kNT, 0, s>>>(a);
-      else
-        dwt_an<T, kTO, kNT, true, 8><<<grid, kNT, 0, s>>>(a);
+      if (lev == 1) {
+        if (v4) dwt_an<T, kTO, kNT, false, 8, big><<<grid, kNT, 0, s>>>(a);
+        else dwt_an<T, kTO, kNT, false, 8, false><<<grid, kNT, 0, s>>>(a);
+      } else {
+        if (v4) dwt_an<T, kTO, kNT, true, 8, big><<<grid, kNT, 0, s>>>(a);
+        else dwt_an<T, kTO, kNT, true, 8, false><<<grid, kNT, 0, s>>>(a);
+      }
     } else {
-      if (lev == 1)
-        dwt_an<T, kTO, kNT, false, 0><<<grid, kNT, 0, s>>>(a);
-      else
-        dwt_an<T, kTO, kNT, true, 0><<<grid, kNT, 0, s>>>(a);
+      if (lev == 1) {
+        if (v4) dwt_an<T, kTO, kNT, false, 0, big><<<grid, kNT, 0, s>>>(a);
+        else dwt_an<T, kTO, kNT, false, 0, false><<<grid, kNT, 0, s>>>(a);
+      } else {
+        if (v4) dwt_an<T, kTO, kNT, true, 0, big><<<grid, kNT, 0, s>>>(a);
+        else dwt_an<T, kTO, kNT, true, 0, false><<<grid, kNT, 0, s>>>(a);
+      }
     }
     MUFFIN_HIP_CHECK(hipGetLastError());
   }
