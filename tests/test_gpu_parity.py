@@ -94,6 +94,25 @@ def test_wavelet_ops_f64(n, L, P, J):
     h.close()
 
 
+# FP32: the tile staging by 16-byte vectors (every level whose half-plane
+# side is a multiple of four) and its scalar fallback (the coarsest levels of
+# n = 8 and 16), the 16- and 32-wide tiles (half-plane side >= 64), P < 8
+@pytest.mark.parametrize("n,L,P,J", [(8, 2, 8, 3), (16, 3, 8, 4), (64, 2, 8, 3), (64, 1, 3, 2),
+                                     (128, 2, 8, 4), (256, 1, 8, 3), (256, 1, 5, 2)])
+def test_wavelet_ops_f32(n, L, P, J):
+    mm = _mm()
+    torch = _torch()
+    rng = np.random.default_rng(11 * n + P)
+    x = rng.standard_normal((L, n, n)).astype(np.float32)
+    u = rng.standard_normal((L, P, n, n)).astype(np.float32)
+    W = op.SpatialDictionary(P, J)
+    cfg = mm.default_config(n, L, mode=mm.F32, n_bases=P, levels=J)
+    h = mm.Muffin(cfg)
+    assert rel(host(h.op("Ws", dev(x, torch.float32))), W.forward(x.astype(np.float64))) < 1e-5
+    assert rel(host(h.op("WsT", dev(u, torch.float32))), W.adjoint(u.astype(np.float64))) < 1e-5
+    h.close()
+
+
 @pytest.mark.parametrize("L", [1, 5, 16, 33, 64, 256])
 def test_dct_ops_f64(L):
     mm = _mm()
