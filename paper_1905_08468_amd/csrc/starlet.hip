@@ -63,13 +63,52 @@ struct StArgs {
   int tiles, nblocks;
 };
 
+// Staged tile of a scale with halo R: W = TS + 2 R rows of WC values, the
+// output tile's column c at c + CR.  FP32 rows start at a multiple of four
+// (halo rounded up to RA >= 4) and are fetched as 16-byte vectors; FP64 rows
+// are the W values themselves.
+template <typename T>
+struct StGeom {
+  static constexpr bool V4 = sizeof(T) == 4;
+  int R, W, RA, WC, CR;
+  __device__ __host__ explicit StGeom(int level) {
+    R = 2 << (level - 1);
+    W = kStTS + 2 * R;
+    RA = V4 ? (R < 4 ? 4 : R) : R;
+    WC = kStTS + 2 * RA;
+    CR = RA;
+  }
+};
+
+// fetch the staged tile of one plane (periodic wrap; n % 4 == 0) through f,
+// which maps a value of the plane at element g (or a vector at g) to the
+// value to stage
+template <typename T, typename F>
+__device__ __forceinline__ void st_stage(T* s_in, const StGeom<T>& sg, int i0, int j0, int n,
+                                         F f) {
+  const int msk = n - 1;
+  if constexpr (StGeom<T>::V4) {
+    const int RE = sg.WC / 4;
+    for (int t = threadIdx.x; t < sg.W * RE; t += kStNT) {
+      const int r = t / RE, c = (t - r * RE) * 4;
+      const size_t g = (size_t)((i0 - sg.R + r) & msk) * n + ((j0 - sg.RA + c) & msk);
+      *reinterpret_cast<float4*>(s_in + r * sg.WC + c) = f(g, float4{});
+    }
+  } else {
+    for (int t = threadIdx.x; t < sg.W * sg.WC; t += kStNT) {
+      const int r = t / sg.WC, c = t - r * sg.WC;
+      s_in[t] = f((size_t)((i0 - sg.R + r) & msk) * n + ((j0 - sg.R + c) & msk), T{});
+    }
+  }
+}
+
 // separable smoothing of the staged tile: rows of s_in into s_row, then the
 // column at (r, c) of the output tile
 template <typename T>
-__device__ __forceinline__ void st_rows(const T* s_in, T* s_row, int W, int R, int d) {
-  for (int t = threadIdx.x; t < W * kStTS; t += kStNT) {
+__device__ __forceinline__ void st_rows(const T* s_in, T* s_row, const StGeom<T>& sg, int d) {
+  for (int t = threadIdx.x; t < sg.W * kStTS; t += kStNT) {
     const int r = t / kStTS, c = t - r * kStTS;
-    const T* p = s_in + r * W + c + R;
+    const T* p = s_in + r * sg.WC + c + sg.CR;
     T acc = T(0);
 #pragma unroll
     for (int m = 0; m < 5; ++m) acc = fma(b3<T>(m), p[(m - 2) * d], acc);
@@ -103,14 +142,15 @@ template <typename T>
 __global__ void __launch_bounds__(kStNT) st_an(StArgs<T> a) {
   extern __shared__ __align__(16) unsigned char st_smem[];
   T* s_in = reinterpret_cast<T*>(st_smem);
-  const int d = 1 << (a.level - 1), R = 2 * d, W = kStTS + 2 * R;
-  T* s_row = s_in + W * W;
+  const int d = 1 << (a.level - 1), R = 2 * d;
+  const StGeom<T> sg(a.level);
+  T* s_row = s_in + sg.W * sg.WC;
   const int lb = st_remap(blockIdx.x, a.nblocks);
   if (lb >= a.nblocks) return;
   const int tiles2 = a.tiles * a.tiles;
   const int band = lb / tiles2, tile = lb - band * tiles2;
   const int i0 = (tile / a.tiles) * kStTS, j0 = (tile % a.tiles) * kStTS;
-  const int set = blockIdx.y, n = a.n, msk = n - 1;
+  const int set = blockIdx.y, n = a.n;
   const size_t N = (size_t)n * n;
   const size_t boff = (size_t)band * N;
   // dual values (and masks) of this thread's outputs, fetched before the
@@ -146,22 +186,24 @@ __global__ void __launch_bounds__(kStNT) st_an(StArgs<T> a) {
     const T* za = a.z_a[set] + boff;
     const bool has_b = a.z_b[set] != nullptr;
     const T* zb = has_b ? a.z_b[set] + boff : za;
-    for (int t = threadIdx.x; t < W * W; t += kStNT) {
-      const int r = t / W, c = t - r * W;
-      const size_t g = (size_t)((i0 - R + r) & msk) * n + ((j0 - R + c) & msk);
-      T z = T(c1) * za[g];
-      if (has_b) z += T(c2) * zb[g];
-      s_in[t] = z;
-    }
+    const T tc1 = T(c1), tc2 = T(c2);
+    st_stage(s_in, sg, i0, j0, n, [&](size_t g, auto v) {
+      using V = decltype(v);
+      V z = *reinterpret_cast<const V*>(za + g);
+      z = z * tc1;
+      if (has_b) {
+        const V b = *reinterpret_cast<const V*>(zb + g);
+        z = z + b * tc2;
+      }
+      return z;
+    });
   } else {
     const T* src = a.in[set] + ((size_t)band * a.in_planes + a.in_plane) * N;
-    for (int t = threadIdx.x; t < W * W; t += kStNT) {
-      const int r = t / W, c = t - r * W;
-      s_in[t] = src[(size_t)((i0 - R + r) & msk) * n + ((j0 - R + c) & msk)];
-    }
+    st_stage(s_in, sg, i0, j0, n,
+             [&](size_t g, auto v) { return *reinterpret_cast<const decltype(v)*>(src + g); });
   }
   lds_barrier();
-  st_rows(s_in, s_row, W, R, d);
+  st_rows(s_in, s_row, sg, d);
   lds_barrier();
   const double beta = a.beta ? a.beta[band] : 1.0;
   const T scale = T(a.dp ? a.dp->sigma * beta : 0.0);
@@ -184,7 +226,7 @@ __global__ void __launch_bounds__(kStNT) st_an(StArgs<T> a) {
     const int r = t / kStTS, c = t - r * kStTS;
     if (i0 + r >= n || j0 + c >= n) continue;
     const T cj = st_col(s_row, r, c, R, d);
-    const T z0 = s_in[(r + R) * W + c + R];
+    const T z0 = s_in[(r + R) * sg.WC + c + sg.CR];
     const size_t pix = opix[k];
     update(pw + pix, z0 - cj, uw[k], mw[k]);  // w_j
     if (last)
@@ -199,14 +241,15 @@ template <typename T>
 __global__ void __launch_bounds__(kStNT) st_sy(StArgs<T> a) {
   extern __shared__ __align__(16) unsigned char st_smem[];
   T* s_in = reinterpret_cast<T*>(st_smem);
-  const int d = 1 << (a.level - 1), R = 2 * d, W = kStTS + 2 * R;
-  T* s_row = s_in + W * W;
+  const int d = 1 << (a.level - 1), R = 2 * d;
+  const StGeom<T> sg(a.level);
+  T* s_row = s_in + sg.W * sg.WC;
   const int lb = st_remap(blockIdx.x, a.nblocks);
   if (lb >= a.nblocks) return;
   const int tiles2 = a.tiles * a.tiles;
   const int band = lb / tiles2, tile = lb - band * tiles2;
   const int i0 = (tile / a.tiles) * kStTS, j0 = (tile % a.tiles) * kStTS;
-  const int set = blockIdx.y, n = a.n, msk = n - 1;
+  const int set = blockIdx.y, n = a.n;
   const size_t N = (size_t)n * n;
   const T* rin = a.in[set] + ((size_t)band * a.in_planes + a.in_plane) * N;
   const T* u = a.U[set] + ((size_t)band * a.planes + (a.level - 1)) * N;
@@ -218,13 +261,12 @@ __global__ void __launch_bounds__(kStNT) st_sy(StArgs<T> a) {
     const int r = t / kStTS, c = t - r * kStTS;
     uo[k] = u[(size_t)min(i0 + r, n - 1) * n + min(j0 + c, n - 1)];
   }
-  for (int t = threadIdx.x; t < W * W; t += kStNT) {
-    const int r = t / W, c = t - r * W;
-    const size_t g = (size_t)((i0 - R + r) & msk) * n + ((j0 - R + c) & msk);
-    s_in[t] = rin[g] - u[g];
-  }
+  st_stage(s_in, sg, i0, j0, n, [&](size_t g, auto v) {
+    using V = decltype(v);
+    return *reinterpret_cast<const V*>(rin + g) - *reinterpret_cast<const V*>(u + g);
+  });
   lds_barrier();
-  st_rows(s_in, s_row, W, R, d);
+  st_rows(s_in, s_row, sg, d);
   lds_barrier();
   const T sc = T(a.level == 1 && a.beta ? a.beta[band] : 1.0);
   T* out = a.out[set] + (size_t)band * N;
@@ -240,8 +282,8 @@ __global__ void __launch_bounds__(kStNT) st_sy(StArgs<T> a) {
 
 template <typename T>
 size_t st_lds_bytes(int level) {
-  const int R = 2 << (level - 1), W = kStTS + 2 * R;
-  return sizeof(T) * ((size_t)W * W + (size_t)W * kStTS);
+  const StGeom<T> sg(level);
+  return sizeof(T) * ((size_t)sg.W * sg.WC + (size_t)sg.W * kStTS);
 }
 
 template <typename T>
