@@ -384,3 +384,163 @@ def test_adapt_loop_updates_theta_and_is_deterministic():
     assert h0["mu"] == max(0.5 - 1e-3 * h0["sugar_mu"], 0.0)
     assert h0["gamma"] == max(0.4 - 1e-3 * h0["sugar_gamma"], 0.0)
     assert r1.X.min() >= 0
+
+
+# ------------------------------------------------ the ADA-PT driver itself --
+# Algorithm 5 and eq. `adaptgrad`: the driver's SUGAR values must be the
+# derivatives of the PSURE it logs, taken over the iterations its reading of
+# the derivative state says they cover, and each theta update (with the step
+# size refreshed after it) must feed the next window.  The references below
+# use only run_muffin / muffin_step and psure(), never the derivative
+# recursions or the driver.
+
+def _driver_problem(seed=14):
+    pb, _, prob = _fd_problem(seed)
+    n = pb.Y.shape[1]
+    beta_H = mf.lipschitz(pb.K, n, iters=300, tol=1e-12)
+    eps = 0.05 * prob.sigma_w
+    return pb, prob, beta_H, eps
+
+
+def _psure_after(pb, prob, eps, steps, mu, gamma, tau, start=None):
+    """PSURE of both trajectories after `steps` iterations of Alg. 2 at fixed
+    (mu, gamma, tau), from zero or from the pair of states `start`."""
+    L, n, _ = pb.Y.shape
+    Ybar = pb.Y + eps * prob.delta
+    zero = mf.State.zeros(L, n, pb.Ws.P)
+    s0, sb0 = (zero, zero) if start is None else start
+    S = _window(pb, pb.Y, s0, mu, gamma, tau, steps)
+    Sb = _window(pb, Ybar, sb0, mu, gamma, tau, steps)
+    return mf.psure(pb.Y, S.X, Sb.X, pb.K, prob.delta, prob.sigma_w, eps), S, Sb
+
+
+def _fd_sugar(pb, prob, eps, steps, mu, gamma, tau, start=None, h=1e-6):
+    f = lambda m, g: _psure_after(pb, prob, eps, steps, m, g, tau, start)[0]
+    return ((f(mu + h, gamma) - f(mu - h, gamma)) / (2 * h),
+            (f(mu, gamma + h) - f(mu, gamma - h)) / (2 * h))
+
+
+def _close(a, b, scale, tol=1e-4):
+    return abs(a - b) <= tol * scale
+
+
+def test_adapt_driver_one_window_sugar_is_fd_of_psure():
+    # eta = 0, a single window of Delta = iters: the logged SUGAR values are
+    # the derivatives in mu and gamma of the logged PSURE over the whole run
+    pb, prob, beta_H, eps = _driver_problem()
+    mu, gamma, Delta = 0.5, 0.4, 6
+    tau = mf.tau_rule(beta_H, pb.sigma, pb.mu_l(mu), pb.gamma_n(gamma).ravel())
+    res = mf.run_adapt(pb, mu, gamma, Delta, prob.delta, eps, prob.sigma_w, Delta=Delta,
+                       eta_mu=0.0, eta_gamma=0.0, tau=tau, deriv_reset=True)
+    assert len(res.history) == 1
+    h0 = res.history[0]
+    ps, S, Sb = _psure_after(pb, prob, eps, Delta, mu, gamma, tau)
+    assert abs(h0["psure"] - ps) <= 1e-12 * abs(ps)
+    assert np.array_equal(res.X, S.X) and np.array_equal(res.Xbar, Sb.X)
+    fd_mu, fd_ga = _fd_sugar(pb, prob, eps, Delta, mu, gamma, tau)
+    scale = max(abs(fd_mu), abs(fd_ga), 1e-3 * abs(ps))
+    assert _close(h0["sugar_mu"], fd_mu, scale), (h0["sugar_mu"], fd_mu)
+    assert _close(h0["sugar_gamma"], fd_ga, scale), (h0["sugar_gamma"], fd_ga)
+    # the two derivatives are distinct quantities (a swapped pair would fail)
+    assert abs(fd_mu - fd_ga) > 10 * 1e-4 * scale
+
+
+@pytest.mark.parametrize("reset", [True, False])
+def test_adapt_driver_three_windows(reset):
+    # eta = 0, three windows.  deriv_reset: the SUGAR at k = 3 Delta is the
+    # derivative of PSURE over the last window, the Delta-step map from the
+    # states at k = 2 Delta (held fixed); without the reset it is the
+    # derivative over the whole 3 Delta-step map from zero.  Every logged
+    # PSURE is that of the iterates at its k.
+    pb, prob, beta_H, eps = _driver_problem(15)
+    mu, gamma, Delta = 0.6, 0.3, 3
+    tau = mf.tau_rule(beta_H, pb.sigma, pb.mu_l(mu), pb.gamma_n(gamma).ravel())
+    res = mf.run_adapt(pb, mu, gamma, 3 * Delta, prob.delta, eps, prob.sigma_w, Delta=Delta,
+                       eta_mu=0.0, eta_gamma=0.0, tau=tau, deriv_reset=reset)
+    assert [r["k"] for r in res.history] == [Delta, 2 * Delta, 3 * Delta]
+    for q, row in enumerate(res.history, start=1):
+        ps, _, _ = _psure_after(pb, prob, eps, q * Delta, mu, gamma, tau)
+        assert abs(row["psure"] - ps) <= 1e-12 * abs(ps), q
+        assert row["mu"] == mu and row["gamma"] == gamma and row["tau"] == tau
+    last = res.history[-1]
+    ps3, S3, Sb3 = _psure_after(pb, prob, eps, 3 * Delta, mu, gamma, tau)
+    assert np.array_equal(res.X, S3.X) and np.array_equal(res.Xbar, Sb3.X)
+    assert abs(last["psure"] - mf.psure(pb.Y, res.X, res.Xbar, pb.K, prob.delta,
+                                        prob.sigma_w, eps)) <= 1e-12 * abs(ps3)
+    if reset:
+        _, S2, Sb2 = _psure_after(pb, prob, eps, 2 * Delta, mu, gamma, tau)
+        fd_mu, fd_ga = _fd_sugar(pb, prob, eps, Delta, mu, gamma, tau, start=(S2, Sb2))
+    else:
+        fd_mu, fd_ga = _fd_sugar(pb, prob, eps, 3 * Delta, mu, gamma, tau)
+    scale = max(abs(fd_mu), abs(fd_ga), 1e-3 * abs(ps3))
+    assert _close(last["sugar_mu"], fd_mu, scale), (last["sugar_mu"], fd_mu)
+    assert _close(last["sugar_gamma"], fd_ga, scale), (last["sugar_gamma"], fd_ga)
+    # the two readings give different gradients on this problem, so each
+    # test can only pass with its own reading
+    if reset:
+        other = _fd_sugar(pb, prob, eps, 3 * Delta, mu, gamma, tau)
+    else:
+        _, S2, Sb2 = _psure_after(pb, prob, eps, 2 * Delta, mu, gamma, tau)
+        other = _fd_sugar(pb, prob, eps, Delta, mu, gamma, tau, start=(S2, Sb2))
+    assert abs(other[0] - fd_mu) > 10 * 1e-4 * scale or abs(other[1] - fd_ga) > 10 * 1e-4 * scale
+
+
+def test_adapt_driver_theta_step_and_tau_refresh_feed_the_next_window():
+    # eta > 0 with tau from the step rule: theta moves against the gradient
+    # of PSURE over the first window (eq. `adaptgrad`, clamped at 0), tau is
+    # recomputed from the new theta, and the second window runs both
+    # trajectories from the states at k = Delta with the new theta and tau.
+    pb, prob, beta_H, eps = _driver_problem(16)
+    mu0, ga0, Delta = 0.5, 0.4, 4
+    eta_mu, eta_ga = 2e-3, 1e-3
+    tau_of = lambda m, g: mf.tau_rule(beta_H, pb.sigma, pb.mu_l(m), pb.gamma_n(g).ravel())
+    res = mf.run_adapt(pb, mu0, ga0, 2 * Delta, prob.delta, eps, prob.sigma_w, Delta=Delta,
+                       eta_mu=eta_mu, eta_gamma=eta_ga, beta_H=beta_H, tau=None,
+                       deriv_reset=True)
+    tau0 = tau_of(mu0, ga0)
+    g_mu, g_ga = _fd_sugar(pb, prob, eps, Delta, mu0, ga0, tau0)
+    mu1 = max(mu0 - eta_mu * g_mu, 0.0)
+    ga1 = max(ga0 - eta_ga * g_ga, 0.0)
+    h0 = res.history[0]
+    # the step is a real move, larger than the finite-difference error
+    assert abs(mu1 - mu0) > 1e-3 * mu0 and abs(ga1 - ga0) > 1e-3 * ga0
+    assert abs(h0["mu"] - mu1) <= 1e-4 * eta_mu * max(abs(g_mu), 1.0)
+    assert abs(h0["gamma"] - ga1) <= 1e-4 * eta_ga * max(abs(g_ga), 1.0)
+    assert abs(h0["tau"] - tau_of(mu1, ga1)) <= 1e-6 * tau_of(mu1, ga1)
+    # second window from the first window's end states, with the driver's
+    # own theta_1 (so only its use is under test here)
+    _, S1, Sb1 = _psure_after(pb, prob, eps, Delta, mu0, ga0, tau0)
+    tau1 = tau_of(h0["mu"], h0["gamma"])
+    ps2, S2, Sb2 = _psure_after(pb, prob, eps, Delta, h0["mu"], h0["gamma"], tau1,
+                                start=(S1, Sb1))
+    np.testing.assert_allclose(res.X, S2.X, rtol=0, atol=1e-12 * np.abs(S2.X).max())
+    np.testing.assert_allclose(res.Xbar, Sb2.X, rtol=0, atol=1e-12 * np.abs(Sb2.X).max())
+    h1 = res.history[1]
+    assert abs(h1["psure"] - ps2) <= 1e-10 * abs(ps2)
+    fd_mu, fd_ga = _fd_sugar(pb, prob, eps, Delta, h0["mu"], h0["gamma"], tau1,
+                             start=(S1, Sb1))
+    scale = max(abs(fd_mu), abs(fd_ga), 1e-3 * abs(ps2))
+    assert _close(h1["sugar_mu"], fd_mu, scale) and _close(h1["sugar_gamma"], fd_ga, scale)
+    # a run that kept the first step size would end elsewhere
+    _, S2_stale, _ = _psure_after(pb, prob, eps, Delta, h0["mu"], h0["gamma"], tau0,
+                                  start=(S1, Sb1))
+    assert np.abs(S2_stale.X - res.X).max() > 1e-9 * np.abs(res.X).max()
+
+
+def test_adapt_driver_clamps_theta_at_zero():
+    # a step larger than theta ends at 0 (mu, gamma are non-negative,
+    # Section 2.1), and the run continues with that value
+    pb, prob, beta_H, eps = _driver_problem(17)
+    mu0, ga0, Delta = 0.5, 0.4, 3
+    tau = mf.tau_rule(beta_H, pb.sigma, pb.mu_l(1.0), pb.gamma_n(1.0).ravel())
+    g_mu, g_ga = _fd_sugar(pb, prob, eps, Delta, mu0, ga0, tau)
+    big_mu = 10 * mu0 / abs(g_mu)
+    big_ga = 10 * ga0 / abs(g_ga)
+    res = mf.run_adapt(pb, mu0, ga0, Delta, prob.delta, eps, prob.sigma_w, Delta=Delta,
+                       eta_mu=big_mu, eta_gamma=big_ga, tau=tau)
+    h0 = res.history[0]
+    exp_mu = max(mu0 - big_mu * g_mu, 0.0)
+    exp_ga = max(ga0 - big_ga * g_ga, 0.0)
+    assert (exp_mu == 0.0) == (h0["mu"] == 0.0) and (exp_ga == 0.0) == (h0["gamma"] == 0.0)
+    assert h0["mu"] >= 0.0 and h0["gamma"] >= 0.0
+    assert h0["mu"] == 0.0 or h0["gamma"] == 0.0
