@@ -138,7 +138,11 @@ typedef struct {
 int muffin_default_config(muffin_config* cfg, int32_t n, int32_t L);
 
 /* Device bytes the handle will hold for *cfg (admission control).  Returns 0
- * for an invalid configuration. */
+ * for an invalid configuration.  muffin_set_problem also takes temporary
+ * device memory for its power iteration, freed before it returns: two FP64
+ * cubes and two FP64 half spectra (about 6 L n^2 doubles), plus in the FP32
+ * forms an FP64 copy of the PSFs and of their transfer functions (about
+ * 8 L n^2 doubles more). */
 size_t muffin_workspace_bytes(const muffin_config* cfg);
 
 /* Creates a handle: validates *cfg (E_INVAL / E_SHAPE), allocates the
@@ -150,10 +154,12 @@ int muffin_create(muffin_handle** h, const muffin_config* cfg, void* stream);
  * transfer functions from the PSFs, weights, beta_H (power iteration, FP64),
  * tau, zero state.
  *   dirty: [L][n][n] device, psf: [L][2n][2n] device (working type).
- *   alpha: host double[n*n] or NULL -> 1/(||y^n|| + eps_w);
- *   beta:  host double[L]   or NULL -> 1/(||y_l|| + eps_w)
+ *   alpha: host double[n*n] or NULL -> 1/(||W_lambda y^n|| + eps_w);
+ *   beta:  host double[L]   or NULL -> 1/(||W_s y_l|| + eps_w)
  *          (the weight rule of Section 2.1 with the dirty cube as the
- *           initial estimate; ||W x|| = ||x|| for both dictionaries).
+ *           initial estimate).  The orthonormal DCT and the Daubechies
+ *           union (a Parseval frame) preserve norms, so those two are plain
+ *           norms of y; the starlet does not, and beta then applies it.
  *   delta: [L][n][n] device N(0,1) probe, required when cfg->sure.
  * Checks the cubes for NaN/Inf (E_NONFINITE).  Synchronises the stream. */
 int muffin_set_problem(muffin_handle* h, const void* dirty, const void* psf,

@@ -59,6 +59,7 @@ enum Slot {
 constexpr int kMaxSets = 6;
 constexpr int kMaxBases = 8;
 constexpr int kHistCols = 8;  // k, mu, gamma, tau, sugar_mu, sugar_gamma, psure, res2
+constexpr int kMaxHistRows = 4096;  // theta updates kept per handle
 
 // ---------------------------------------------------------------- FFT ----
 // FFT plan: side n (image n x n, FFT grid 2n x 2n).

@@ -221,7 +221,11 @@ size_t workspace_bytes_of(const muffin_config* c) {
                                                                 (int)P, (int)es));
   const size_t mv_bytes = std::max(LN, 4 * dct_mask_words((int)N));
   shared += c->sure ? 2 * (mu_bytes + mv_bytes) : 0;
-  shared += (N + L) * 8 + 4096 * 8 + 64 * 1024;                  // weights, partials, params
+  // weights; partial sums (as allocated by init); theta history; device
+  // parameters, flags and small sums
+  const size_t nparts = std::max({(size_t)fft_res_blocks((int)n, (int)L, (int)es),
+                                  (size_t)dot_blocks(), (size_t)(64 * L * 3), (size_t)4096});
+  shared += (N + L) * 8 + nparts * 8 + (size_t)kMaxHistRows * kHistCols * 8 + 64 * 1024;
   if (c->stop_rel > 0) shared += (P + 1) * LN * es;              // U, V snapshots (stop rule)
   return nsets * per_set + shared;
 }
@@ -340,7 +344,7 @@ struct Impl final : ImplBase {
     beta = dev.alloc<double>(L);
     const int nres = fft_res_blocks(n, L, sizeof(T));
     partials = dev.alloc<double>(std::max({nres, dot_blocks(), 64 * L * 3, 4096}));
-    max_hist = 4096;
+    max_hist = kMaxHistRows;
     hist = dev.alloc<double>((size_t)max_hist * kHistCols);
     dp = dev.alloc<DevParams>(1);
     flag = dev.alloc<int>(1);

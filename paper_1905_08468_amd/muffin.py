@@ -201,6 +201,56 @@ def _dptr(a):
     return a, a.ctypes.data_as(C.POINTER(C.c_double))
 
 
+def _working_dtype(cfg: Config):
+    import torch
+    return torch.float64 if cfg.mode == F64 else torch.float32
+
+
+def check_cube(t, shape, dtype, name, device=None):
+    """Raises ValueError unless t is a contiguous device tensor of the given
+    shape and dtype (on `device` if given): the library reads and writes
+    exactly that many elements through the raw pointer."""
+    if t is None:
+        raise ValueError(f"{name}: a tensor is required")
+    ok = (tuple(t.shape) == tuple(shape) and t.dtype == dtype and t.is_cuda
+          and t.is_contiguous() and (device is None or t.device == device))
+    if not ok:
+        raise ValueError(f"{name}: expected a contiguous {dtype} cuda tensor of shape "
+                         f"{tuple(shape)}{'' if device is None else ' on ' + str(device)}, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}"
+                         f"{'' if t.is_contiguous() else ' (not contiguous)'}")
+
+
+def check_weights(alpha, beta, n, L):
+    """Host weight arrays: alpha has n*n entries, beta L (or None).  Returns
+    the marshalled pairs of _dptr."""
+    a = _dptr(alpha)
+    b = _dptr(beta)
+    if a is not None and a[0].size != n * n:
+        raise ValueError(f"alpha must have n*n = {n * n} entries, got {a[0].size}")
+    if b is not None and b[0].size != L:
+        raise ValueError(f"beta must have L = {L} entries, got {b[0].size}")
+    return a, b
+
+
+def check_problem(cfg: Config, dirty, psf, alpha, beta, delta, x0=None):
+    """The checks every entry point that takes a problem applies: cube shapes,
+    the working dtype, one device for all cubes, weight lengths, and the
+    probe delta when the configuration runs ADA-PT."""
+    n, L = cfg.n, cfg.L
+    dt = _working_dtype(cfg)
+    check_cube(dirty, (L, n, n), dt, "dirty")
+    dv = dirty.device
+    check_cube(psf, (L, 2 * n, 2 * n), dt, "psf", dv)
+    if delta is not None:
+        check_cube(delta, (L, n, n), dt, "delta", dv)
+    elif cfg.sure:
+        raise ValueError("delta: the probe cube is required when cfg.sure is set")
+    if x0 is not None:
+        check_cube(x0, (L, n, n), dt, "x0", dv)
+    return check_weights(alpha, beta, n, L)
+
+
 class Muffin:
     """One solve on the current CUDA/HIP device and torch stream."""
 
@@ -219,10 +269,7 @@ class Muffin:
         self.h = h
 
     def _check(self, t, shape, name):
-        if tuple(t.shape) != tuple(shape) or t.dtype != self.dtype or not t.is_cuda \
-                or not t.is_contiguous():
-            raise ValueError(f"{name}: expected contiguous {self.dtype} cuda tensor {shape}, "
-                             f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+        check_cube(t, shape, self.dtype, name, self.device)
 
     @property
     def cube(self):
@@ -238,17 +285,9 @@ class Muffin:
         return r.as_dict()
 
     def set_problem(self, dirty, psf, alpha=None, beta=None, delta=None):
-        n, L = self.cfg.n, self.cfg.L
-        self._check(dirty, (L, n, n), "dirty")
-        self._check(psf, (L, 2 * n, 2 * n), "psf")
-        if delta is not None:
-            self._check(delta, (L, n, n), "delta")
-        a = _dptr(alpha)
-        b = _dptr(beta)
-        if a is not None and a[0].size != n * n:
-            raise ValueError("alpha must have n*n entries")
-        if b is not None and b[0].size != L:
-            raise ValueError("beta must have L entries")
+        a, b = check_problem(self.cfg, dirty, psf, alpha, beta, delta)
+        if dirty.device != self.device:
+            raise ValueError(f"dirty: on {dirty.device}, the handle is on {self.device}")
         self._keep = (dirty, psf, delta)
         rc = _lib.muffin_set_problem(self.h, _ptr(dirty), _ptr(psf),
                                      a[1] if a else None, b[1] if b else None, _ptr(delta))
@@ -402,10 +441,9 @@ def solve(cfg: Config, dirty, psf, iters: int, alpha=None, beta=None, delta=None
           stream=None):
     """One-call solve (muffin_solve): returns (sky tensor, report dict)."""
     import torch
-    dt = torch.float64 if cfg.mode == F64 else torch.float32
+    a, b = check_problem(cfg, dirty, psf, alpha, beta, delta, x0)
+    dt = _working_dtype(cfg)
     out = torch.empty((cfg.L, cfg.n, cfg.n), dtype=dt, device=dirty.device)
-    a = _dptr(alpha)
-    b = _dptr(beta)
     s = stream if stream is not None else torch.cuda.current_stream()
     rep = Report()
     rc = _lib.muffin_solve(C.byref(cfg), _ptr(dirty), _ptr(psf), a[1] if a else None,
@@ -438,15 +476,11 @@ class Server:
     def submit(self, cfg: Config, dirty, psf, max_iters: int, alpha=None, beta=None,
                delta=None, out=None):
         import torch
-        dt = torch.float64 if cfg.mode == F64 else torch.float32
+        a, b = check_problem(cfg, dirty, psf, alpha, beta, delta)
+        dt = _working_dtype(cfg)
         if out is None:
             out = torch.empty((cfg.L, cfg.n, cfg.n), dtype=dt, device=dirty.device)
-        for t, shape in ((dirty, (cfg.L, cfg.n, cfg.n)), (psf, (cfg.L, 2 * cfg.n, 2 * cfg.n)),
-                         (out, (cfg.L, cfg.n, cfg.n))):
-            if tuple(t.shape) != shape or t.dtype != dt or not t.is_contiguous():
-                raise ValueError(f"expected contiguous {dt} {shape}, got {t.dtype} {tuple(t.shape)}")
-        a = _dptr(alpha)
-        b = _dptr(beta)
+        check_cube(out, (cfg.L, cfg.n, cfg.n), dt, "out", dirty.device)
         tk = C.c_int64()
         # the C side reads the inputs when it admits the request
         torch.cuda.current_stream().synchronize()
@@ -590,14 +624,7 @@ class MultiStart:
         self.chunk = 0
 
     def set_problem(self, dirty, psf, alpha=None, beta=None, delta=None, chunk: int = 0):
-        v = self.views[0]
-        n, L = self.cfg.n, self.cfg.L
-        v._check(dirty, (L, n, n), "dirty")
-        v._check(psf, (L, 2 * n, 2 * n), "psf")
-        if delta is not None:
-            v._check(delta, (L, n, n), "delta")
-        a = _dptr(alpha)
-        b = _dptr(beta)
+        a, b = check_problem(self.cfg, dirty, psf, alpha, beta, delta)
         self._keep = (dirty, psf, delta)
         # set-up runs on the starts' own streams: inputs must be complete
         self.torch.cuda.current_stream().synchronize()
@@ -743,10 +770,13 @@ def vis_degrid(uv, x, stream=None):
     u = _vis_dev(uv, torch)
     L, K = u.shape[0], u.shape[1]
     n = x.shape[-1]
+    if x.dtype not in (torch.float32, torch.float64):
+        raise ValueError("x: float32 or float64 cube")
+    check_cube(x, (L, n, n), x.dtype, "x")
     mode = F64 if x.dtype == torch.float64 else F32
     out = torch.empty((L, K, 2), dtype=torch.float64, device=u.device)
     s = stream if stream is not None else torch.cuda.current_stream()
-    rc = _lib.muffin_vis_degrid(_ptr(u), L, K, n, int(mode), _ptr(x.contiguous()), _ptr(out),
+    rc = _lib.muffin_vis_degrid(_ptr(u), L, K, n, int(mode), _ptr(x), _ptr(out),
                                 C.c_void_p(s.cuda_stream))
     if rc:
         raise MuffinError(rc, "muffin_vis_degrid")

@@ -564,3 +564,108 @@ def test_full_side_adapt_iterations(mode, full_side_adapt):
         assert abs(rep["mu"] - ref.mu) <= 1e-3 * abs(ref.mu)
         assert abs(rep["gamma"] - ref.gamma) <= 1e-3 * abs(ref.gamma)
     h.close()
+
+
+# ------------------------------------------- band counts above 128 (DCT) --
+# The spectral kernels give each wave the 16-band output tiles kt and kt + 8;
+# the second exists only when L > 128 (bands 128 ... 255: the dual update and
+# clip of those DCT coefficients, their mask bits, and the T rows of the
+# adjoint product).  Per-band gains drawn uniformly in [0.2, 1.8] spread the
+# dirty cube's spectrum over every DCT frequency, so coefficients above 128
+# clip from the second iteration on and the derivative role reads set bits.
+
+def _band_gain_case(L, seed):
+    n = 32
+    prob = _problem(n, L, seed)
+    gain = np.random.default_rng(seed + 1000).uniform(0.2, 1.8, L)
+    dirty = prob.dirty * gain[:, None, None]
+    alpha, beta = synth.random_weights(L, n, seed)
+    return n, prob, dirty, alpha, beta
+
+
+_BAND_REF = {}
+
+
+def _band_adapt_ref(L, seed, iters, Delta, mu0, ga0, eta):
+    key = (L, seed, iters, Delta, mu0, ga0, eta)
+    if key not in _BAND_REF:
+        n, prob, dirty, alpha, beta = _band_gain_case(L, seed)
+        pb = om.make_problem(dirty, prob.psf, P=8, J=3, alpha=alpha, beta=beta)
+        tau = safe_tau(prob.psf, 10.0, 2 * mu0 * beta, 2 * ga0 * alpha)
+        eps = 0.05 * prob.sigma_w
+        ref = om.run_adapt(pb, mu0, ga0, iters, prob.delta, eps, prob.sigma_w, Delta=Delta,
+                           eta_mu=eta, eta_gamma=eta, tau=tau)
+        # the spectral clip is active above band 128 in the reference run
+        _, it = om.muffin_step(ref.states["S"], pb.Y, pb, ref.mu, ref.gamma, tau)
+        assert np.mean(np.abs(it["vt"][128:]) > 1) > 0.005
+        _BAND_REF[key] = (n, prob, dirty, alpha, beta, tau, eps, ref)
+    return _BAND_REF[key]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("form", ["f64", "bf16"])
+@pytest.mark.parametrize("L", [129, 200, 256])
+def test_adapt_band_counts_above_128(L, form):
+    """ADA-PT (Algs. 2-5) at n = 32 with L = 129, 200, 256 bands, 8 iterations
+    with theta updates at k = 3 and 6, against the oracle: in FP64 X, V, T of
+    all six state sets, U of both trajectories and the theta / SUGAR / PSURE
+    history; in the bf16 form X and theta."""
+    mm = _mm()
+    torch = _torch()
+    iters, Delta, mu0, ga0, eta = 8, 3, 0.5, 2.0, 1e-4
+    n, prob, dirty, alpha, beta, tau, eps, ref = _band_adapt_ref(L, 61 + L, iters, Delta,
+                                                                  mu0, ga0, eta)
+    mode = mm.F64 if form == "f64" else mm.F32_BF16DCT
+    dt = torch.float64 if form == "f64" else torch.float32
+    cfg = _config(mm, n, L, mode=mode, mu=mu0, gamma=ga0, tau=tau, pi_iters=0, sure=1,
+                  delta_period=Delta, eps_fd=eps, sigma_w=prob.sigma_w, eta_mu=eta,
+                  eta_gamma=eta)
+    h = mm.Muffin(cfg)
+    h.set_problem(dev(dirty, dt), dev(prob.psf, dt), alpha, beta, dev(prob.delta, dt))
+    rep = h.run(iters)
+    assert rep["theta_updates"] == len(ref.history) == 2
+    if form == "f64":
+        assert rel(host(h.sky()), ref.X) < 1e-10
+        sets = [(0, "S"), (1, "Sb"), (2, "Dm"), (3, "Dg"), (4, "Dbm"), (5, "Dbg")]
+        for s, key in sets:
+            st = ref.states[key]
+            for which, arr in [(0, st.X), (2, st.V), (3, st.T)]:
+                got = host(h.get_state(which, s))
+                assert rel(got, arr) < 1e-9 or np.abs(arr).max() == 0, (key, which)
+            # the bands above 128 on their own
+            got_v = host(h.get_state(2, s))[128:]
+            assert rel(got_v, st.V[128:]) < 1e-9 or np.abs(st.V[128:]).max() == 0, key
+        for s, key in [(0, "S"), (1, "Sb")]:
+            assert rel(host(h.get_state(1, s)), ref.states[key].U) < 1e-9, key
+        for row, r in zip(h.history(), ref.history):
+            assert int(row[0]) == r["k"]
+            for j, key in [(4, "sugar_mu"), (5, "sugar_gamma"), (6, "psure")]:
+                assert abs(row[j] - r[key]) <= 1e-9 * max(1.0, abs(r[key])), key
+            assert abs(row[1] - r["mu"]) <= 1e-12 * max(1.0, abs(r["mu"]))
+            assert abs(row[2] - r["gamma"]) <= 1e-12 * max(1.0, abs(r["gamma"]))
+    else:
+        assert rel(host(h.sky()), ref.X) < 1e-3
+        assert abs(rep["mu"] - ref.mu) <= 1e-3 * abs(ref.mu)
+        assert abs(rep["gamma"] - ref.gamma) <= 1e-3 * abs(ref.gamma)
+    h.close()
+
+
+@pytest.mark.timeout(600)
+def test_plain_f32_256_bands():
+    """Plain MUFFIN in FP32 at n = 32, L = 256 (both k-tiles of every wave of
+    the FP32 spectral kernel), 20 iterations against the oracle."""
+    mm = _mm()
+    torch = _torch()
+    L, iters, mu, gamma = 256, 20, 0.5, 2.0
+    n, prob, dirty, alpha, beta = _band_gain_case(L, 71)
+    pb = om.make_problem(dirty, prob.psf, P=8, J=3, alpha=alpha, beta=beta)
+    tau = safe_tau(prob.psf, 10.0, mu * beta, gamma * alpha)
+    ref = om.run_muffin(pb, mu, gamma, tau, iters)
+    _, it = om.muffin_step(ref, pb.Y, pb, mu, gamma, tau)
+    assert np.mean(np.abs(it["vt"][128:]) > 1) > 0.005
+    h = mm.Muffin(_config(mm, n, L, mode=mm.F32, mu=mu, gamma=gamma, tau=tau, pi_iters=0))
+    h.set_problem(dev(dirty, torch.float32), dev(prob.psf, torch.float32), alpha, beta)
+    h.run(iters)
+    assert rel(host(h.sky()), ref.X) < 1e-5
+    assert rel(host(h.get_state(3, 0)), ref.T) < 1e-4
+    h.close()
