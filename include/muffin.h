@@ -47,7 +47,9 @@ enum {
   MUFFIN_E_NONFINITE = -4, /* NaN or Inf in an input cube */
   MUFFIN_E_HIP = -5,       /* HIP runtime error */
   MUFFIN_E_STATE = -6,     /* call out of order (e.g. run before set_problem) */
-  MUFFIN_E_BUSY = -7       /* serving queue full */
+  MUFFIN_E_BUSY = -7,      /* serving queue full */
+  MUFFIN_E_SCRATCH = -8    /* too large for the static workspace of
+                              muffin_solve_noalloc */
 };
 
 /* Arithmetic forms.  F64: everything in double.  F32: FFT, wavelet,
@@ -193,6 +195,33 @@ int muffin_state_load(muffin_handle* h, const void* host_buf, size_t bytes);
 int muffin_solve(const muffin_config* cfg, const void* dirty, const void* psf,
                  const double* alpha, const double* beta, const void* delta, const void* x0,
                  int32_t iters, void* sky_out, muffin_report* report, void* stream);
+
+/* Allocation-free one-call solve, for callers that cannot allocate device
+ * memory: code that runs while its caller captures a HIP graph of other
+ * work, tight serving loops, harnesses that forbid hipMalloc.  Arguments,
+ * results and kernels are those of muffin_solve, but every device buffer and
+ * table of the solve (state, transfer functions, FFT and DCT tables, set-up
+ * temporaries) is carved from one static device array of
+ * MUFFIN_NOALLOC_BYTES bytes per GPU, which the library holds from its
+ * loading until the process ends; no hipMalloc, hipFree, hipHostMalloc or
+ * other allocating call is made (host memory for a few small structures
+ * aside).
+ *   Size limit: a configuration whose buffers, tables and set-up temporaries
+ *   do not fit returns MUFFIN_E_SCRATCH before any device work (for example,
+ *   plain FP32 solves fit up to 128 x 128 x 32 or 256 x 256 x 8 with the
+ *   power iteration, ADA-PT in FP32 up to 128 x 128 x 8; passing tau > 0
+ *   and pi_iters = 0 skips the power iteration's temporaries).
+ *   Sharing: every call on a GPU uses that GPU's one array, which keeps what
+ *   the last call left; each solve initialises everything it reads.  Calls
+ *   on one GPU are serialised by a per-GPU lock and return only after
+ *   `stream` has finished the solve; work the caller enqueues elsewhere that
+ *   overlaps a call must not touch its outputs.
+ * Synchronises `stream`. */
+#define MUFFIN_NOALLOC_BYTES (128u << 20)
+int muffin_solve_noalloc(const muffin_config* cfg, const void* dirty, const void* psf,
+                         const double* alpha, const double* beta, const void* delta,
+                         const void* x0, int32_t iters, void* sky_out, muffin_report* report,
+                         void* stream);
 
 /* Copies the current sky estimate X (Y trajectory) to x_out [L][n][n]. */
 int muffin_get_sky(muffin_handle* h, void* x_out);

@@ -592,8 +592,15 @@ static float bf16_value(uint16_t b) {
   return f;
 }
 
+size_t dct_plan_bytes(int L, int kind, int elem_bytes) {
+  const size_t Lp = kind == DCT_BF16X3 ? (L + 31) & ~31 : (L + 15) & ~15;
+  size_t b = region_round((size_t)elem_bytes * 2 * Lp * Lp);
+  if (kind == DCT_BF16X3) b += region_round(sizeof(uint16_t) * 4 * (Lp / 16) * (Lp / 32) * 64 * 8);
+  return b;
+}
+
 template <typename T>
-int dct_make_plan(DctPlan<T>& p, int L, int N, int kind) {
+int dct_make_plan(DctPlan<T>& p, int L, int N, int kind, Region* r) {
   if (L < 1 || L > 16 * kDctMaxKt) return -2;
   p.L = L;
   p.N = N;
@@ -616,7 +623,9 @@ int dct_make_plan(DctPlan<T>& p, int L, int N, int kind) {
         f1[o] = T(c[(size_t)(t * 16 + i) * Lp + ks * 4 + k]);   // C[row][col]
         f2[o] = T(c[(size_t)(ks * 4 + k) * Lp + t * 16 + i]);   // C^T[row][col]
       }
-  MUFFIN_HIP_CHECK(hipMalloc(&p.C, sizeof(T) * 2 * f1.size()));
+  p.borrowed = r != nullptr;
+  p.C = static_cast<T*>(region_alloc(r, sizeof(T) * 2 * f1.size()));
+  if (!p.C) return -3; /* E_NOMEM */
   MUFFIN_HIP_CHECK(hipMemcpy(p.C, f1.data(), sizeof(T) * f1.size(), hipMemcpyHostToDevice));
   MUFFIN_HIP_CHECK(hipMemcpy(p.C + f1.size(), f2.data(), sizeof(T) * f2.size(),
                              hipMemcpyHostToDevice));
@@ -639,7 +648,8 @@ int dct_make_plan(DctPlan<T>& p, int L, int N, int kind) {
             h[2 * cnt + o] = h2;
             h[3 * cnt + o] = bf16_bits((float)(v2 - (long double)bf16_value(h2)));
           }
-    MUFFIN_HIP_CHECK(hipMalloc(&p.Chi, sizeof(uint16_t) * h.size()));
+    p.Chi = static_cast<uint16_t*>(region_alloc(r, sizeof(uint16_t) * h.size()));
+    if (!p.Chi) return -3; /* E_NOMEM */
     MUFFIN_HIP_CHECK(hipMemcpy(p.Chi, h.data(), sizeof(uint16_t) * h.size(), hipMemcpyHostToDevice));
     p.Clo = p.Chi + cnt;
   }
@@ -648,8 +658,8 @@ int dct_make_plan(DctPlan<T>& p, int L, int N, int kind) {
 
 template <typename T>
 void dct_free_plan(DctPlan<T>& p) {
-  if (p.C) (void)hipFree(p.C);
-  if (p.Chi) (void)hipFree(p.Chi);
+  if (p.C && !p.borrowed) (void)hipFree(p.C);
+  if (p.Chi && !p.borrowed) (void)hipFree(p.Chi);
   p.C = nullptr;
   p.Chi = p.Clo = nullptr;
 }
@@ -727,8 +737,8 @@ int dct_update(const DctPlan<T>& p, const DctIO<T>& io, const DevParams* dp, hip
   return 0;
 }
 
-template int dct_make_plan<double>(DctPlan<double>&, int, int, int);
-template int dct_make_plan<float>(DctPlan<float>&, int, int, int);
+template int dct_make_plan<double>(DctPlan<double>&, int, int, int, Region*);
+template int dct_make_plan<float>(DctPlan<float>&, int, int, int, Region*);
 template void dct_free_plan<double>(DctPlan<double>&);
 template void dct_free_plan<float>(DctPlan<float>&);
 template int dct_update<double>(const DctPlan<double>&, const DctIO<double>&,

@@ -1352,8 +1352,15 @@ static std::vector<cplx<T>> stage_tables(int lognf) {
   return out;
 }
 
+size_t fft_plan_bytes(int n, int L, int elem_bytes) {
+  const int logn = 31 - __builtin_clz(n);
+  const size_t c = 2 * (size_t)elem_bytes;  // one complex value
+  return region_round(c * (2 * (size_t)n + stage_table_len(logn) + stage_table_len(logn + 1))) +
+         region_round(c * (size_t)L * (n + 1) * 2 * n);
+}
+
 template <typename T>
-int fft_make_plan(FftPlan<T>& p, int n, int L, hipStream_t s) {
+int fft_make_plan(FftPlan<T>& p, int n, int L, hipStream_t s, Region* r) {
   p.n = n;
   p.L = L;
   const int m2 = 2 * n;
@@ -1368,21 +1375,24 @@ int fft_make_plan(FftPlan<T>& p, int n, int L, hipStream_t s) {
   // the kernels size their LDS copies of the tables with stage_table_len
   if ((int)tr.size() != stage_table_len(logn) || (int)tc.size() != stage_table_len(logn + 1))
     return -2; /* E_SHAPE */
-  MUFFIN_HIP_CHECK(hipMalloc(&p.tw, sizeof(cplx<T>) * (m2 + tr.size() + tc.size())));
+  p.borrowed = r != nullptr;
+  p.tw = static_cast<cplx<T>*>(region_alloc(r, sizeof(cplx<T>) * (m2 + tr.size() + tc.size())));
+  if (!p.tw) return -3; /* E_NOMEM */
   p.twr = p.tw + m2;
   p.twc = p.twr + tr.size();
   MUFFIN_HIP_CHECK(hipMemcpy(p.tw, h.data(), sizeof(cplx<T>) * m2, hipMemcpyHostToDevice));
   MUFFIN_HIP_CHECK(hipMemcpy(p.twr, tr.data(), sizeof(cplx<T>) * tr.size(), hipMemcpyHostToDevice));
   MUFFIN_HIP_CHECK(hipMemcpy(p.twc, tc.data(), sizeof(cplx<T>) * tc.size(), hipMemcpyHostToDevice));
-  MUFFIN_HIP_CHECK(hipMalloc(&p.Kh, sizeof(cplx<T>) * (size_t)L * (n + 1) * m2));
+  p.Kh = static_cast<cplx<T>*>(region_alloc(r, sizeof(cplx<T>) * (size_t)L * (n + 1) * m2));
+  if (!p.Kh) return -3; /* E_NOMEM */
   (void)s;
   return 0;
 }
 
 template <typename T>
 void fft_free_plan(FftPlan<T>& p) {
-  if (p.tw) (void)hipFree(p.tw);
-  if (p.Kh) (void)hipFree(p.Kh);
+  if (p.tw && !p.borrowed) (void)hipFree(p.tw);
+  if (p.Kh && !p.borrowed) (void)hipFree(p.Kh);
   p.tw = p.twr = p.twc = nullptr;
   p.Kh = nullptr;
 }
@@ -1607,8 +1617,8 @@ int fft_chain(const FftPlan<T>& p, const ChainIO<T>& io, int op, hipStream_t s) 
   return launch_row<T, IN_SPEC, OUT_REAL>(c, ns, s);
 }
 
-template int fft_make_plan<double>(FftPlan<double>&, int, int, hipStream_t);
-template int fft_make_plan<float>(FftPlan<float>&, int, int, hipStream_t);
+template int fft_make_plan<double>(FftPlan<double>&, int, int, hipStream_t, Region*);
+template int fft_make_plan<float>(FftPlan<float>&, int, int, hipStream_t, Region*);
 template void fft_free_plan<double>(FftPlan<double>&);
 template void fft_free_plan<float>(FftPlan<float>&);
 template int fft_psf_spectrum<double>(FftPlan<double>&, const double*, cplx<double>*, hipStream_t);

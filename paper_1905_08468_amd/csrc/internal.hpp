@@ -61,6 +61,19 @@ constexpr int kMaxBases = 8;
 constexpr int kHistCols = 8;  // k, mu, gamma, tau, sugar_mu, sugar_gamma, psure, res2
 constexpr int kMaxHistRows = 4096;  // theta updates kept per handle
 
+// Device memory for buffers and plan tables: hipMalloc (region == nullptr),
+// or consecutive 256-byte-aligned pieces of a region the caller owns (the
+// allocation-free solve).  region_alloc returns nullptr when the region is
+// full (or hipMalloc fails); pieces of a region are never freed one by one:
+// the owner rewinds `used`.
+struct Region {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+};
+void* region_alloc(Region* r, size_t bytes);
+inline size_t region_round(size_t bytes) { return (bytes + 255) & ~size_t(255); }
+
 // ---------------------------------------------------------------- FFT ----
 // FFT plan: side n (image n x n, FFT grid 2n x 2n).
 template <typename T>
@@ -71,6 +84,7 @@ struct FftPlan {
   cplx<T>* twr = nullptr;  // stage twiddle tables, length-n FFT (inside tw's block)
   cplx<T>* twc = nullptr;  // stage twiddle tables, length-2n FFT
   cplx<T>* Kh = nullptr;   // [L][n+1][2n] transfer function / (4 n^2)
+  bool borrowed = false;   // tables live in a caller's region (not freed)
 };
 
 // One input/output pair of a batched convolution chain.
@@ -86,7 +100,9 @@ struct ChainIO {
 };
 
 template <typename T>
-int fft_make_plan(FftPlan<T>& p, int n, int L, hipStream_t s);
+int fft_make_plan(FftPlan<T>& p, int n, int L, hipStream_t s, Region* r = nullptr);
+// device bytes of a plan's tables (as allocated by fft_make_plan)
+size_t fft_plan_bytes(int n, int L, int elem_bytes);
 template <typename T>
 void fft_free_plan(FftPlan<T>& p);
 // K-PSF: Kh from the PSF cube [L][2n][2n] (centre (n, n)); tmp holds
@@ -188,6 +204,7 @@ struct DctPlan {
   T* C = nullptr;            // [Lp][Lp] padded DCT-II matrix (row k, column l)
   uint16_t* Chi = nullptr;   // bf16 hi/lo fragments of C and C^T (BF16X3 only)
   uint16_t* Clo = nullptr;   // (inside Chi's allocation)
+  bool borrowed = false;     // tables live in a caller's region (not freed)
 };
 
 template <typename T>
@@ -210,7 +227,9 @@ struct DctIO {
 // (one per thread and block; the largest of its launch shapes).
 size_t dct_mask_words(int N);
 template <typename T>
-int dct_make_plan(DctPlan<T>& p, int L, int N, int kind);
+int dct_make_plan(DctPlan<T>& p, int L, int N, int kind, Region* r = nullptr);
+// device bytes of a plan's tables (as allocated by dct_make_plan)
+size_t dct_plan_bytes(int L, int kind, int elem_bytes);
 template <typename T>
 void dct_free_plan(DctPlan<T>& p);
 template <typename T>

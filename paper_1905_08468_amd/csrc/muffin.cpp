@@ -154,25 +154,68 @@ int validate(const muffin_config* c) {
   return MUFFIN_OK;
 }
 
+}  // namespace muffin
+
+void* muffin::region_alloc(Region* r, size_t bytes) {
+  if (bytes == 0) bytes = 1;
+  if (r == nullptr) {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return p;
+  }
+  const size_t need = region_round(bytes);
+  if (r->used > r->cap || need > r->cap - r->used) return nullptr;
+  void* p = r->base + r->used;
+  r->used += need;
+  return p;
+}
+
+namespace muffin {
+
+// The device buffers of a handle or of a set-up step: hipMalloc'd pieces,
+// or pieces of a caller's region (then release() rewinds the region to where
+// this object's first piece began; such objects are released in the reverse
+// order of their first allocation).
 struct Dev {
   std::vector<void*> owned;
   bool failed = false;
+  Region* region = nullptr;
+  size_t mark = 0;
+  bool marked = false;
+  Dev() = default;
+  explicit Dev(Region* r) : region(r) {}
   template <typename U>
   U* alloc(size_t count) {
     if (failed) return nullptr;
-    void* p = nullptr;
     if (count == 0) count = 1;
-    if (hipMalloc(&p, sizeof(U) * count) != hipSuccess) {
-      (void)hipGetLastError();
+    if (region && !marked) {
+      mark = region->used;
+      marked = true;
+    }
+    void* p = region_alloc(region, sizeof(U) * count);
+    if (!p) {
       failed = true;
       return nullptr;
     }
-    owned.push_back(p);
+    if (!region) owned.push_back(p);
     return static_cast<U*>(p);
+  }
+  // marks the region's current end now, so that release() also rewinds
+  // pieces taken from the region by others (plan tables) after this call
+  void hold() {
+    if (region && !marked) {
+      mark = region->used;
+      marked = true;
+    }
   }
   void release() {
     for (void* p : owned) (void)hipFree(p);
     owned.clear();
+    if (region && marked) region->used = mark;
+    marked = false;
   }
 };
 
@@ -259,6 +302,7 @@ struct Impl final : ImplBase {
   DctPlan<T> dct;
   DevParams* dp = nullptr;
   DevParams hp{};
+  Region* region = nullptr;  // non-null: every device buffer comes from it
   T *X[kMaxSets]{}, *Xt[kMaxSets]{}, *U[kMaxSets]{}, *V[kMaxSets]{}, *Tt[kMaxSets]{};
   T *G[kMaxSets]{}, *S[kMaxSets]{}, *scr[kMaxSets]{};
   uint8_t *maskU[2]{}, *maskV[2]{};
@@ -319,6 +363,7 @@ struct Impl final : ImplBase {
   T* zbuf(int s) { return scr[s] + 3 * LN; }
 
   int init() override {
+    dev.region = region;
     for (int s = 0; s < nsets; ++s) {
       X[s] = dev.alloc<T>(LN);
       Xt[s] = dev.alloc<T>(LN);
@@ -358,7 +403,7 @@ struct Impl final : ImplBase {
       dev.release();
       return MUFFIN_E_NOMEM;
     }
-    RC(fft_make_plan(fft, n, L, st));
+    RC(fft_make_plan(fft, n, L, st, region));
     dwt.n = n;
     dwt.L = L;
     dwt.P = P;
@@ -366,7 +411,8 @@ struct Impl final : ImplBase {
     if (!star) RC(dwt_upload_filters(P));
     RC(dct_make_plan(dct, L, N,
                       sizeof(T) == 8 ? DCT_F64
-                                     : (cfg.mode == MUFFIN_F32_BF16DCT ? DCT_BF16X3 : DCT_F32)));
+                                     : (cfg.mode == MUFFIN_F32_BF16DCT ? DCT_BF16X3 : DCT_F32),
+                      region));
     hp.sigma = cfg.sigma;
     hp.mu = cfg.mu;
     hp.gamma = cfg.gamma;
@@ -399,12 +445,19 @@ struct Impl final : ImplBase {
   int power_iteration(const T* psf) {
     FftPlan<double> f64;
     FftPlan<double>* pf = nullptr;
-    Dev tmp;
+    Dev tmp(region);
+    tmp.hold();
     double* psf64 = nullptr;
     if constexpr (sizeof(T) == 8) {
       pf = reinterpret_cast<FftPlan<double>*>(&fft);
     } else {
-      RC(fft_make_plan(f64, n, L, st));
+      // (the plan's tables come first from a region: tmp's pieces follow)
+      const int prc = fft_make_plan(f64, n, L, st, region);
+      if (prc) {
+        fft_free_plan(f64);
+        tmp.release();
+        return prc;
+      }
       pf = &f64;
       psf64 = tmp.alloc<double>((size_t)L * 4 * N);
       cplx<double>* ktmp = tmp.alloc<cplx<double>>((size_t)L * (n + 1) * 2 * n);
@@ -484,7 +537,7 @@ struct Impl final : ImplBase {
     MUFFIN_HIP_CHECK(hipMemcpyAsync(Y, dy, sizeof(T) * LN, hipMemcpyDeviceToDevice, st));
     // transfer functions (K-PSF)
     {
-      Dev tmp;
+      Dev tmp(region);
       cplx<T>* ktmp = tmp.alloc<cplx<T>>((size_t)L * (n + 1) * 2 * n);
       if (tmp.failed) return MUFFIN_E_NOMEM;
       int rc = fft_psf_spectrum(fft, ps, ktmp, st);
@@ -1569,6 +1622,99 @@ int muffin_solve(const muffin_config* cfg, const void* dirty, const void* psf,
   return rc;
 }
 
+}  // extern "C"
+
+// ---- allocation-free solve ----
+// One static device array per GPU holds every buffer and table of the solve
+// (the handle's state, the transfer functions, the FFT and DCT tables and
+// the set-up temporaries), carved in order by a Region.  Its device address
+// on each GPU is looked up once, with that GPU current; host code never
+// passes the array's own name to a kernel or a copy.
+namespace {
+constexpr size_t kNoAllocBytes = size_t(MUFFIN_NOALLOC_BYTES);
+constexpr int kNoAllocDevices = 64;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+struct NoAllocSlot {
+  std::mutex mu;         // serialises the solves on one GPU
+  void* ptr = nullptr;   // device address of `scratch` on that GPU
+};
+NoAllocSlot g_noalloc[kNoAllocDevices];
+
+// Bytes the solve of *c takes from the array: the resident workspace, the
+// FFT and DCT tables, a margin for the 256-byte rounding of every piece, and
+// the larger of the two set-up temporaries (the PSF spectra, then the FP64
+// power iteration with its own plan in the FP32 forms).
+size_t noalloc_need(const muffin_config* c) {
+  const size_t n = c->n, L = c->L, N = n * n, LN = L * N;
+  const int es = c->mode == MUFFIN_F64 ? 8 : 4;
+  const int kind = es == 8 ? DCT_F64 : (c->mode == MUFFIN_F32_BF16DCT ? DCT_BF16X3 : DCT_F32);
+  const size_t resident = workspace_bytes_of(c) + fft_plan_bytes((int)n, (int)L, es) +
+                          dct_plan_bytes((int)L, kind, es) + 128 * 256;
+  const size_t spec = region_round((size_t)2 * es * L * (n + 1) * 2 * n);
+  size_t pi = 0;
+  if (c->tau <= 0 || c->pi_iters > 0) {
+    pi = 2 * region_round(8 * LN) + 2 * region_round(16 * LN) + region_round(24 * L);
+    if (es == 4)
+      pi += fft_plan_bytes((int)n, (int)L, 8) + region_round(8 * 4 * LN) +
+            region_round((size_t)16 * L * (n + 1) * 2 * n);
+  }
+  return resident + std::max(spec, pi);
+}
+}  // namespace
+
+extern "C" {
+
+int muffin_solve_noalloc(const muffin_config* cfg, const void* dirty, const void* psf,
+                         const double* alpha, const double* beta, const void* delta,
+                         const void* x0, int32_t iters, void* sky_out, muffin_report* report,
+                         void* stream) {
+  if (!sky_out || !dirty || !psf || iters < 0) return MUFFIN_E_INVAL;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (noalloc_need(cfg) > kNoAllocBytes) return MUFFIN_E_SCRATCH;
+  int d = 0;
+  if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= kNoAllocDevices) return MUFFIN_E_HIP;
+  NoAllocSlot& slot = g_noalloc[d];
+  std::lock_guard<std::mutex> lock(slot.mu);
+  if (!slot.ptr) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return MUFFIN_E_HIP;
+    }
+    slot.ptr = ptr;
+  }
+  Region region;
+  region.base = static_cast<char*>(slot.ptr);
+  region.cap = kNoAllocBytes;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // the same handle and calls as muffin_solve; the Impl's buffers come from
+  // the region (its destructor rewinds it), and set_problem zeroes the
+  // state, so nothing depends on what an earlier call left in the array
+  std::unique_ptr<ImplBase> impl;
+  if (cfg->mode == MUFFIN_F64) {
+    auto* m = new (std::nothrow) Impl<double>(*cfg, st);
+    if (m) m->region = &region;
+    impl.reset(m);
+  } else {
+    auto* m = new (std::nothrow) Impl<float>(*cfg, st);
+    if (m) m->region = &region;
+    impl.reset(m);
+  }
+  if (!impl) return MUFFIN_E_NOMEM;
+  rc = impl->init();
+  if (!rc) rc = impl->set_problem(dirty, psf, alpha, beta, delta);
+  if (!rc && x0) rc = impl->set_initial(x0);
+  if (!rc) rc = impl->run(iters);
+  if (!rc && report) rc = impl->report(report);
+  if (!rc) rc = impl->get_state(0, 0, sky_out);
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = MUFFIN_E_HIP;
+  impl.reset();
+  // a region that ran out maps to the size error, not to an allocation error
+  if (rc == MUFFIN_E_NOMEM) rc = MUFFIN_E_SCRATCH;
+  return rc;
+}
+
 int muffin_destroy(muffin_handle* h) {
   if (!h) return MUFFIN_E_INVAL;
   (void)hipStreamSynchronize(h->stream);
@@ -1606,6 +1752,7 @@ const char* muffin_strerror(int code) {
     case MUFFIN_E_INVAL: return "invalid argument or configuration";
     case MUFFIN_E_SHAPE: return "unsupported size";
     case MUFFIN_E_NOMEM: return "device allocation failed";
+    case MUFFIN_E_SCRATCH: return "problem too large for the static workspace of muffin_solve_noalloc";
     case MUFFIN_E_NONFINITE: return "non-finite value in an input cube";
     case MUFFIN_E_HIP: return "HIP runtime error";
     case MUFFIN_E_STATE: return "call out of order";

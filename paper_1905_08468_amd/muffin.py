@@ -21,7 +21,7 @@ TAU_OPNORM, TAU_PAPER_SUM = 0, 1
 DICT_DAUBECHIES, DICT_STARLET = 0, 1
 
 ERRORS = {0: "ok", -1: "E_INVAL", -2: "E_SHAPE", -3: "E_NOMEM", -4: "E_NONFINITE",
-          -5: "E_HIP", -6: "E_STATE", -7: "E_BUSY"}
+          -5: "E_HIP", -6: "E_STATE", -7: "E_BUSY", -8: "E_SCRATCH"}
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED = 0, 1, 2, 3
 
 
@@ -92,7 +92,7 @@ EXPORTS = [
     "muffin_op_WsT", "muffin_op_dct", "muffin_op_idct",
     "muffin_set_timing", "muffin_get_timing", "muffin_stage_name",
     "muffin_set_initial", "muffin_state_bytes", "muffin_state_save", "muffin_state_load",
-    "muffin_solve",
+    "muffin_solve", "muffin_solve_noalloc",
     "muffin_server_default_config", "muffin_server_create", "muffin_server_submit",
     "muffin_server_poll", "muffin_server_wait", "muffin_server_cancel",
     "muffin_server_get_stats", "muffin_server_destroy",
@@ -134,6 +134,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "muffin_state_save": ([vp, vp, C.c_size_t], C.c_int),
         "muffin_state_load": ([vp, vp, C.c_size_t], C.c_int),
         "muffin_solve": ([cfgp, vp, vp, dp, dp, vp, vp, i32, vp, C.POINTER(Report), vp], C.c_int),
+        "muffin_solve_noalloc": ([cfgp, vp, vp, dp, dp, vp, vp, i32, vp, C.POINTER(Report), vp],
+                                 C.c_int),
         "muffin_server_default_config": ([C.POINTER(ServerConfig)], C.c_int),
         "muffin_server_create": ([C.POINTER(vp), C.POINTER(ServerConfig)], C.c_int),
         "muffin_server_submit": ([vp, cfgp, vp, vp, dp, dp, vp, i32, vp,
@@ -452,6 +454,31 @@ def solve(cfg: Config, dirty, psf, iters: int, alpha=None, beta=None, delta=None
     if rc:
         raise MuffinError(rc, "muffin_solve")
     return out, rep.as_dict()
+
+
+def solve_noalloc(cfg: Config, dirty, psf, iters: int, alpha=None, beta=None, delta=None,
+                  x0=None, out=None, stream=None):
+    """One-call solve that allocates no device memory in the library
+    (muffin_solve_noalloc): its buffers live in a static array of
+    NOALLOC_BYTES per GPU.  `out` (the sky) may be passed so that the call
+    allocates nothing in torch either.  Returns (sky tensor, report dict)."""
+    import torch
+    a, b = check_problem(cfg, dirty, psf, alpha, beta, delta, x0)
+    dt = _working_dtype(cfg)
+    if out is None:
+        out = torch.empty((cfg.L, cfg.n, cfg.n), dtype=dt, device=dirty.device)
+    check_cube(out, (cfg.L, cfg.n, cfg.n), dt, "out", dirty.device)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rep = Report()
+    rc = _lib.muffin_solve_noalloc(C.byref(cfg), _ptr(dirty), _ptr(psf), a[1] if a else None,
+                                   b[1] if b else None, _ptr(delta), _ptr(x0), int(iters),
+                                   _ptr(out), C.byref(rep), C.c_void_p(s.cuda_stream))
+    if rc:
+        raise MuffinError(rc, "muffin_solve_noalloc")
+    return out, rep.as_dict()
+
+
+NOALLOC_BYTES = 128 << 20
 
 
 class Server:
