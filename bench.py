@@ -64,7 +64,28 @@ def wavelet_fmas(stage, n, L, sets):
 
 FP32_VECTOR_PEAK, FP32_VECTOR_UNPACKED = 157.3, 78.6   # TFLOP/s (packed FP32 is not used)
 
+
+def fft_chain_flops(n, L, sets):
+    """Nominal flops of the FFT chain: H^T H is four real 2-D transforms of
+    the (2n)^2 grid per band and set, counted as 2.5 M log2 M for M = 4 n^2
+    points (the radix-2 count of a real transform of M points; the pruned
+    passes compute fewer)."""
+    import math
+    M = 4 * n * n
+    return sets * L * 4 * 2.5 * M * math.log2(M)
+
 STAGE_TRAFFIC = {
+    # the five launches of the FFT chain (H^T H of every set): the first
+    # row pass reads the image (1 V) and writes the half spectrum (2 V); the
+    # column passes read and write it (2 + 2 V) and read the transfer
+    # function once for all sets (4 V); the middle row pass reads and writes
+    # spectra (2 + 2 V); the last reads the spectrum and writes the image
+    # (2 + 1 V).  6 sets: 18, 28, 24, 28, 18 V (116 V per chain).
+    "fft_row1": (18, 0),
+    "fft_col1": (28, 0),
+    "fft_row2": (24, 0),
+    "fft_col2": (28, 0),
+    "fft_row3": (18, 0),
     "synthesis_l1": (54, 0),
     "analysis_l1_primal": (30, 2),
     "analysis_l1_deriv": (62, 4),
@@ -130,33 +151,110 @@ def parse():
     ap.add_argument("--no-starlet", action="store_true")
     ap.add_argument("--no-vis", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=20)
     ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-sweep", default="",
+                    help="comma-separated further arrival rates (req/s) replayed after "
+                         "--serve-rate with the same requests")
     return ap.parse_args()
 
 
-def cpu_baseline(prob, n_bands_sample=1, Delta=10):
-    """The FP64 oracle, as it stands, on a bounded sample of the workload:
-    one ADA-PT iteration of the full-size images on `n_bands_sample` bands
-    (per-band work dominates; it is scaled by L / n_bands_sample)."""
+def _oracle_band_step(args):
+    """Worker: `iters` iterations of the FP64 oracle on one band's images
+    (ADA-PT when `adapt`, else plain MUFFIN), the band's own time in s."""
+    dirty, psf, delta, sigma_w, adapt, iters = args
     import numpy as np
     from oracle import muffin as om
-    L = prob.L
-    sl = slice(0, n_bands_sample)
-    alpha = np.ones(prob.n * prob.n)
-    beta = np.ones(n_bands_sample)
-    pb = om.make_problem(prob.dirty[sl], prob.psf[sl], P=8, J=3, alpha=alpha, beta=beta)
+    n = dirty.shape[-1]
+    pb = om.make_problem(dirty[None], psf[None], P=8, J=3, alpha=np.ones(n * n),
+                         beta=np.ones(1))
     t0 = time.perf_counter()
-    om.run_adapt(pb, 1.0, 1.0, 1, prob.delta[sl], 0.01 * prob.sigma_w, prob.sigma_w,
-                 Delta=Delta, tau=1e-4)
-    dt = time.perf_counter() - t0
-    per_iter = dt * L / n_bands_sample
-    return {"value": 1.0 / per_iter, "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 ADA-PT iteration (Alg. 5) of the FP64 numpy oracle on {n_bands_sample} "
-                      f"of {L} bands at {prob.n}x{prob.n} px ({dt:.1f} s), scaled x{L // n_bands_sample}; "
-                      "numpy FFT and wavelet loops single-threaded",
-            "cpu": platform.processor() or platform.machine(),
-            "host_threads": os.cpu_count()}
+    if adapt:
+        om.run_adapt(pb, 1.0, 1.0, iters, delta[None], 0.01 * sigma_w, sigma_w, Delta=10,
+                     tau=1e-4)
+    else:
+        om.run_muffin(pb, 1.0, 1.0, 1e-4, iters)
+    return time.perf_counter() - t0
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def _oracle_warm(_):
+    import numpy  # noqa: F401
+    from oracle import muffin  # noqa: F401
+    return os.getpid()
+
+
+def cpu_baseline(prob, synth, workers=None):
+    """The FP64 oracle, as it stands (numpy, one thread per process), on
+    bounded samples, with one band per worker process on the host's cores:
+      - the benchmark workload: one ADA-PT iteration of as many 1024^2 bands
+        as there are workers, all at once; the per-band work (FFT
+        convolutions, wavelet transforms) dominates the oracle's iteration,
+        so the cube's rate is the sample's scaled by L / bands;
+      - 256^2 x 64 (ADA-PT): one iteration of `workers` bands, scaled;
+      - 64^2 x 8 (plain MUFFIN): 20 iterations of the whole cube in one
+        process (the oracle's own band loop).
+    Worker processes are started fresh (spawn) with one BLAS thread each."""
+    import multiprocessing as mp
+    import numpy as np
+    from oracle import muffin as om
+    ncpu = os.cpu_count() or 1
+    workers = workers or max(1, min(16, ncpu, prob.L))
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
+                                             "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"
+    try:
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(workers) as pool:
+            pool.map(_oracle_warm, range(workers))
+            jobs = [(prob.dirty[b], prob.psf[b], prob.delta[b], prob.sigma_w, True, 1)
+                    for b in range(workers)]
+            t0 = time.perf_counter()
+            per_band = pool.map(_oracle_band_step, jobs)
+            wall = time.perf_counter() - t0
+            p1 = synth.make_config("c1", seed=0)
+            jobs = [(p1.dirty[b], p1.psf[b], p1.delta[b], p1.sigma_w, True, 1)
+                    for b in range(min(workers, p1.L))]
+            t0 = time.perf_counter()
+            pool.map(_oracle_band_step, jobs)
+            wall1 = time.perf_counter() - t0
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    p0 = synth.make_config("c0", seed=0)
+    pb0 = om.make_problem(p0.dirty, p0.psf, P=8, J=3)
+    t0 = time.perf_counter()
+    om.run_muffin(pb0, 1.0, 1.0, 1e-3, 20)
+    t_c0 = (time.perf_counter() - t0) / 20
+    per_iter = wall * prob.L / workers
+    nb1 = min(workers, p1.L)
+    return {"value": 1.0 / per_iter, "unit": "iters/s", "cores": workers, "kind": "oracle",
+            "sample": f"1 ADA-PT iteration (Alg. 5) of the FP64 numpy oracle on {workers} of "
+                      f"{prob.L} bands of {prob.n}x{prob.n} px, one band per process on "
+                      f"{workers} cores at once ({wall:.1f} s wall; single band "
+                      f"{np.mean(per_band):.1f} s), scaled x{prob.L / workers:g}",
+            "cpu": _cpu_model(), "host_threads": ncpu,
+            "other_workloads": {
+                "adapt_256x256x64": {"value": 1.0 / (wall1 * p1.L / nb1), "unit": "iters/s",
+                                     "sample": f"1 ADA-PT iteration on {nb1} of {p1.L} bands "
+                                               f"at once ({wall1:.1f} s), scaled "
+                                               f"x{p1.L / nb1:g}"},
+                "plain_64x64x8": {"value": 1.0 / t_c0, "unit": "iters/s",
+                                  "sample": "20 plain MUFFIN iterations of the whole cube, "
+                                            "one process"}}}
 
 
 def _class_inputs(synth, torch, n, L, seed, dtype):
@@ -386,59 +484,84 @@ def vis_form(mm, torch, synth, steps, seed=0):
             "ms_per_step": round(1e3 * el / steps, 3), "psure": rep["psure"]}
 
 
-def serve_form(mm, torch, synth, n_req, rate, seed=11):
-    """Serving form: Poisson arrivals (rate req/s) of plain deconvolution
-    solves, sizes uniform over {64,...,512}^2 px x {8,...,64} bands, FP32 with
-    the bf16 DCT, each to a relative change of 1e-4 (at most 2000
-    iterations), through the continuous-batching server (8 slots)."""
+def serve_form(mm, torch, synth, prob_c2, n_req, rates, seed=11, slots=8):
+    """Serving form (the paper has none; the workload is the serving
+    configuration of the benchmark): Poisson arrivals of plain deconvolution
+    solves, sizes uniform over n in {64, ..., 1024} x L in {8, ..., 256}
+    (powers of two), FP32 with the bf16 DCT, each to a relative change of
+    1e-4 or 2000 iterations, through the continuous-batching server.  The
+    same seeded draw of `n_req` requests is replayed at every rate of
+    `rates` (req/s); inputs of a size class are generated once (the
+    1024-pixel classes take the first L bands of the 1024^2 x 256 cube)."""
     import numpy as np
     rng = np.random.default_rng(seed)
-    ns, Ls = [64, 128, 256, 512], [8, 16, 32, 64]
+    ns, Ls = [64, 128, 256, 512, 1024], [8, 16, 32, 64, 128, 256]
     classes = [(n, L) for n in ns for L in Ls]
-    inputs = {c: _class_inputs(synth, torch, c[0], c[1], 2000 + c[0] + c[1], torch.float32)
-              for c in classes}
+    picks = [classes[i] for i in rng.integers(0, len(classes), size=n_req)]
+    gaps = rng.exponential(1.0, size=n_req)          # arrivals at rate r: gaps / r
+    inputs = {}
+    for c in sorted(set(picks)):
+        n, L = c
+        if n == prob_c2.n:
+            d = lambda a: torch.from_numpy(np.ascontiguousarray(a[:L])).to("cuda:0",
+                                                                            torch.float32)
+            inputs[c] = (d(prob_c2.dirty), d(prob_c2.psf))
+        else:
+            _, di, ps, _ = _class_inputs(synth, torch, n, L, 2000 + n + L, torch.float32)
+            inputs[c] = (di, ps)
     torch.cuda.synchronize()
     cfgs = {c: mm.default_config(c[0], c[1], mode=mm.F32_BF16DCT, stop_rel=1e-4,
-                                 check_every=10, pi_iters=30, pi_tol=1e-4) for c in classes}
-    srv = mm.Server(max_active=8)
+                                 check_every=10, pi_iters=30, pi_tol=1e-4) for c in inputs}
+    srv = mm.Server(max_active=slots)
     # warm-up: one short solve per size class (handles pooled, kernels loaded)
-    warm = [srv.submit(cfgs[c], inputs[c][1], inputs[c][2], 10) for c in classes]
-    for t in warm:
+    for t in [srv.submit(cfgs[c], inputs[c][0], inputs[c][1], 10) for c in inputs]:
         srv.wait(t)
-    picks = [classes[i] for i in rng.integers(0, len(classes), size=n_req)]
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
-    tickets = []
-    t0 = time.perf_counter()
-    for c, ta in zip(picks, arrivals):
-        dt = t0 + ta - time.perf_counter()
-        if dt > 0:
-            time.sleep(dt)
-        tickets.append((c, srv.submit(cfgs[c], inputs[c][1], inputs[c][2], 2000)))
-    lat, its, vox_it, stopped = [], [], 0.0, 0
-    for c, t in tickets:
-        r = srv.wait(t)
-        if r["status"] != mm.REQ_DONE:
-            raise RuntimeError(f"request {t} ended with status {r['status']}")
-        lat.append(r["latency_ms"])
-        k = r["report"]["iters_done"]
-        its.append(k)
-        stopped += r["report"]["stopped"]
-        vox_it += c[0] * c[0] * c[1] * k
-    span = time.perf_counter() - t0
+    runs = []
+    for rate in rates:
+        arrivals = np.cumsum(gaps / rate)
+        tickets = []
+        t0 = time.perf_counter()
+        for c, ta in zip(picks, arrivals):
+            dt = t0 + ta - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append((c, srv.submit(cfgs[c], inputs[c][0], inputs[c][1], 2000)))
+        lat, its, vox_it, stopped = [], [], 0.0, 0
+        for c, t in tickets:
+            r = srv.wait(t)
+            if r["status"] != mm.REQ_DONE:
+                raise RuntimeError(f"request {t} ended with status {r['status']}")
+            lat.append(r["latency_ms"])
+            k = r["report"]["iters_done"]
+            its.append(k)
+            stopped += r["report"]["stopped"]
+            vox_it += c[0] * c[0] * c[1] * k
+            log(f"[bench] serve {rate} req/s: request {len(lat)}/{n_req} done "
+                f"({c[0]}^2 x {c[1]}, {k} its, {r['latency_ms'] / 1e3:.1f} s)")
+        span = time.perf_counter() - t0
+        lat = np.array(lat)
+        runs.append({"rate_req_per_s": rate,
+                     "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                     "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                     "mean_ms": round(float(lat.mean()), 2),
+                     "throughput_req_per_s": round(n_req / span, 4),
+                     "voxel_updates_per_s": round(vox_it / span, 1),
+                     "iterations_mean": round(float(np.mean(its)), 1),
+                     "met_1e-4": stopped, "span_s": round(span, 2)})
     srv.close()
     del inputs
     torch.cuda.empty_cache()
-    lat = np.array(lat)
-    return {"form": "plain MUFFIN, FP32 + bf16 DCT, to relative change 1e-4 or 2000 iterations",
-            "requests": n_req, "rate_req_per_s": rate, "slots": 8,
-            "sizes": "n in {64,128,256,512}, L in {8,16,32,64}, uniform",
-            "p50_ms": round(float(np.percentile(lat, 50)), 2),
-            "p99_ms": round(float(np.percentile(lat, 99)), 2),
-            "mean_ms": round(float(lat.mean()), 2),
-            "throughput_req_per_s": round(n_req / span, 3),
-            "voxel_updates_per_s": round(vox_it / span, 1),
-            "iterations_mean": round(float(np.mean(its)), 1), "stopped_by_rule": stopped,
-            "span_s": round(span, 2)}
+    out = {"form": "plain MUFFIN, FP32 + bf16 DCT, to relative change 1e-4 or 2000 iterations",
+           "requests": n_req, "slots": slots,
+           "sizes": "n in {64,128,256,512,1024}, L in {8,16,32,64,128,256}, uniform "
+                    "(seeded draw); the 1024-pixel classes use the first L bands of the "
+                    "1024^2 x 256 cube",
+           "drawn": sorted({f"{n}x{L}" for n, L in picks}),
+           "voxels_mean": round(float(np.mean([n * n * L for n, L in picks])), 1)}
+    out.update(runs[0])
+    if len(runs) > 1:
+        out["sweep"] = runs
+    return out
 
 
 def _errors(torch, x, ref):
@@ -447,51 +570,65 @@ def _errors(torch, x, ref):
                                                      torch.linalg.vector_norm(ref))}
 
 
-def accuracy_form(mm, torch, synth, prob_c2, iters_plain=20, iters_adapt=40):
+def accuracy_form(mm, torch, synth, prob_c2, plain_iters=(20, 500), adapt_iters=(40, 500),
+                  eta=(5e-3, 1e-3)):
     """Errors of the reduced-precision forms against the FP64 GPU path (the
     path the parity tests pin to the FP64 oracle) from the same inputs and a
-    fixed step tau: plain MUFFIN at 1024^2 x 256 after `iters_plain`
-    iterations, ADA-PT at 256^2 x 64 after `iters_adapt` iterations (theta
-    updated every 10)."""
+    fixed step tau, after short and long runs: plain MUFFIN at 1024^2 x 256
+    (iterations `plain_iters`), ADA-PT at 256^2 x 64 with theta updated every
+    10 iterations by steps `eta` (iterations `adapt_iters`; theta moves well
+    away from its start, so its error is that of the whole SUGAR path).
+    Each form runs once to the last count; the sky is copied at the others."""
     forms = [("f32", mm.F32), ("bf16", mm.F32_BF16DCT)]
 
-    def solve(prob, mode, sure, iters, tau):
+    def run(prob, mode, sure, counts, tau):
         dt = torch.float64 if mode == mm.F64 else torch.float32
         cfg = mm.default_config(prob.n, prob.L, mode=mode, sure=1 if sure else 0,
                                 delta_period=10, eps_fd=0.01 * prob.sigma_w,
-                                sigma_w=prob.sigma_w, eta_mu=1e-6, eta_gamma=1e-6,
+                                sigma_w=prob.sigma_w, eta_mu=eta[0], eta_gamma=eta[1],
                                 tau=tau, pi_iters=50, pi_tol=1e-6)
         h = mm.Muffin(cfg)
         dev = lambda a: torch.from_numpy(a).to("cuda:0", dt)
         h.set_problem(dev(prob.dirty), dev(prob.psf), None, None,
                       dev(prob.delta) if sure else None)
-        rep = h.run(iters)
-        x = h.sky().double()
+        out, done = {}, 0
+        for k in counts:
+            rep = h.run(k - done)
+            done = k
+            out[k] = (h.sky().double(), rep)
         h.close()
         torch.cuda.empty_cache()
-        return x, rep
+        return out
 
-    out = {}
-    _, rep0 = solve(prob_c2, mm.F64, False, 0, 0.0)   # tau of the FP64 set-up
+    res = {}
+    rep0 = run(prob_c2, mm.F64, False, (0,), 0.0)[0][1]   # tau of the FP64 set-up
     tau = rep0["tau"]
-    x64, _ = solve(prob_c2, mm.F64, False, iters_plain, tau)
-    out[f"plain_1024x256_{iters_plain}_iters"] = {
-        k: _errors(torch, solve(prob_c2, m, False, iters_plain, tau)[0], x64) for k, m in forms}
-    del x64
+    ref = run(prob_c2, mm.F64, False, plain_iters, tau)
+    for name, m in forms:
+        got = run(prob_c2, m, False, plain_iters, tau)
+        for k in plain_iters:
+            res.setdefault(f"plain_1024x256_{k}_iters", {})[name] = _errors(torch, got[k][0],
+                                                                             ref[k][0])
+        del got
+    del ref
     torch.cuda.empty_cache()
     p1 = synth.make_config("c1", seed=0, device="cuda:0")
-    _, r0 = solve(p1, mm.F64, True, 0, 0.0)
-    x64, r64 = solve(p1, mm.F64, True, iters_adapt, r0["tau"])
-    ad = {}
-    for k, m in forms:
-        x, r = solve(p1, m, True, iters_adapt, r0["tau"])
-        e = _errors(torch, x, x64)
-        e["mu_rel"] = abs(r["mu"] - r64["mu"]) / abs(r64["mu"])
-        e["gamma_rel"] = abs(r["gamma"] - r64["gamma"]) / abs(r64["gamma"])
-        ad[k] = e
-    out[f"adapt_256x64_{iters_adapt}_iters"] = ad
-    out["reference"] = "FP64 GPU path, same inputs, same fixed tau"
-    return out
+    r0 = run(p1, mm.F64, True, (0,), 0.0)[0][1]
+    ref = run(p1, mm.F64, True, adapt_iters, r0["tau"])
+    for name, m in forms:
+        got = run(p1, m, True, adapt_iters, r0["tau"])
+        for k in adapt_iters:
+            e = _errors(torch, got[k][0], ref[k][0])
+            r, r64 = got[k][1], ref[k][1]
+            e["mu"], e["gamma"] = r["mu"], r["gamma"]
+            e["mu_rel"] = abs(r["mu"] - r64["mu"]) / abs(r64["mu"]) if r64["mu"] else abs(r["mu"])
+            e["gamma_rel"] = abs(r["gamma"] - r64["gamma"]) / abs(r64["gamma"])
+            res.setdefault(f"adapt_256x64_{k}_iters", {})[name] = e
+    for k in adapt_iters:
+        res[f"adapt_256x64_{k}_iters"]["fp64_theta"] = [ref[k][1]["mu"], ref[k][1]["gamma"]]
+    res["reference"] = ("FP64 GPU path, same inputs, same fixed tau; ADA-PT with eta = "
+                        f"({eta[0]}, {eta[1]}), eps = 0.01 sigma_w, theta(0) = (1, 1)")
+    return res
 
 
 def run_form(mm, torch, prob, mode, sure, steps, warmup, Delta=10, dictionary=0):
@@ -581,6 +718,22 @@ def main():
             tf = fl / (ms / calls * 1e-3) / 1e12
             entry["mfma_TFLOPs"] = round(tf, 1)
             entry["mfma_util"] = round(tf / peak, 4)
+        if k == "fft_chain":
+            # the chain's algorithmic bytes (116 V per voxel for 6 sets) and
+            # its nominal flops over its measured time
+            sets = 6
+            nbytes = LN * es * sum(STAGE_TRAFFIC[f"fft_{p}"][0] for p in
+                                   ("row1", "col1", "row2", "col2", "row3"))
+            avg = ms / calls
+            entry["algorithmic_GB"] = round(nbytes / 1e9, 2)
+            entry["GBps"] = round(nbytes / (avg * 1e-3) / 1e9, 1)
+            entry["frac_hbm"] = round(nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+            tfl = fft_chain_flops(n, L, sets) / (avg * 1e-3) / 1e12
+            entry["nominal_TFLOPs"] = round(tfl, 1)
+            vec_peak = FP32_VECTOR_UNPACKED if mode != mm.F64 else MFMA_F64_PEAK
+            entry["frac_vector_peak"] = round(tfl / vec_peak, 4)
+        if k in STAGE_TRAFFIC:
+            entry["frac_hbm"] = round(entry["GBps"] / HBM_PEAK_GBS, 4)
         stages[k] = entry
     dom = max((k for k in stages if k in STAGE_TRAFFIC), key=lambda k: tm[k][0])
     vals, mbytes = STAGE_TRAFFIC[dom]
@@ -589,7 +742,10 @@ def main():
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     kernel_of = {"synthesis_l1": "dwt_sy level 1", "analysis_l1_primal": "dwt_an level 1",
                  "analysis_l1_deriv": "dwt_an level 1", "dct_primal": "dct kernel",
-                 "dct_deriv": "dct kernel", "primal_step": "primal_kernel"}
+                 "dct_deriv": "dct kernel", "primal_step": "primal_kernel",
+                 "fft_row1": "row_pass_pruned", "fft_col1": "col_pass_rt",
+                 "fft_row2": "row_pass_pruned", "fft_col2": "col_pass_rt",
+                 "fft_row3": "row_pass_pruned"}
     kname = f"{kernel_of[dom]} ({dom})"
     traffic = measured_traffic(kname) if args.workload == "c2" and mode == mm.F32_BF16DCT else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -693,15 +849,19 @@ def main():
     serve = None
     if not args.no_serve:
         try:
-            serve = serve_form(mm, torch, synth, args.serve_requests, args.serve_rate)
+            rates = [args.serve_rate] + [float(r) for r in args.serve_sweep.split(",") if r]
+            serve = serve_form(mm, torch, synth, prob, args.serve_requests, rates)
             log(f"[bench] serve: p50 {serve['p50_ms']} ms, p99 {serve['p99_ms']} ms, "
                 f"{serve['throughput_req_per_s']} req/s")
         except Exception as e:  # report, do not hide
             serve = {"error": str(e)}
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(prob)
-        log(f"[bench] cpu oracle: {cpu['value']:.3e} it/s")
+        try:
+            cpu = cpu_baseline(prob, synth)
+            log(f"[bench] cpu oracle: {cpu['value']:.3e} it/s on {cpu['cores']} cores")
+        except Exception as e:  # report, do not hide
+            cpu = {"error": str(e)}
 
     out = {
         "metric": METRIC,

@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 namespace muffin {
@@ -93,6 +94,59 @@ __device__ __forceinline__ int out_row(int lk, int r) {
   return sizeof(T) == 8 ? lk + 4 * r : 4 * lk + r;
 }
 
+// One product of a block: acc[i][g] += A(tile wave + kDctWaves i) B(g),
+// summed over the nks k-steps of 4 bands, B from the LDS tile Z ([band][pixel]).
+// The A fragments (one value per lane, from the fragment-ordered table in
+// global memory) are fetched kDctAhead k-steps before their use, in two
+// alternating register buffers, so the table's L2 latency overlaps the
+// MFMAs of the previous k-steps instead of stalling every k-step.
+constexpr int kDctAhead = 4;
+template <typename T, int G, typename Acc>
+__device__ __forceinline__ void dct_product(Acc (&acc)[kDctKtPerWave][G], const T* __restrict__ A,
+                                            const T* Z, int nkt, int nks, int wave, int lane,
+                                            int lr, int lk) {
+  constexpr int PIX = 16 * G;
+  auto fetch = [&](T (&av)[kDctAhead][kDctKtPerWave], int ks0) {
+#pragma unroll
+    for (int d = 0; d < kDctAhead; ++d) {
+      const int ks = min(ks0 + d, nks - 1);  // clamped: the tail re-reads the last step
+#pragma unroll
+      for (int i = 0; i < kDctKtPerWave; ++i) {
+        const int kt = min(wave + kDctWaves * i, nkt - 1);
+        av[d][i] = A[((size_t)kt * nks + ks) * 64 + lane];
+      }
+    }
+  };
+  auto use = [&](const T (&av)[kDctAhead][kDctKtPerWave], int ks0) {
+#pragma unroll
+    for (int d = 0; d < kDctAhead; ++d) {
+      const int ks = ks0 + d;
+      if (ks < nks) {
+        T b[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) b[g] = Z[(4 * ks + lk) * PIX + 16 * g + lr];
+#pragma unroll
+        for (int i = 0; i < kDctKtPerWave; ++i) {
+          if (wave + kDctWaves * i < nkt) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) acc[i][g] = mfma16(av[d][i], b[g], acc[i][g]);
+          }
+        }
+      }
+    }
+  };
+  T a0[kDctAhead][kDctKtPerWave], a1[kDctAhead][kDctKtPerWave];
+  fetch(a0, 0);
+  for (int ks0 = 0; ks0 < nks; ks0 += 2 * kDctAhead) {
+    fetch(a1, ks0 + kDctAhead);
+    use(a0, ks0);
+    if (ks0 + kDctAhead < nks) {
+      fetch(a0, ks0 + 2 * kDctAhead);
+      use(a1, ks0 + kDctAhead);
+    }
+  }
+}
+
 // Block = kDctWaves waves x (16 * G) pixels.  Wave w owns the output row
 // tiles w, w + kDctWaves, ... for every pixel group, so each A fragment
 // (read coalesced from the fragment-ordered matrix) feeds G MFMAs.  Eight
@@ -125,7 +179,7 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_kernel(DctArgs<T> a) {
     const T* za = a.z_a[set];
     const bool has_b = !a.pure && a.z_b[set] != nullptr;
     const T* zb = has_b ? a.z_b[set] : za;
-    constexpr int U = 8;
+    constexpr int U = 16;
     constexpr int NT = 64 * kDctWaves;
     const int total = Lp * PIX;
     for (int t0 = threadIdx.x; t0 < total; t0 += U * NT) {
@@ -155,6 +209,21 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_kernel(DctArgs<T> a) {
   }
   lds_barrier();
 
+  // the pixels' weights alpha_n and (derivative role) the mask word are
+  // fetched before the first product, which hides their latency.  Masks
+  // 1[|v~| <= 1] are bits of one 32-bit word per thread and block (bit
+  // 4 (G i + g) + r), written by the primal role, read by the derivative
+  // role (same launch shape).  Lanes past the last pixel read a clamped
+  // weight and store nothing.
+  T al[G];
+  uint32_t* __restrict__ MW =
+      (!a.pure && a.mask[set]) ? reinterpret_cast<uint32_t*>(a.mask[set]) +
+                                     (size_t)blockIdx.x * blockDim.x + threadIdx.x
+                               : nullptr;
+  uint32_t mw = (a.role != ROLE_PRIMAL && MW) ? *MW : 0u;
+#pragma unroll
+  for (int g = 0; g < G; ++g) al[g] = a.alpha ? T(a.alpha[min(pix0 + 16 * g + lr, N - 1)]) : T(1);
+
   acc_t acc[kDctKtPerWave][G];
 #pragma unroll
   for (int i = 0; i < kDctKtPerWave; ++i)
@@ -162,21 +231,7 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_kernel(DctArgs<T> a) {
     for (int g = 0; g < G; ++g) acc[i][g] = acc_t{0, 0, 0, 0};
 
   // ---- product 1: C Z (pure == 2: C^T Z) ----
-  const T* A1 = a.pure == 2 ? a.Cf2 : a.Cf1;
-  for (int ks = 0; ks < nks; ++ks) {
-    T b[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) b[g] = Z[(4 * ks + lk) * PIX + 16 * g + lr];
-#pragma unroll
-    for (int i = 0; i < kDctKtPerWave; ++i) {
-      const int kt = wave + kDctWaves * i;
-      if (kt < nkt) {
-        const T av = A1[((size_t)kt * nks + ks) * 64 + lane];
-#pragma unroll
-        for (int g = 0; g < G; ++g) acc[i][g] = mfma16(av, b[g], acc[i][g]);
-      }
-    }
-  }
+  dct_product<T, G>(acc, a.pure == 2 ? a.Cf2 : a.Cf1, Z, nkt, nks, wave, lane, lr, lk);
 
   if (a.pure) {
     T* out = a.V[set];
@@ -205,21 +260,7 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_kernel(DctArgs<T> a) {
   const T d2 = T(dct_coef(a.d2_sel[set], dp));
   T* __restrict__ V = a.V[set];
   const T* __restrict__ Vb = a.Vb[set];
-  // masks 1[|v~| <= 1] as bits of one 32-bit word per thread and block (bit
-  // 4 (G i + g) + r), written by the primal role, read by the derivative
-  // role (same launch shape)
-  uint32_t* __restrict__ MW =
-      a.mask[set] ? reinterpret_cast<uint32_t*>(a.mask[set]) + (size_t)blockIdx.x * blockDim.x +
-                        threadIdx.x
-                  : nullptr;
   const bool has_vb = Vb != nullptr;
-  uint32_t mw = (a.role != ROLE_PRIMAL && MW) ? *MW : 0u;
-  T al[G];
-#pragma unroll
-  for (int g = 0; g < G; ++g) {
-    const int pix = pix0 + 16 * g + lr;
-    al[g] = a.alpha ? (pix < N ? T(a.alpha[pix]) : T(0)) : T(1);
-  }
 #pragma unroll
   for (int i = 0; i < kDctKtPerWave; ++i) {
     const int kt = wave + kDctWaves * i;
@@ -273,20 +314,7 @@ __global__ void __launch_bounds__(64 * kDctWaves, 2) dct_kernel(DctArgs<T> a) {
   for (int i = 0; i < kDctKtPerWave; ++i)
 #pragma unroll
     for (int g = 0; g < G; ++g) acc[i][g] = acc_t{0, 0, 0, 0};
-  for (int ks = 0; ks < nks; ++ks) {
-    T b[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) b[g] = Z[(4 * ks + lk) * PIX + 16 * g + lr];
-#pragma unroll
-    for (int i = 0; i < kDctKtPerWave; ++i) {
-      const int lt = wave + kDctWaves * i;
-      if (lt < nkt) {
-        const T av = a.Cf2[((size_t)lt * nks + ks) * 64 + lane];
-#pragma unroll
-        for (int g = 0; g < G; ++g) acc[i][g] = mfma16(av, b[g], acc[i][g]);
-      }
-    }
-  }
+  dct_product<T, G>(acc, a.Cf2, Z, nkt, nks, wave, lane, lr, lk);
   T* To = a.Tout[set];
 #pragma unroll
   for (int i = 0; i < kDctKtPerWave; ++i) {
@@ -353,7 +381,60 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
-__global__ void __launch_bounds__(64 * kBfWaves, 2) dct_bf16_kernel(DctBfArgs a) {
+// One product of a block in the split form: acc[i][g] += A(tile wave +
+// kBfWaves i) B(g) over the nks k-steps of 32 bands, each as the three bf16
+// products hi hi + lo hi + hi lo.  The A fragments (hi and lo, one 16-byte
+// vector each per lane) are fetched one k-step ahead of their use, in two
+// alternating register buffers, so their L2 latency overlaps the MFMAs of
+// the step before; B comes from the LDS tile ([pixel][band], row pitch LpS).
+__device__ __forceinline__ void bf_product(flt4 (&acc)[kBfKtPerWave][kBfG],
+                                           const bf16x8* __restrict__ Ah,
+                                           const bf16x8* __restrict__ Al, const __bf16* Zh,
+                                           const __bf16* Zl, int LpS, int nkt, int nks, int wave,
+                                           int lane, int lr, int lk) {
+  auto fetch = [&](bf16x8 (&h)[kBfKtPerWave], bf16x8 (&l)[kBfKtPerWave], int ks) {
+    ks = min(ks, nks - 1);  // clamped: the tail re-reads the last step
+#pragma unroll
+    for (int i = 0; i < kBfKtPerWave; ++i) {
+      const int kt = min(wave + kBfWaves * i, nkt - 1);
+      const size_t f = ((size_t)kt * nks + ks) * 64 + lane;
+      h[i] = Ah[f];
+      l[i] = Al[f];
+    }
+  };
+  auto use = [&](const bf16x8 (&h)[kBfKtPerWave], const bf16x8 (&l)[kBfKtPerWave], int ks) {
+    bf16x8 bh[kBfG], bl[kBfG];
+#pragma unroll
+    for (int g = 0; g < kBfG; ++g) {
+      const int o = (16 * g + lr) * LpS + 32 * ks + 8 * lk;
+      bh[g] = *reinterpret_cast<const bf16x8*>(Zh + o);
+      bl[g] = *reinterpret_cast<const bf16x8*>(Zl + o);
+    }
+#pragma unroll
+    for (int i = 0; i < kBfKtPerWave; ++i) {
+      if (wave + kBfWaves * i < nkt) {
+#pragma unroll
+        for (int g = 0; g < kBfG; ++g) {
+          acc[i][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h[i], bh[g], acc[i][g], 0, 0, 0);
+          acc[i][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l[i], bh[g], acc[i][g], 0, 0, 0);
+          acc[i][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h[i], bl[g], acc[i][g], 0, 0, 0);
+        }
+      }
+    }
+  };
+  bf16x8 h0[kBfKtPerWave], l0[kBfKtPerWave], h1[kBfKtPerWave], l1[kBfKtPerWave];
+  fetch(h0, l0, 0);
+  for (int ks = 0; ks < nks; ks += 2) {
+    fetch(h1, l1, ks + 1);
+    use(h0, l0, ks);
+    if (ks + 1 < nks) {
+      fetch(h0, l0, ks + 2);
+      use(h1, l1, ks + 1);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(64 * kBfWaves, 4) dct_bf16_kernel(DctBfArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int L = a.L, Lp = a.Lp, N = a.N;
   const int LpS = Lp + 8;  // padded band stride of the [pixel][band] tile
@@ -371,70 +452,80 @@ __global__ void __launch_bounds__(64 * kBfWaves, 2) dct_bf16_kernel(DctBfArgs a)
     const float* za = a.z_a[set];
     const bool has_b = !a.pure && a.z_b[set] != nullptr;
     const float* zb = has_b ? a.z_b[set] : za;
-    // each thread converts 8 consecutive bands of one pixel and stores them
-    // as one 16-byte hi and one 16-byte lo vector; the operands of the 8
-    // bands are loaded unconditionally (clamped indices) before any is used
+    // each thread converts 8 consecutive bands of one pixel per item and
+    // stores them as one 16-byte hi and one 16-byte lo vector; the operands
+    // of all the thread's items (at most kBfItems) are loaded unconditionally
+    // (clamped indices) before any is used, so the whole tile is in flight
+    // at once
+    constexpr int NT = 64 * kBfWaves;
+    constexpr int kBfItems = (256 / 8) * kBfPix / NT;
     const int total = (Lp / 8) * kBfPix;
-    for (int t = threadIdx.x; t < total; t += 64 * kBfWaves) {
-      const int lg = t / kBfPix, j = t - lg * kBfPix;
-      const int pix = pix0 + j;
-      const int pc = min(pix, N - 1);
-      float va[8], vb[8];
+    auto stage = [&](auto two) {
+      constexpr bool B = decltype(two)::value;
+      float va[kBfItems][8], vb[B ? kBfItems : 1][8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const size_t idx = (size_t)min(8 * lg + e, L - 1) * N + pc;
-        va[e] = za[idx];
-        if (has_b) vb[e] = zb[idx];
-      }
-      bf16x8 vh, vl;
+      for (int it = 0; it < kBfItems; ++it) {
+        const int t = min((int)threadIdx.x + it * NT, total - 1);
+        const int lg = t / kBfPix, j = t - lg * kBfPix;
+        const int pc = min(pix0 + j, N - 1);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int l = 8 * lg + e;
-        float z = 0.f;
-        if (l < L && pix < N) {
-          z = float(c1) * va[e];
-          if (has_b) z += float(c2) * vb[e];
+        for (int e = 0; e < 8; ++e) {
+          const size_t idx = (size_t)min(8 * lg + e, L - 1) * N + pc;
+          va[it][e] = za[idx];
+          if constexpr (B) vb[it][e] = zb[idx];
         }
-        __bf16 h, lo;
-        split_bf16(z, h, lo);
-        vh[e] = h;
-        vl[e] = lo;
       }
-      *reinterpret_cast<bf16x8*>(Zh + j * LpS + 8 * lg) = vh;
-      *reinterpret_cast<bf16x8*>(Zl + j * LpS + 8 * lg) = vl;
-    }
+#pragma unroll
+      for (int it = 0; it < kBfItems; ++it) {
+        const int t = threadIdx.x + it * NT;
+        if (t < total) {
+          const int lg = t / kBfPix, j = t - lg * kBfPix;
+          const int pix = pix0 + j;
+          bf16x8 vh, vl;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int l = 8 * lg + e;
+            float z = 0.f;
+            if (l < L && pix < N) {
+              z = float(c1) * va[it][e];
+              if constexpr (B) z += float(c2) * vb[it][e];
+            }
+            __bf16 h, lo;
+            split_bf16(z, h, lo);
+            vh[e] = h;
+            vl[e] = lo;
+          }
+          *reinterpret_cast<bf16x8*>(Zh + j * LpS + 8 * lg) = vh;
+          *reinterpret_cast<bf16x8*>(Zl + j * LpS + 8 * lg) = vl;
+        }
+      }
+    };
+    if (has_b)
+      stage(std::true_type{});
+    else
+      stage(std::false_type{});
   }
   lds_barrier();
+  // the pixels' weights alpha_n and (derivative role) the mask word are
+  // fetched before the first product, which hides their latency; mask bits
+  // as in dct_kernel: bit 4 (kBfG i + g) + r of the thread's word.  Lanes
+  // past the last pixel read a clamped weight and store nothing.
+  float al[kBfG];
+  uint32_t* __restrict__ MW =
+      (!a.pure && a.mask[set]) ? reinterpret_cast<uint32_t*>(a.mask[set]) +
+                                     (size_t)blockIdx.x * blockDim.x + threadIdx.x
+                               : nullptr;
+  uint32_t mw = (a.role != ROLE_PRIMAL && MW) ? *MW : 0u;
+#pragma unroll
+  for (int g = 0; g < kBfG; ++g)
+    al[g] = a.alpha ? float(a.alpha[min(pix0 + 16 * g + lr, N - 1)]) : 1.f;
   flt4 acc[kBfKtPerWave][kBfG];
 #pragma unroll
   for (int i = 0; i < kBfKtPerWave; ++i)
 #pragma unroll
     for (int g = 0; g < kBfG; ++g) acc[i][g] = flt4{0, 0, 0, 0};
-  const bf16x8* Ah = a.pure == 2 ? a.Ah2 : a.Ah1;
-  const bf16x8* Al = a.pure == 2 ? a.Al2 : a.Al1;
-  for (int ks = 0; ks < nks; ++ks) {
-    bf16x8 bh[kBfG], bl[kBfG];
-#pragma unroll
-    for (int g = 0; g < kBfG; ++g) {
-      const int o = (16 * g + lr) * LpS + 32 * ks + 8 * lk;
-      bh[g] = *reinterpret_cast<const bf16x8*>(Zh + o);
-      bl[g] = *reinterpret_cast<const bf16x8*>(Zl + o);
-    }
-#pragma unroll
-    for (int i = 0; i < kBfKtPerWave; ++i) {
-      const int kt = wave + kBfWaves * i;
-      if (kt < nkt) {
-        const size_t f = ((size_t)kt * nks + ks) * 64 + lane;
-        const bf16x8 ah = Ah[f], al = Al[f];
-#pragma unroll
-        for (int g = 0; g < kBfG; ++g) {
-          acc[i][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[g], acc[i][g], 0, 0, 0);
-          acc[i][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[g], acc[i][g], 0, 0, 0);
-          acc[i][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[g], acc[i][g], 0, 0, 0);
-        }
-      }
-    }
-  }
+  bf_product(acc, a.pure == 2 ? a.Ah2 : a.Ah1, a.pure == 2 ? a.Al2 : a.Al1, Zh, Zl, LpS, nkt, nks,
+             wave, lane, lr, lk);
   if (a.pure) {
     float* out = a.V[set];
 #pragma unroll
@@ -460,36 +551,42 @@ __global__ void __launch_bounds__(64 * kBfWaves, 2) dct_bf16_kernel(DctBfArgs a)
   const float d2 = float(dct_coef(a.d2_sel[set], dp));
   float* __restrict__ V = a.V[set];
   const float* __restrict__ Vb = a.Vb[set];
-  // mask bits as in dct_kernel: bit 4 (kBfG i + g) + r of the thread's word
-  uint32_t* __restrict__ MW =
-      a.mask[set] ? reinterpret_cast<uint32_t*>(a.mask[set]) + (size_t)blockIdx.x * blockDim.x +
-                        threadIdx.x
-                  : nullptr;
   const bool has_vb = Vb != nullptr;
-  uint32_t mw = (a.role != ROLE_PRIMAL && MW) ? *MW : 0u;
-  float al[kBfG];
+  // phase 1: the operands of both of the wave's k-tiles in flight at once
+  // (clamped, unconditional loads; values outside the cube are not used);
+  // the second term v_b of the adjoint's input, when there is one, is
+  // fetched per k-tile (one tile ahead) to stay within 128 registers
+  float vold[kBfKtPerWave][kBfG][4], vbv[kBfG][4];
+  auto load_vb = [&](int i) {
+    const int kt = min(wave + kBfWaves * i, nkt - 1);
 #pragma unroll
-  for (int g = 0; g < kBfG; ++g) {
-    const int pix = pix0 + 16 * g + lr;
-    al[g] = a.alpha ? (pix < N ? float(a.alpha[pix]) : 0.f) : 1.f;
+    for (int g = 0; g < kBfG; ++g) {
+      const int pix = min(pix0 + 16 * g + lr, N - 1);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = min(kt * 16 + 4 * lk + r, L - 1);
+        vbv[g][r] = Vb[(size_t)k * N + pix];
+      }
+    }
+  };
+#pragma unroll
+  for (int i = 0; i < kBfKtPerWave; ++i) {
+    const int kt = min(wave + kBfWaves * i, nkt - 1);
+#pragma unroll
+    for (int g = 0; g < kBfG; ++g) {
+      const int pix = min(pix0 + 16 * g + lr, N - 1);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = min(kt * 16 + 4 * lk + r, L - 1);
+        vold[i][g][r] = V[(size_t)k * N + pix];
+      }
+    }
   }
 #pragma unroll
   for (int i = 0; i < kBfKtPerWave; ++i) {
     const int kt = wave + kBfWaves * i;
+    if (has_vb) load_vb(i);
     if (kt < nkt) {
-      // phase 1: every operand of this k-tile in flight at once
-      float vold[kBfG][4], vbv[kBfG][4];
-#pragma unroll
-      for (int g = 0; g < kBfG; ++g) {
-        const int pix = min(pix0 + 16 * g + lr, N - 1);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int k = min(kt * 16 + 4 * lk + r, L - 1);
-          const size_t idx = (size_t)k * N + pix;
-          vold[g][r] = V[idx];
-          if (has_vb) vbv[g][r] = Vb[idx];
-        }
-      }
 #pragma unroll
       for (int g = 0; g < kBfG; ++g) {
         const int pix = pix0 + 16 * g + lr;
@@ -500,7 +597,7 @@ __global__ void __launch_bounds__(64 * kBfWaves, 2) dct_bf16_kernel(DctBfArgs a)
           float bv = 0.f;
           if (k < L && pix < N) {
             const size_t idx = (size_t)k * N + pix;
-            const float vt = vold[g][r] + sg * al[g] * acc[i][g][r];
+            const float vt = vold[i][g][r] + sg * al[g] * acc[i][g][r];
             float vn;
             const uint32_t bit = 1u << (4 * (kBfG * i + g) + r);
             if (a.role == ROLE_PRIMAL) {
@@ -530,29 +627,7 @@ __global__ void __launch_bounds__(64 * kBfWaves, 2) dct_bf16_kernel(DctBfArgs a)
   for (int i = 0; i < kBfKtPerWave; ++i)
 #pragma unroll
     for (int g = 0; g < kBfG; ++g) acc[i][g] = flt4{0, 0, 0, 0};
-  for (int ks = 0; ks < nks; ++ks) {
-    bf16x8 bh[kBfG], bl[kBfG];
-#pragma unroll
-    for (int g = 0; g < kBfG; ++g) {
-      const int o = (16 * g + lr) * LpS + 32 * ks + 8 * lk;
-      bh[g] = *reinterpret_cast<const bf16x8*>(Zh + o);
-      bl[g] = *reinterpret_cast<const bf16x8*>(Zl + o);
-    }
-#pragma unroll
-    for (int i = 0; i < kBfKtPerWave; ++i) {
-      const int lt = wave + kBfWaves * i;
-      if (lt < nkt) {
-        const size_t f = ((size_t)lt * nks + ks) * 64 + lane;
-        const bf16x8 ah = a.Ah2[f], al2 = a.Al2[f];
-#pragma unroll
-        for (int g = 0; g < kBfG; ++g) {
-          acc[i][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[g], acc[i][g], 0, 0, 0);
-          acc[i][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al2, bh[g], acc[i][g], 0, 0, 0);
-          acc[i][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[g], acc[i][g], 0, 0, 0);
-        }
-      }
-    }
-  }
+  bf_product(acc, a.Ah2, a.Al2, Zh, Zl, LpS, nkt, nks, wave, lane, lr, lk);
   float* To = a.Tout[set];
 #pragma unroll
   for (int i = 0; i < kBfKtPerWave; ++i) {

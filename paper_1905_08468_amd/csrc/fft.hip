@@ -997,6 +997,12 @@ struct Sched {
   static_assert(NMID == 1 ? D2 == DL : D2 + radix_log_c(LOGNF - D2) == DL, "three or four stages");
 };
 
+// Row passes: bit 0 (first pass) / bit 1 (passes reading spectra) load the
+// next state set's input while the current set is transformed.
+#ifndef MUFFIN_ROW_PREFETCH
+#define MUFFIN_ROW_PREFETCH 3
+#endif
+
 // ---- row passes with pruned end stages (n = 2^LOGN at compile time) ----
 // IN_REAL: the first stage is computed from the loaded image pairs (the
 // padded upper half of every row is zero), with no staging of the input in
@@ -1086,9 +1092,15 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass_pruned(RowArgs<T> a
       for (int r = 0; r < R0; ++r) buf[b * stride + sw<T>(j * R0 + r)] = v[q][r];
     }
   };
-  for (int set = 0; set < a.nsets; ++set) {
+  // The input of the next state set is loaded into registers while the
+  // current set is transformed (its loads stay in flight through the LDS
+  // stages), so each block keeps HBM busy between its sets.
+  constexpr int PQ = IN == IN_REAL ? 1 : EMAX / NT;
+  static_assert(IN == IN_REAL || EMAX % NT == 0, "whole input elements per thread");
+  cplx<T> vin[IN == IN_REAL ? Q0 : 1][R0];  // IN_REAL: the first stage's loaded pairs
+  cplx<T> pin[PQ];                          // IN_SPEC: the set's spectrum elements
+  auto load_set = [&](int set) {
     if constexpr (IN == IN_REAL) {
-      cplx<T> v[Q0][R0];
 #pragma unroll
       for (int q = 0; q < Q0; ++q) {
         const int t = threadIdx.x + q * NT;
@@ -1096,24 +1108,28 @@ __global__ void __launch_bounds__(NT, 2 * NT / 256) row_pass_pruned(RowArgs<T> a
         const T* row = a.in[set] + ((size_t)band * N + i0 + b) * N;
 #pragma unroll
         for (int r = 0; r < R0 / 2; ++r)
-          v[q][r] = *reinterpret_cast<const cplx<T>*>(row + 2 * (j + r * NB0));
+          vin[q][r] = *reinterpret_cast<const cplx<T>*>(row + 2 * (j + r * NB0));
       }
-      first_store(v);
+    } else {
+#pragma unroll
+      for (int u = 0; u < PQ; ++u)
+        pin[u] = row_input<T, RB, NT, IN>(a, set, band, i0, threadIdx.x + u * NT, N, LOGN);
+    }
+  };
+  constexpr bool AHEAD = (MUFFIN_ROW_PREFETCH >> (IN == IN_REAL ? 0 : 1)) & 1;
+  if (AHEAD) load_set(0);
+  for (int set = 0; set < a.nsets; ++set) {
+    if (!AHEAD) load_set(set);
+    if constexpr (IN == IN_REAL) {
+      first_store(vin);
+      if (AHEAD && set + 1 < a.nsets) load_set(set + 1);
       lds_barrier();
       fwd_rest();
     } else {
-      constexpr int U = 4;
-      for (int t0 = threadIdx.x; t0 < EMAX; t0 += U * NT) {
-        cplx<T> v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-          v[u] = row_input<T, RB, NT, IN>(a, set, band, i0, min(t0 + u * NT, EMAX - 1), N, LOGN);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int t = t0 + u * NT;
-          if (t < EMAX) buf[row_slot<T, RB, IN>(t, N, LOGN, stride)] = v[u];
-        }
-      }
+      for (int u = 0; u < PQ; ++u)
+        buf[row_slot<T, RB, IN>(threadIdx.x + u * NT, N, LOGN, stride)] = pin[u];
+      if (AHEAD && set + 1 < a.nsets) load_set(set + 1);
       lds_barrier();
       herm_pre<T, RB, NT>(buf, stride, a.tw, N);
       lds_barrier();
@@ -1569,6 +1585,9 @@ int fft_psf_spectrum(FftPlan<T>& p, const T* psf, cplx<T>* tmp, hipStream_t s) {
 template <typename T>
 int fft_chain(const FftPlan<T>& p, const ChainIO<T>& io, int op, hipStream_t s) {
   const int ns = io.nsets;
+  auto mark = [&](int pass) {
+    if (io.mark) io.mark(io.mark_ctx, pass);
+  };
   RowArgs<T> a{};
   a.tw = p.tw;
   a.twr = p.twr;
@@ -1581,8 +1600,10 @@ int fft_chain(const FftPlan<T>& p, const ChainIO<T>& io, int op, hipStream_t s) 
     a.in[i] = io.in[i];
     a.out_spec[i] = io.specA[i];
   }
+  mark(0);
   int rc = launch_row<T, IN_REAL, OUT_SPEC>(a, ns, s);
   if (rc) return rc;
+  mark(1);
   const cplx<T>* cin[kMaxSets];
   cplx<T>* cout[kMaxSets];
   for (int i = 0; i < ns; ++i) {
@@ -1600,12 +1621,14 @@ int fft_chain(const FftPlan<T>& p, const ChainIO<T>& io, int op, hipStream_t s) 
     }
     b.y = io.y;
     b.partials = io.res_partials;
+    mark(2);
     rc = launch_row<T, IN_SPEC, OUT_SPEC>(b, ns, s);
     if (rc) return rc;
     for (int i = 0; i < ns; ++i) {
       cin[i] = io.specA[i];
       cout[i] = io.specB[i];
     }
+    mark(3);
     rc = launch_col<T>(p, cin, cout, ns, 1, s);
     if (rc) return rc;
   }
@@ -1614,7 +1637,11 @@ int fft_chain(const FftPlan<T>& p, const ChainIO<T>& io, int op, hipStream_t s) 
     c.in_spec[i] = io.specB[i];
     c.out[i] = io.out[i];
   }
-  return launch_row<T, IN_SPEC, OUT_REAL>(c, ns, s);
+  mark(4);
+  rc = launch_row<T, IN_SPEC, OUT_REAL>(c, ns, s);
+  if (rc) return rc;
+  mark(5);
+  return 0;
 }
 
 template int fft_make_plan<double>(FftPlan<double>&, int, int, hipStream_t, Region*);

@@ -97,6 +97,11 @@ struct ChainIO {
   const T* y;                 // optional: residual ||H in[0] - y||^2
   double* res_partials;       // per-block partial sums, or null
   int nsets;
+  // optional: called on the host before each pass (p = 0 row, 1 column,
+  // 2 middle row, 3 second column, 4 last row) and after the last (p = 5),
+  // for per-pass device timing
+  void (*mark)(void* ctx, int p);
+  void* mark_ctx;
 };
 
 template <typename T>

@@ -57,13 +57,19 @@ enum Stage {
   ST_DCT_PRIMAL,       // spectral DCT update, primal sets (one launch)
   ST_DCT_DERIV,        // spectral DCT update, derivative sets (one launch)
   ST_WINDOW,           // SURE/SUGAR reductions, theta update, resets
+  ST_FFT_R1,           // the five launches of ST_FFT: first row pass,
+  ST_FFT_C1,           //   first column pass,
+  ST_FFT_R2,           //   middle row pass,
+  ST_FFT_C2,           //   second column pass,
+  ST_FFT_R3,           //   last row pass (ST_FFT is their sum)
   ST_COUNT
 };
 
 const char* const kStageNames[ST_COUNT] = {
     "fft_chain", "synthesis_deep", "synthesis_l1",
     "primal_step",      "analysis_l1_primal", "analysis_deep_primal", "analysis_l1_deriv",
-    "analysis_deep_deriv", "dct_primal", "dct_deriv", "window_update"};
+    "analysis_deep_deriv", "dct_primal", "dct_deriv", "window_update",
+    "fft_row1", "fft_col1", "fft_row2", "fft_col2", "fft_row3"};
 
 struct Timer {
   bool on = false;
@@ -90,6 +96,17 @@ struct Timer {
     if (!on) return;
     hipEvent_t e = get();
     if (e) (void)hipEventRecord(e, s);
+  }
+  // the FFT chain's pass boundaries (ChainIO::mark): pass p ends the
+  // previous pass's interval and starts its own
+  struct PassMark {
+    Timer* t;
+    hipStream_t s;
+  };
+  static void pass_mark(void* ctx, int p) {
+    auto* m = static_cast<PassMark*>(ctx);
+    if (p > 0) m->t->end(m->s);
+    if (p < 5) m->t->begin(ST_FFT_R1 + p, m->s);
   }
   int collect(hipStream_t s) {
     if (used == 0) return 0;
@@ -422,8 +439,12 @@ struct Impl final : ImplBase {
 
   // -- operator helpers ------------------------------------------------
   int chain(const T* const* in, T* const* out, const int* sets, int ns, int op,
-            const T* y = nullptr, double* res = nullptr) {
+            const T* y = nullptr, double* res = nullptr, Timer::PassMark* pm = nullptr) {
     ChainIO<T> io{};
+    if (pm) {
+      io.mark = &Timer::pass_mark;
+      io.mark_ctx = pm;
+    }
     for (int i = 0; i < ns; ++i) {
       io.in[i] = in[i];
       io.out[i] = out[i];
@@ -669,9 +690,9 @@ struct Impl final : ImplBase {
         in[s] = X[s];
         out[s] = G[s];
       }
-      tm.begin(ST_FFT, st);
-      RC(chain(in, out, sets, nsets, gop()));
-      tm.end(st);
+      // timed per pass (the chain's total is their sum)
+      Timer::PassMark pm{&tm, st};
+      RC(chain(in, out, sets, nsets, gop(), nullptr, nullptr, tm.on ? &pm : nullptr));
     }
     // 2. synthesis
     {
@@ -1735,9 +1756,18 @@ int muffin_get_timing(muffin_handle* h, double* ms, int64_t* calls, int32_t max_
   if (!h) return MUFFIN_E_INVAL;
   Timer& t = h->impl->timer();
   RC(t.collect(h->impl->stream()));
+  double total[ST_COUNT];
+  long long ncalls[ST_COUNT];
+  for (int i = 0; i < ST_COUNT; ++i) {
+    total[i] = t.ms[i];
+    ncalls[i] = t.calls[i];
+  }
+  // the chain's time is the sum of its passes (timed one by one)
+  for (int i = ST_FFT_R1; i <= ST_FFT_R3; ++i) total[ST_FFT] += t.ms[i];
+  ncalls[ST_FFT] = std::max(ncalls[ST_FFT], ncalls[ST_FFT_R1]);
   for (int i = 0; i < ST_COUNT && i < max_stages; ++i) {
-    if (ms) ms[i] = t.ms[i];
-    if (calls) calls[i] = t.calls[i];
+    if (ms) ms[i] = total[i];
+    if (calls) calls[i] = ncalls[i];
   }
   return ST_COUNT;
 }
